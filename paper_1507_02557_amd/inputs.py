@@ -1,0 +1,282 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module holds no arithmetic of the discontinuous Galerkin method itself:
+it builds vertex-mapped hybrid meshes (vertex coordinates plus element vertex
+lists), draws the seeded vertex jitter, and evaluates closed-form initial and
+exact fields at caller-supplied points.
+
+Mesh construction ("four-slab" cube meshes)
+-------------------------------------------
+The unit cube is cut into n^3 cubes of side h = 1/n.  The x-layers of cubes
+are grouped into four slabs; slab k covers layers
+[round(k n / 4), round((k+1) n / 4)).  By default the slabs are, in x order:
+
+* ``hex``    -- every cube is one hexahedron;
+* ``wedge``  -- every cube is cut by the vertical plane through its
+  (x0,y0)-(x1,y1) edge diagonal into two wedges (triangles in z = const
+  planes, extruded along z); this is the cube subdivision into wedges used
+  for the paper's single-type wedge meshes (Section 4.1);
+* ``pyrtet`` -- every cube is cut into six pyramids with apex at the cube
+  centre; the -x pyramid is kept, and so is the +x pyramid when the next
+  cube in +x is also of this kind (so that x-interior faces stay conforming
+  quadrilaterals); every other pyramid is cut into two tetrahedra along the
+  diagonal of its base through the face's (min,min)-(max,max) corners;
+* ``tet``    -- every cube is cut into the six Kuhn tetrahedra along its
+  (x0,y0,z0)-(x1,y1,z1) diagonal.
+
+``pyr6`` (all six pyramids kept) is also available for single-type pyramid
+meshes, the subdivision of hexahedra into pyramids used in Section 4.1.
+
+All choices above are conforming: every interior face is shared by exactly
+two elements with the same vertex set.
+
+Element-local vertex orders are those of the reference elements:
+
+* hex   (r,s,t) in [-1,1]^3: 0(-1,-1,-1) 1(1,-1,-1) 2(1,1,-1) 3(-1,1,-1)
+  4(-1,-1,1) 5(1,-1,1) 6(1,1,1) 7(-1,1,1)
+* wedge (triangle in (r,t), extruded in s): 0(-1,-1,-1) 1(1,-1,-1)
+  2(-1,-1,1) 3(-1,1,-1) 4(1,1,-1) 5(-1,1,1)
+* pyramid (base t = -1, apex over (r,s) = (-1,-1)): 0(-1,-1,-1) 1(1,-1,-1)
+  2(1,1,-1) 3(-1,1,-1) 4(-1,-1,1)
+* tet: 0(-1,-1,-1) 1(1,-1,-1) 2(-1,1,-1) 3(-1,-1,1)
+
+The generator orders each element's vertices so that the vertex map has a
+positive Jacobian.
+
+Jitter: every vertex strictly inside the unit cube (cube centres included) is
+moved by an independent uniform displacement in [-j h, j h]^3 drawn from
+``numpy.random.default_rng(seed)`` for all vertices in id order (boundary
+vertices' draws are discarded).  Grid vertex (i,j,k) has id
+i + (n+1)(j + (n+1)k); cube centres follow in order of creation.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HEX, WEDGE, PYR, TET = 0, 1, 2, 3
+NVERT = {HEX: 8, WEDGE: 6, PYR: 5, TET: 4}
+TYPE_NAMES = {HEX: "hex", WEDGE: "wedge", PYR: "pyr", TET: "tet"}
+
+BC_FREE_SURFACE = 0  # p = 0 on the boundary (the paper's boundary condition)
+BC_RIGID_WALL = 1    # u . n = 0 on the boundary
+
+DEFAULT_SLABS = ("hex", "wedge", "pyrtet", "tet")
+
+
+@dataclass
+class Mesh:
+    """A vertex-mapped hybrid mesh: vertices plus element vertex lists."""
+
+    xyz: np.ndarray            # (n_vert, 3) float64
+    etype: np.ndarray          # (n_elem,) int8, HEX/WEDGE/PYR/TET
+    everts: np.ndarray         # (n_elem, 8) int64, local vertex order, -1 padded
+    kappa: np.ndarray          # (n_elem,) float64 bulk modulus
+    rho: np.ndarray            # (n_elem,) float64 density
+    n: int = 0
+    info: dict = field(default_factory=dict)
+
+    @property
+    def n_elem(self) -> int:
+        return int(self.etype.shape[0])
+
+    def counts(self) -> dict:
+        return {TYPE_NAMES[t]: int(np.sum(self.etype == t)) for t in (HEX, WEDGE, PYR, TET)}
+
+
+def _slab_of_layer(n: int, layer: int, nslab: int) -> int:
+    for k in range(nslab):
+        lo = int(round(k * n / nslab))
+        hi = int(round((k + 1) * n / nslab))
+        if lo <= layer < hi:
+            return k
+    return nslab - 1
+
+
+def _det3(a, b, c) -> float:
+    return float(np.dot(a, np.cross(b, c)))
+
+
+def _orient(kind: int, v: list, P: np.ndarray) -> list:
+    """Reorder vertices so that the reference-to-physical map has J > 0."""
+    p = [P[i] for i in v]
+    if kind == TET:
+        if _det3(p[1] - p[0], p[2] - p[0], p[3] - p[0]) < 0:
+            v = [v[0], v[1], v[3], v[2]]
+    elif kind == PYR:
+        if _det3(p[1] - p[0], p[3] - p[0], p[4] - p[0]) < 0:
+            v = [v[0], v[3], v[2], v[1], v[4]]
+    elif kind == WEDGE:
+        # r along v0->v1, s along v0->v3, t along v0->v2
+        if _det3(p[1] - p[0], p[3] - p[0], p[2] - p[0]) < 0:
+            v = [v[0], v[2], v[1], v[3], v[5], v[4]]
+    elif kind == HEX:
+        if _det3(p[1] - p[0], p[3] - p[0], p[4] - p[0]) < 0:
+            raise ValueError("hex construction produced a negative Jacobian")
+    return v
+
+
+def four_slab_mesh(n: int, seed: int = 0, jitter: float = 0.1,
+                   slabs=DEFAULT_SLABS, kappa: float = 1.0, rho: float = 1.0) -> Mesh:
+    """Build the four-slab hybrid cube mesh described in the module docstring.
+
+    ``slabs`` lists the kind of each x-slab ("hex", "wedge", "pyrtet", "tet",
+    "pyr6"); its length sets the number of slabs (a one-element list gives a
+    single-type mesh).
+    """
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    slabs = tuple(slabs)
+    nslab = len(slabs)
+    h = 1.0 / n
+    n1 = n + 1
+
+    def gid(i, j, k):
+        return i + n1 * (j + n1 * k)
+
+    # id order i fastest: flat index = i + n1*(j + n1*k)
+    pts = np.empty((n1 ** 3, 3))
+    kk, jj, ii = np.meshgrid(np.arange(n1), np.arange(n1), np.arange(n1), indexing="ij")
+    pts[:, 0] = (ii.ravel()) * h
+    pts[:, 1] = (jj.ravel()) * h
+    pts[:, 2] = (kk.ravel()) * h
+    centres: list = []
+
+    def centre_id(i, j, k):
+        centres.append(((i + 0.5) * h, (j + 0.5) * h, (k + 0.5) * h))
+        return n1 ** 3 + len(centres) - 1
+
+    elems: list = []  # (type, [vertex ids])
+
+    def kind_of(i):
+        if i < 0 or i >= n:
+            return None
+        return slabs[_slab_of_layer(n, i, nslab)]
+
+    for k in range(n):
+        for j in range(n):
+            for i in range(n):
+                kind = kind_of(i)
+                c = [[[gid(i + a, j + b, k + d) for d in (0, 1)] for b in (0, 1)] for a in (0, 1)]
+                # c[a][b][d]: corner at (x_i+a, y_j+b, z_k+d)
+                if kind == "hex":
+                    v = [c[0][0][0], c[1][0][0], c[1][1][0], c[0][1][0],
+                         c[0][0][1], c[1][0][1], c[1][1][1], c[0][1][1]]
+                    elems.append((HEX, None, v))
+                elif kind == "wedge":
+                    for tri in (((0, 0), (1, 0), (1, 1)), ((0, 0), (1, 1), (0, 1))):
+                        bot = [c[a][b][0] for a, b in tri]
+                        top = [c[a][b][1] for a, b in tri]
+                        v = [bot[0], bot[1], bot[2], top[0], top[1], top[2]]
+                        # reference order: 0,1,2 on s=-1 (triangle r,t), 3,4,5 on s=+1
+                        elems.append((WEDGE, None, v))
+                elif kind == "tet":
+                    lo = np.array([i, j, k])
+                    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+                        p = lo.copy()
+                        v = [gid(*p)]
+                        for ax in perm:
+                            p[ax] += 1
+                            v.append(gid(*p))
+                        elems.append((TET, None, v))
+                elif kind in ("pyrtet", "pyr6"):
+                    cid = centre_id(i, j, k)
+                    # six faces: (axis, side)
+                    for ax in range(3):
+                        for side in (0, 1):
+                            # face corners in cyclic order in the two tangential axes
+                            t1, t2 = [a for a in range(3) if a != ax]
+                            cyc = []
+                            for (u, w) in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                                idx = [0, 0, 0]
+                                idx[ax] = side
+                                idx[t1] = u
+                                idx[t2] = w
+                                cyc.append(c[idx[0]][idx[1]][idx[2]])
+                            keep = False
+                            if kind == "pyr6":
+                                keep = True
+                            elif ax == 0 and side == 0:
+                                keep = True
+                            elif ax == 0 and side == 1 and kind_of(i + 1) == "pyrtet":
+                                keep = True
+                            if keep:
+                                elems.append((PYR, None, cyc + [cid]))
+                            else:
+                                # split along the (min,min)-(max,max) diagonal of the face
+                                a0, a1, a2, a3 = cyc  # (0,0),(1,0),(1,1),(0,1)
+                                elems.append((TET, None, [a0, a1, a2, cid]))
+                                elems.append((TET, None, [a0, a2, a3, cid]))
+                else:
+                    raise ValueError(f"unknown slab kind {kind!r}")
+
+    allpts = np.concatenate([pts, np.array(centres, dtype=np.float64).reshape(-1, 3)], axis=0)
+    n_vert = allpts.shape[0]
+    # orientation decisions use the unjittered positions
+    fixed = [(t, _orient(t, v, allpts)) for (t, _, v) in elems]
+
+    etype = np.array([t for t, _ in fixed], dtype=np.int8)
+    everts = -np.ones((len(fixed), 8), dtype=np.int64)
+    for e, (t, v) in enumerate(fixed):
+        everts[e, : len(v)] = v
+
+    rng = np.random.default_rng(seed)
+    disp = rng.uniform(-jitter * h, jitter * h, size=(n_vert, 3))
+    tol = 1e-12
+    on_bnd = np.any((allpts < tol) | (allpts > 1.0 - tol), axis=1)
+    disp[on_bnd] = 0.0
+    xyz = allpts + disp
+
+    ne = etype.shape[0]
+    return Mesh(xyz=xyz, etype=etype, everts=everts,
+                kappa=np.full(ne, float(kappa)), rho=np.full(ne, float(rho)), n=n,
+                info={"seed": seed, "jitter": jitter, "slabs": list(slabs)})
+
+
+# ---------------------------------------------------------------------------
+# Closed-form fields (kappa = rho = 1)
+# ---------------------------------------------------------------------------
+
+def standing_mode_rigid(x, y, z, t):
+    """Rigid-wall (u.n = 0) resonant mode of p_t + div u = 0, u_t + grad p = 0.
+
+    p = cos(pi x) cos(pi y) cos(pi z) cos(sqrt(3) pi t) and
+    u_x = sin(pi x) cos(pi y) cos(pi z) sin(sqrt(3) pi t) / sqrt(3), cyclic.
+    Returns (p, ux, uy, uz).
+    """
+    pi = np.pi
+    w = np.sqrt(3.0) * pi
+    cx, cy, cz = np.cos(pi * x), np.cos(pi * y), np.cos(pi * z)
+    sx, sy, sz = np.sin(pi * x), np.sin(pi * y), np.sin(pi * z)
+    st = np.sin(w * t) / np.sqrt(3.0)
+    return (cx * cy * cz * np.cos(w * t), sx * cy * cz * st, cx * sy * cz * st, cx * cy * sz * st)
+
+
+def standing_mode_free(x, y, z, t):
+    """Free-surface (p = 0) resonant cavity mode of Section 4.1.
+
+    p = sin(pi x) sin(pi y) sin(pi z) cos(sqrt(3) pi t) and
+    u_x = -cos(pi x) sin(pi y) sin(pi z) sin(sqrt(3) pi t) / sqrt(3), cyclic.
+    Returns (p, ux, uy, uz).
+    """
+    pi = np.pi
+    w = np.sqrt(3.0) * pi
+    cx, cy, cz = np.cos(pi * x), np.cos(pi * y), np.cos(pi * z)
+    sx, sy, sz = np.sin(pi * x), np.sin(pi * y), np.sin(pi * z)
+    st = -np.sin(w * t) / np.sqrt(3.0)
+    return (sx * sy * sz * np.cos(w * t), cx * sy * sz * st, sx * cy * sz * st, sx * sy * cz * st)
+
+
+def pulse_centre(seed: int) -> np.ndarray:
+    """Centre of the Gaussian pressure pulse, uniform in [0.2, 0.8]^3 from the seed."""
+    rng = np.random.default_rng(seed + 7919)
+    return rng.uniform(0.2, 0.8, size=3)
+
+
+def gaussian_pulse(x, y, z, centre, width: float = 0.05):
+    """p = exp(-|x - x0|^2 / (2 width^2)), u = 0.  Returns (p, ux, uy, uz)."""
+    r2 = (x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2
+    p = np.exp(-r2 / (2.0 * width * width))
+    zero = np.zeros_like(p)
+    return (p, zero, zero.copy(), zero.copy())
