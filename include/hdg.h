@@ -1,0 +1,165 @@
+/*
+ * hdg.h -- C ABI of the MI355X DG solver for the acoustic wave equation on
+ * vertex-mapped hybrid hexahedral / wedge / pyramidal / tetrahedral meshes.
+ *
+ * Method: Chan, Wang, Modave, Remacle, Warburton, "GPU-accelerated
+ * discontinuous Galerkin methods on hybrid meshes" (arXiv:1507.02557).
+ *   - PDE (Section 2.2): (1/kappa) p_t + div u = 0, rho u_t + grad p = 0 with
+ *     kappa, rho constant per element; upwind-penalty flux with
+ *     tau_p = 1/{rho c}, tau_u = {rho c}.
+ *   - Bases and element forms (Section 2.1, Table forms, GL formulation):
+ *     GL nodal hexahedra (strong), nodal tetrahedra (strong), LSC-DG modal
+ *     wedges (skew-symmetric), semi-nodal pyramids (skew-symmetric,
+ *     quadrature-free operators of Section 2.3.4).
+ *   - Stable local time steps from the computed trace constants (Section 3.4,
+ *     eq. dtK); multi-rate level binning (Section 2.4).
+ *
+ * Conventions
+ *   - Status codes: 0 = success, negative = error (HDG_E*).  No exception
+ *     crosses this interface.  hdg_last_error() returns a message for the
+ *     most recent failing call on a context.
+ *   - Element types: 0 hexahedron, 1 wedge, 2 pyramid, 3 tetrahedron.
+ *   - "host" arguments are read during the call and not retained; "device"
+ *     arguments are HIP device pointers owned by the caller, read or written
+ *     asynchronously on the context's stream (the call returns before the
+ *     copy completes).  The context owns all memory it allocates.
+ *   - Field layout (structure of arrays): for element type t with K_t elements
+ *     and Np(t) dofs per element, each field is a float array [K_t][Np(t)];
+ *     elements of a type are numbered in mesh order.
+ *   - Dof meaning per type: hex: values at the (N+1)^3 Gauss-Legendre nodes,
+ *     node i + (N+1)(j + (N+1)k); tet: values at the equispaced nodes
+ *     (i,j,k), i+j+k <= N, k outermost, i fastest; wedge: coefficients of the
+ *     orthonormal basis phi_{i,j,k} of Section 2.1.3 divided by sqrt(J),
+ *     index j*Ntri + tri(i,k) (tri: i outer, k inner); pyramid: coefficients
+ *     of the unit-norm semi-nodal basis of Section 2.1.4, index
+ *     off_k + j(k+1) + i.
+ */
+#ifndef HDG_H
+#define HDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HDG_OK 0
+#define HDG_EINVAL (-1)     /* bad argument (order, type, size, pointer)   */
+#define HDG_EMESH (-2)      /* invalid mesh: J <= 0, unmatched faces, ...  */
+#define HDG_ENOMEM (-3)     /* device allocation failed                    */
+#define HDG_EHIP (-4)       /* HIP runtime error                           */
+#define HDG_ENONFINITE (-5) /* non-finite value found in the state         */
+#define HDG_ESTATE (-6)     /* call not valid in the context's state       */
+
+#define HDG_HEX 0
+#define HDG_WEDGE 1
+#define HDG_PYR 2
+#define HDG_TET 3
+
+#define HDG_BC_FREE_SURFACE 0 /* p = 0 (Section 2.2)          */
+#define HDG_BC_RIGID_WALL 1   /* u . n = 0                     */
+
+#define HDG_PREC_FP32 0      /* operator arithmetic in FP32 */
+
+typedef struct hdg_ctx hdg_ctx;
+
+/* Mesh description (all host pointers, copied by hdg_create).
+ *   xyz       [3*n_vert]  vertex coordinates (x,y,z interleaved), float64
+ *   type      [n_elem]    element types (HDG_HEX..HDG_TET)
+ *   verts     [8*n_elem]  vertex ids per element in the reference vertex
+ *                         order of its type, unused entries -1:
+ *     hex   (r,s,t): (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1)
+ *                    (-1,-1,1) (1,-1,1) (1,1,1) (-1,1,1)
+ *     wedge (triangle in (r,t), extruded in s): (-1,-1,-1) (1,-1,-1)
+ *                    (-1,-1,1) (-1,1,-1) (1,1,-1) (-1,1,1)
+ *     pyramid: (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1) apex (-1,-1,1)
+ *     tet:     (-1,-1,-1) (1,-1,-1) (-1,1,-1) (-1,-1,1)
+ *   kappa,rho [n_elem]    bulk modulus and density (> 0)
+ *   bc                    boundary condition on every boundary face        */
+typedef struct hdg_mesh {
+  int64_t n_vert;
+  const double* xyz;
+  int64_t n_elem;
+  const int8_t* type;
+  const int64_t* verts;
+  const double* kappa;
+  const double* rho;
+  int32_t bc;
+} hdg_mesh;
+
+/* Create a solver context for order N (1 <= N <= 5) on mesh m (Section 2).
+ * Builds the reference operators in FP64 on the host, matches faces, and
+ * computes the geometric factors in FP64 on the device.  Work is enqueued on
+ * hip_stream (a hipStream_t, may be NULL for the null stream); the call
+ * synchronises that stream before returning.  precision: HDG_PREC_FP32.
+ * Errors: HDG_EINVAL (N out of range, bad type id, NULL pointer),
+ * HDG_EMESH (non-positive Jacobian, a face shared by more than two elements),
+ * HDG_ENOMEM, HDG_EHIP.  On error *out is NULL. */
+int hdg_create(hdg_ctx** out, const hdg_mesh* m, int N, int precision, void* hip_stream);
+
+/* Release the context and all device memory it owns.  NULL is accepted. */
+void hdg_destroy(hdg_ctx* ctx);
+
+/* Message for the last failing call on ctx (or for the last failed
+ * hdg_create in this thread if ctx is NULL). */
+const char* hdg_last_error(const hdg_ctx* ctx);
+
+/* Number of elements of type t, dofs per element, and sample points per
+ * element used by hdg_project (hex/tet: the nodes; wedge: the volume
+ * cubature; pyramid: the projection rule).  Any output may be NULL. */
+int hdg_type_info(const hdg_ctx* ctx, int t, int64_t* n_elem, int32_t* np, int32_t* n_sample);
+
+/* Local stable time steps (Section 3.4, eq. dtK):
+ *   dtau_K = C / (C_rhokappa^K C_T(N) C_J^K),
+ * C_rhokappa^K = max(tau_p,K kappa_K, tau_u,K / rho_K) (face maxima),
+ * C_J^K = max|J^s| max|1/J| (hex, pyramid, tet) or max|J^s/J| (LSC wedge)
+ * over cubature points, C_T(N) the computed trace constants of Appendix B.
+ * dt_out (host) receives dtau_K for every element in mesh order [n_elem];
+ * dt_min_out (host) the minimum.  Either may be NULL.  cfl = C > 0. */
+int hdg_dt(hdg_ctx* ctx, double cfl, double* dt_out, double* dt_min_out);
+
+/* Physical sample points (device, float64 [K_t][n_sample][3]) of type t. */
+int hdg_get_points(hdg_ctx* ctx, int t, double* xyz_dev);
+
+/* Set the state of type t from samples of the four fields at the points of
+ * hdg_get_points (device, float64, each [K_t][n_sample]): interpolation at
+ * nodes (hex, tet); L2 projection with the element's own mass (wedge:
+ * u_i = sum_q w_q sqrt(J_q) phi_i(q) f_q; pyramid:
+ * u_i = sum_q w_q J_q phi_i(q) f_q / J(a_i, b_j)). */
+int hdg_project(hdg_ctx* ctx, int t, const double* p, const double* ux, const double* uy,
+                const double* uz);
+
+/* Copy the state (which = 0) or the last right-hand side (which = 1) of type
+ * t into / out of caller device buffers, each float [K_t][Np]. */
+int hdg_set_state(hdg_ctx* ctx, int t, const float* p, const float* ux, const float* uy,
+                  const float* uz);
+int hdg_get_field(hdg_ctx* ctx, int which, int t, float* p, float* ux, float* uy, float* uz);
+
+/* Evaluate the semi-discrete right-hand side dU/dt = M^{-1} A U of the
+ * current state into the context's rhs buffers (read with hdg_get_field). */
+int hdg_rhs(hdg_ctx* ctx);
+
+/* Advance the state by n_steps single-rate LSERK4 steps of size dt (the
+ * Carpenter-Kennedy 5-stage, 4th-order, 2N-storage scheme): per stage
+ * res = a_s res + dt rhs(U); U = U + b_s res.  One fused kernel per element
+ * type and stage.  Asynchronous on the context's stream. */
+int hdg_step(hdg_ctx* ctx, double dt, int64_t n_steps);
+
+/* Energy E = 1/2 sum_K (p^T M p / kappa + rho u^T M u) of the current state,
+ * accumulated in FP64 on the device (synchronises the stream). */
+int hdg_energy(hdg_ctx* ctx, double* E);
+
+/* Kernel timing for benchmarking.  While enabled (on != 0), hdg_step and
+ * hdg_rhs bracket every stage-kernel launch with HIP events on the context's
+ * stream.  hdg_profile_read synchronises the stream and returns, per element
+ * type, the total kernel time in milliseconds (ms_out[4]) and the number of
+ * launches (count_out[4]) since the last reset; either may be NULL.
+ * Enabling or disabling resets the counters. */
+int hdg_profile(hdg_ctx* ctx, int on);
+int hdg_profile_read(hdg_ctx* ctx, double* ms_out, int64_t* count_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HDG_H */

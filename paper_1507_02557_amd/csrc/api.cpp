@@ -1,0 +1,717 @@
+// C ABI of the hybrid-mesh DG solver (declared in include/hdg.h).
+//
+// hdg_create does all set-up: FP64 reference operators on the host, face
+// matching and canonical orientations, upload, FP64 geometry on the device,
+// FP32 operator tables.  The hot path is hdg_step: per Runge-Kutta stage one
+// fused kernel per element type, traces double-buffered between stages.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/hdg.h"
+#include "kernels.hpp"
+#include "refel.hpp"
+
+using namespace hdg;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage RK.
+const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+
+struct TypeData {
+  int present = 0;
+  int64_t K = 0;
+  int Np = 0, nf = 0, nv = 0, nsample = 0, nvp = 0;
+  std::vector<int64_t> elems;  // global element ids in mesh order
+  int64_t slot0 = 0;
+  float* U = nullptr;
+  float* R = nullptr;
+  float* geo = nullptr;
+  float2* mat = nullptr;
+  float4* fgeo = nullptr;
+  float* isqJ = nullptr;
+  double* V = nullptr;         // [K][nv][3]
+  float* ops = nullptr;
+  int* iops = nullptr;
+  double* spts = nullptr;      // sample reference points [nsample][3]
+  double* sw = nullptr;        // sample weights (wedge, pyramid)
+  double* Phi = nullptr;       // basis at sample points (wedge, pyramid)
+  double* gpts = nullptr;      // pyramid geometry points [Np][3]
+  double* Mhat = nullptr;      // tet reference mass
+  std::vector<double> cJ, minJ, crk;
+};
+
+}  // namespace
+
+struct hdg_ctx {
+  int N = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  FaceTables ft;
+  HexRef hex;
+  TetRef tet;
+  WedgeRef wedge;
+  PyrRef pyr;
+  TypeData td[4];
+  int64_t n_elem = 0;
+  int64_t nslot = 0;
+  int* nbr = nullptr;
+  int8_t* ori = nullptr;
+  float2* tau = nullptr;
+  float4* trace[2] = {nullptr, nullptr};
+  int cur = 0;
+  bool traces_valid = false;
+  GeoTables* gtab = nullptr;
+  double* partial = nullptr;
+  int* flag = nullptr;
+  std::vector<void*> allocs;
+  bool prof = false;
+  std::vector<std::array<hipEvent_t, 2>> ev_pool;
+  std::vector<int> ev_type;
+  size_t ev_used = 0;
+};
+
+namespace {
+
+int fail(hdg_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                              \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(ctx, HDG_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+template <class T>
+int dalloc(hdg_ctx* c, T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc((void**)p, n * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    return fail(c, HDG_ENOMEM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  }
+  c->allocs.push_back((void*)*p);
+  return HDG_OK;
+}
+
+template <class T>
+int upload(hdg_ctx* c, T** p, const std::vector<T>& h) {
+  int rc = dalloc(c, p, h.size());
+  if (rc) return rc;
+  if (!h.empty()) {
+    HIPCHK(c, hipMemcpyAsync(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // h is pageable and may be released by the caller
+  }
+  return HDG_OK;
+}
+
+std::vector<float> to_f(const Vec& v) { return std::vector<float>(v.begin(), v.end()); }
+
+void append(std::vector<float>& dst, const Vec& v) {
+  for (double x : v) dst.push_back((float)x);
+}
+
+int build_tables(hdg_ctx* c, int t, std::vector<float>& ops, std::vector<int>& iops) {
+  const int N = c->N;
+  const FaceTables& ft = c->ft;
+  ops.clear();
+  iops.clear();
+  if (t == kHex) {
+    append(ops, c->hex.D1);
+    append(ops, c->hex.Lm);
+    append(ops, c->hex.Lp);
+    iops.insert(iops.end(), ft.quad_perm.begin(), ft.quad_perm.end());
+  } else if (t == kTet) {
+    const TetRef& T = c->tet;
+    append(ops, T.Dr);
+    append(ops, T.Ds);
+    append(ops, T.Dt);
+    append(ops, T.Minv);
+    append(ops, ft.Ican);
+    append(ops, ft.tri_w);
+    iops.insert(iops.end(), T.fnode.begin(), T.fnode.end());
+    iops.insert(iops.end(), ft.tri_perm.begin(), ft.tri_perm.end());
+    std::vector<int> nodeface(4 * T.Np, -1);
+    for (int f = 0; f < 4; ++f)
+      for (int m = 0; m < ft.Nfn; ++m) nodeface[f * T.Np + T.fnode[f * ft.Nfn + m]] = m;
+    iops.insert(iops.end(), nodeface.begin(), nodeface.end());
+  } else if (t == kPyr) {
+    const PyrRef& P = c->pyr;
+    append(ops, P.Dr);
+    append(ops, P.Ds);
+    append(ops, P.Dt);
+    append(ops, P.Fquad);
+    append(ops, P.Ftri);
+    append(ops, ft.Ican);
+    iops.insert(iops.end(), ft.quad_perm.begin(), ft.quad_perm.end());
+    iops.insert(iops.end(), ft.tri_perm.begin(), ft.tri_perm.end());
+  } else {
+    const WedgeRef& W = c->wedge;
+    append(ops, W.Pt);
+    append(ops, W.Ptr);
+    append(ops, W.Ptt);
+    append(ops, W.tri_w);
+    append(ops, W.P1);
+    append(ops, W.dP1);
+    Vec x1, w1;
+    gauss_jacobi(N + 1, 0.0, 0.0, x1, w1);
+    append(ops, w1);
+    append(ops, W.P1m);
+    append(ops, W.P1p);
+    append(ops, W.Ftri);
+    append(ops, W.Fedge);
+    append(ops, ft.Ican);
+    iops.insert(iops.end(), ft.quad_perm.begin(), ft.quad_perm.end());
+    iops.insert(iops.end(), ft.tri_perm.begin(), ft.tri_perm.end());
+  }
+  int nf = 0, ni = 0;
+  stage_table_sizes(t, N, &nf, &ni);
+  if ((int)ops.size() != nf || (int)iops.size() != ni)
+    return fail(c, HDG_EINVAL, "internal: operator table size mismatch for type " + std::to_string(t));
+  return HDG_OK;
+}
+
+int check_type(const hdg_ctx* c, int t) {
+  if (t < 0 || t > 3) return HDG_EINVAL;
+  return c->td[t].present ? HDG_OK : HDG_EINVAL;
+}
+
+int ensure_traces(hdg_ctx* c) {
+  if (c->traces_valid) return HDG_OK;
+  for (int t = 0; t < 4; ++t) {
+    TypeData& d = c->td[t];
+    if (!d.present) continue;
+    StageArgs a{};
+    a.K = d.K;
+    a.U = d.U;
+    a.R = d.R;
+    a.geo = d.geo;
+    a.mat = d.mat;
+    a.nbr = c->nbr;
+    a.ori = c->ori;
+    a.tau = c->tau;
+    a.fgeo = d.fgeo;
+    a.isqJ = d.isqJ;
+    a.tr_in = c->trace[c->cur];
+    a.tr_out = c->trace[c->cur];
+    a.slot0 = d.slot0;
+    a.ops = d.ops;
+    a.iops = d.iops;
+    a.mode = kModeTrace;
+    if (launch_stage(t, c->N, a, c->stream)) return fail(c, HDG_EINVAL, "no stage kernel for this order");
+  }
+  HIPCHK(c, hipGetLastError());
+  c->traces_valid = true;
+  return HDG_OK;
+}
+
+int prof_begin(hdg_ctx* c, int t, hipEvent_t* stop) {
+  *stop = nullptr;
+  if (!c->prof) return HDG_OK;
+  if (c->ev_used == c->ev_pool.size()) {
+    std::array<hipEvent_t, 2> p;
+    HIPCHK(c, hipEventCreate(&p[0]));
+    HIPCHK(c, hipEventCreate(&p[1]));
+    c->ev_pool.push_back(p);
+    c->ev_type.push_back(t);
+  }
+  c->ev_type[c->ev_used] = t;
+  HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used][0], c->stream));
+  *stop = c->ev_pool[c->ev_used][1];
+  c->ev_used++;
+  return HDG_OK;
+}
+
+int run_stage(hdg_ctx* c, int mode, float ra, float rb, float dt) {
+  for (int t = 0; t < 4; ++t) {
+    TypeData& d = c->td[t];
+    if (!d.present) continue;
+    StageArgs a{};
+    a.K = d.K;
+    a.U = d.U;
+    a.R = d.R;
+    a.geo = d.geo;
+    a.mat = d.mat;
+    a.nbr = c->nbr;
+    a.ori = c->ori;
+    a.tau = c->tau;
+    a.fgeo = d.fgeo;
+    a.isqJ = d.isqJ;
+    a.tr_in = c->trace[c->cur];
+    a.tr_out = c->trace[1 - c->cur];
+    a.slot0 = d.slot0;
+    a.ops = d.ops;
+    a.iops = d.iops;
+    a.a = ra;
+    a.b = rb;
+    a.dt = dt;
+    a.mode = mode;
+    hipEvent_t stop;
+    int rc = prof_begin(c, t, &stop);
+    if (rc) return rc;
+    if (launch_stage(t, c->N, a, c->stream)) return fail(c, HDG_EINVAL, "no stage kernel for this order");
+    if (stop) HIPCHK(c, hipEventRecord(stop, c->stream));
+  }
+  HIPCHK(c, hipGetLastError());
+  if (mode == kModeStage) c->cur = 1 - c->cur;
+  return HDG_OK;
+}
+
+int create_impl(hdg_ctx* c, const hdg_mesh* m, int N) {
+  c->N = N;
+  build_face_tables(N, c->ft);
+  const FaceTables& ft = c->ft;
+  const int64_t ne = m->n_elem;
+  c->n_elem = ne;
+  // ---- element lists per type, vertex checks
+  for (int64_t e = 0; e < ne; ++e) {
+    const int t = m->type[e];
+    if (t < 0 || t > 3) return fail(c, HDG_EINVAL, "element " + std::to_string(e) + " has bad type");
+    const int nv = elem_desc(t).nv;
+    for (int v = 0; v < nv; ++v) {
+      const int64_t id = m->verts[8 * e + v];
+      if (id < 0 || id >= m->n_vert) return fail(c, HDG_EINVAL, "element " + std::to_string(e) + " has a bad vertex id");
+    }
+    if (!(m->kappa[e] > 0.0) || !(m->rho[e] > 0.0))
+      return fail(c, HDG_EINVAL, "element " + std::to_string(e) + " has non-positive kappa or rho");
+    c->td[t].elems.push_back(e);
+  }
+  std::vector<int> etype_local(ne), eidx(ne);
+  int64_t slot = 0;
+  for (int t = 0; t < 4; ++t) {
+    TypeData& d = c->td[t];
+    d.K = (int64_t)d.elems.size();
+    d.present = d.K > 0;
+    const ElemDesc& E = elem_desc(t);
+    d.nv = E.nv;
+    d.nf = E.nf;
+    d.Np = np_of(t, N);
+    d.slot0 = slot;
+    slot += d.K * d.nf;
+    for (int64_t k = 0; k < d.K; ++k) {
+      etype_local[d.elems[k]] = t;
+      eidx[d.elems[k]] = (int)k;
+    }
+  }
+  c->nslot = slot;
+  if (c->nslot >= (int64_t)1 << 31) return fail(c, HDG_EINVAL, "mesh too large (face slots exceed int32)");
+  if (c->td[kHex].present) build_hex(N, c->hex);
+  if (c->td[kTet].present) build_tet(N, ft, c->tet);
+  if (c->td[kWedge].present) build_wedge(N, ft, c->wedge);
+  if (c->td[kPyr].present) build_pyr(N, ft, c->pyr);
+
+  // ---- face matching by sorted vertex ids, canonical orientation codes
+  const int64_t ns = c->nslot;
+  std::vector<std::array<int64_t, 4>> keys(ns);
+  std::vector<int8_t> ori(ns);
+  std::vector<int64_t> slot_elem(ns);
+  for (int t = 0; t < 4; ++t) {
+    TypeData& d = c->td[t];
+    const ElemDesc& E = elem_desc(t);
+    for (int64_t k = 0; k < d.K; ++k) {
+      const int64_t e = d.elems[k];
+      for (int f = 0; f < E.nf; ++f) {
+        const int64_t s = d.slot0 + k * E.nf + f;
+        int64_t g[4];
+        for (int v = 0; v < E.fnv[f]; ++v) g[v] = m->verts[8 * e + E.fv[f][v]];
+        ori[s] = (int8_t)face_orientation(E.fnv[f], g, nullptr);
+        std::array<int64_t, 4> key{-1, -1, -1, -1};
+        std::sort(g, g + E.fnv[f]);
+        for (int v = 0; v < E.fnv[f]; ++v) key[4 - E.fnv[f] + v] = g[v];
+        keys[s] = key;
+        slot_elem[s] = e;
+      }
+    }
+  }
+  std::vector<int64_t> order(ns);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return keys[x] < keys[y]; });
+  std::vector<int> nbr(ns, -1 - m->bc);
+  for (int64_t i = 0; i < ns;) {
+    int64_t j = i + 1;
+    while (j < ns && keys[order[j]] == keys[order[i]]) ++j;
+    if (j - i == 2) {
+      nbr[order[i]] = (int)order[i + 1];
+      nbr[order[i + 1]] = (int)order[i];
+    } else if (j - i > 2) {
+      return fail(c, HDG_EMESH, "a face is shared by more than two elements");
+    }
+    i = j;
+  }
+  // penalties: tau_p = 1 / {rho c}, tau_u = {rho c}; boundary uses own rho c
+  std::vector<float2> tau(ns);
+  std::vector<double> taup_max(ne, 0.0), tauu_max(ne, 0.0);
+  for (int64_t s = 0; s < ns; ++s) {
+    const int64_t e = slot_elem[s];
+    const double rc = std::sqrt(m->kappa[e] * m->rho[e]);
+    const double rn = nbr[s] >= 0 ? std::sqrt(m->kappa[slot_elem[nbr[s]]] * m->rho[slot_elem[nbr[s]]]) : rc;
+    const double avg = 0.5 * (rc + rn);
+    tau[s] = make_float2((float)(1.0 / avg), (float)avg);
+    taup_max[e] = std::max(taup_max[e], 1.0 / avg);
+    tauu_max[e] = std::max(tauu_max[e], avg);
+  }
+  int rc;
+  if ((rc = upload(c, &c->nbr, nbr))) return rc;
+  if ((rc = upload(c, &c->ori, ori))) return rc;
+  if ((rc = upload(c, &c->tau, tau))) return rc;
+
+  // ---- geometry tables
+  GeoTables G{};
+  for (int t = 0; t < 4; ++t) {
+    const ElemDesc& E = elem_desc(t);
+    G.nv[t] = E.nv;
+    G.nf[t] = E.nf;
+    for (int v = 0; v < E.nv; ++v)
+      for (int d = 0; d < 3; ++d) G.vref[t][v][d] = E.vref[v][d];
+    for (int f = 0; f < E.nf; ++f) {
+      G.fnv[t][f] = E.fnv[f];
+      G.farea[t][f] = E.farea[f];
+      for (int v = 0; v < 4; ++v) G.fv[t][f][v] = E.fv[f][v];
+      for (int d = 0; d < 3; ++d) G.nref[t][f][d] = E.nref[f][d];
+    }
+  }
+  G.Nfq = ft.Nfq;
+  if (ft.Nfq > 64) return fail(c, HDG_EINVAL, "order too high for the face tables");
+  for (int q = 0; q < ft.Nfq; ++q) {
+    G.tri_eta[q][0] = ft.tri_eta[2 * q];
+    G.tri_eta[q][1] = ft.tri_eta[2 * q + 1];
+    G.tri_w[q] = ft.tri_w[q];
+    G.quad_eta[q][0] = ft.quad_eta[2 * q];
+    G.quad_eta[q][1] = ft.quad_eta[2 * q + 1];
+    G.quad_w[q] = ft.quad_w[q];
+  }
+  for (int o = 0; o < 6; ++o) orientation_perm(3, o, G.tri_P[o]);
+  for (int o = 0; o < 8; ++o) orientation_perm(4, o, G.quad_P[o]);
+  if ((rc = dalloc(c, &c->gtab, 1))) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->gtab, &G, sizeof(G), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+
+  // ---- per-type data
+  for (int t = 0; t < 4; ++t) {
+    TypeData& d = c->td[t];
+    if (!d.present) continue;
+    const int64_t K = d.K;
+    std::vector<double> V(K * d.nv * 3);
+    std::vector<float2> mat(K);
+    for (int64_t k = 0; k < K; ++k) {
+      const int64_t e = d.elems[k];
+      for (int v = 0; v < d.nv; ++v)
+        for (int dd = 0; dd < 3; ++dd) V[(k * d.nv + v) * 3 + dd] = m->xyz[3 * m->verts[8 * e + v] + dd];
+      mat[k] = make_float2((float)m->kappa[e], (float)(1.0 / m->rho[e]));
+    }
+    if ((rc = upload(c, &d.V, V))) return rc;
+    if ((rc = upload(c, &d.mat, mat))) return rc;
+    std::vector<double> vpts, vw, spts, sw, Phi, gpts;
+    const int n1 = N + 1;
+    if (t == kHex) {
+      for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+          for (int i = 0; i < n1; ++i) {
+            vpts.insert(vpts.end(), {c->hex.x1[i], c->hex.x1[j], c->hex.x1[k]});
+            vw.push_back(c->hex.w1[i] * c->hex.w1[j] * c->hex.w1[k]);
+          }
+      spts = vpts;
+    } else if (t == kTet) {
+      vpts = {-0.5, -0.5, -0.5};
+      spts = c->tet.nodes;
+    } else if (t == kWedge) {
+      vpts = c->wedge.vol_pts;
+      spts = c->wedge.vol_pts;
+      sw = c->wedge.vol_w;
+      Phi = c->wedge.Phi;
+    } else {
+      vpts = c->pyr.geo_pts;
+      spts = c->pyr.proj_pts;
+      sw = c->pyr.proj_w;
+      Phi = c->pyr.Phi;
+      gpts = c->pyr.geo_pts;
+    }
+    d.nvp = (int)(vpts.size() / 3);
+    d.nsample = (int)(spts.size() / 3);
+    double* d_vpts = nullptr;
+    double* d_vw = nullptr;
+    if ((rc = upload(c, &d_vpts, vpts))) return rc;
+    if ((rc = upload(c, &d_vw, vw))) return rc;
+    if ((rc = upload(c, &d.spts, spts))) return rc;
+    if ((rc = upload(c, &d.sw, sw))) return rc;
+    if ((rc = upload(c, &d.Phi, Phi))) return rc;
+    if ((rc = upload(c, &d.gpts, gpts))) return rc;
+    if (t == kTet && (rc = upload(c, &d.Mhat, c->tet.Mhat))) return rc;
+    const int ngeo = (t == kTet) ? 12 : (t == kWedge ? 12 * d.nvp : 10 * d.nvp);
+    if ((rc = dalloc(c, &d.geo, (size_t)K * ngeo))) return rc;
+    const int fstride = (t == kTet) ? 1 : ft.Nfq;
+    if ((rc = dalloc(c, &d.fgeo, (size_t)K * d.nf * fstride))) return rc;
+    if (t == kWedge && (rc = dalloc(c, &d.isqJ, (size_t)K * d.nf * ft.Nfq))) return rc;
+    double *cJ = nullptr, *minJ = nullptr;
+    if ((rc = dalloc(c, &cJ, K))) return rc;
+    if ((rc = dalloc(c, &minJ, K))) return rc;
+    GeoArgs ga{};
+    ga.type = t;
+    ga.K = K;
+    ga.V = d.V;
+    ga.ori = c->ori + d.slot0;
+    ga.T = c->gtab;
+    ga.vpts = d_vpts;
+    ga.nvp = d.nvp;
+    ga.vw = d_vw;
+    ga.geo = d.geo;
+    ga.fgeo = d.fgeo;
+    ga.fstride = fstride;
+    ga.isqJ = d.isqJ;
+    ga.cJ = cJ;
+    ga.minJ = minJ;
+    launch_geometry(ga, c->stream);
+    HIPCHK(c, hipGetLastError());
+    d.cJ.resize(K);
+    d.minJ.resize(K);
+    HIPCHK(c, hipMemcpyAsync(d.cJ.data(), cJ, K * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d.minJ.data(), minJ, K * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    d.crk.resize(K);
+    for (int64_t k = 0; k < K; ++k) {
+      const int64_t e = d.elems[k];
+      d.crk[k] = std::max(taup_max[e] * m->kappa[e], tauu_max[e] / m->rho[e]);
+    }
+    std::vector<float> ops;
+    std::vector<int> iops;
+    if ((rc = build_tables(c, t, ops, iops))) return rc;
+    if ((rc = upload(c, &d.ops, ops))) return rc;
+    if ((rc = upload(c, &d.iops, iops))) return rc;
+    const size_t nstate = (size_t)4 * K * d.Np;
+    if ((rc = dalloc(c, &d.U, nstate))) return rc;
+    if ((rc = dalloc(c, &d.R, nstate))) return rc;
+    HIPCHK(c, hipMemsetAsync(d.U, 0, nstate * sizeof(float), c->stream));
+    HIPCHK(c, hipMemsetAsync(d.R, 0, nstate * sizeof(float), c->stream));
+  }
+  if ((rc = dalloc(c, &c->trace[0], (size_t)ns * ft.Nfq))) return rc;
+  if ((rc = dalloc(c, &c->trace[1], (size_t)ns * ft.Nfq))) return rc;
+  if ((rc = dalloc(c, &c->partial, (size_t)(ne / 256 + 8)))) return rc;
+  if ((rc = dalloc(c, &c->flag, 1))) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int t = 0; t < 4; ++t) {
+    const TypeData& d = c->td[t];
+    for (int64_t k = 0; k < d.K; ++k)
+      if (!(d.minJ[k] > 0.0))
+        return fail(c, HDG_EMESH, "element " + std::to_string(d.elems[k]) + " has a non-positive Jacobian");
+  }
+  return HDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hdg_create(hdg_ctx** out, const hdg_mesh* m, int N, int precision, void* hip_stream) {
+  if (!out) return fail(nullptr, HDG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!m || !m->xyz || !m->type || !m->verts || !m->kappa || !m->rho)
+    return fail(nullptr, HDG_EINVAL, "mesh or one of its arrays is NULL");
+  if (N < 1 || N > kMaxN) return fail(nullptr, HDG_EINVAL, "order N must be in [1, 5]");
+  if (precision != HDG_PREC_FP32) return fail(nullptr, HDG_EINVAL, "unsupported precision mode");
+  if (m->n_elem < 1 || m->n_vert < 1) return fail(nullptr, HDG_EINVAL, "empty mesh");
+  if (m->bc != HDG_BC_FREE_SURFACE && m->bc != HDG_BC_RIGID_WALL)
+    return fail(nullptr, HDG_EINVAL, "unknown boundary condition");
+  hdg_ctx* c = new hdg_ctx();
+  c->stream = (hipStream_t)hip_stream;
+  int rc;
+  try {
+    rc = create_impl(c, m, N);
+  } catch (const std::exception& ex) {
+    rc = fail(c, HDG_EINVAL, std::string("set-up failed: ") + ex.what());
+  }
+  if (rc != HDG_OK) {
+    g_create_error = c->err;
+    hdg_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return HDG_OK;
+}
+
+void hdg_destroy(hdg_ctx* c) {
+  if (!c) return;
+  if (!c->allocs.empty()) {
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+  }
+  for (auto& p : c->ev_pool) {
+    hipEventDestroy(p[0]);
+    hipEventDestroy(p[1]);
+  }
+  for (void* p : c->allocs) hipFree(p);
+  delete c;
+}
+
+const char* hdg_last_error(const hdg_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int hdg_type_info(const hdg_ctx* c, int t, int64_t* n_elem, int32_t* np, int32_t* n_sample) {
+  if (!c || t < 0 || t > 3) return HDG_EINVAL;
+  const TypeData& d = c->td[t];
+  if (n_elem) *n_elem = d.K;
+  if (np) *np = np_of(t, c->N);
+  if (n_sample) *n_sample = d.present ? d.nsample : 0;
+  return HDG_OK;
+}
+
+int hdg_dt(hdg_ctx* c, double cfl, double* dt_out, double* dt_min_out) {
+  if (!c) return HDG_EINVAL;
+  if (!(cfl > 0.0)) return fail(c, HDG_EINVAL, "CFL constant must be positive");
+  double mn = 1e300;
+  for (int t = 0; t < 4; ++t) {
+    const TypeData& d = c->td[t];
+    const double ct = trace_constant(t, c->N);
+    for (int64_t k = 0; k < d.K; ++k) {
+      const double dt = cfl / (d.crk[k] * ct * d.cJ[k]);
+      if (dt_out) dt_out[d.elems[k]] = dt;
+      mn = std::min(mn, dt);
+    }
+  }
+  if (dt_min_out) *dt_min_out = mn;
+  return HDG_OK;
+}
+
+int hdg_get_points(hdg_ctx* c, int t, double* xyz) {
+  if (!c) return HDG_EINVAL;
+  if (check_type(c, t) || !xyz) return fail(c, HDG_EINVAL, "bad type or NULL output");
+  const TypeData& d = c->td[t];
+  launch_points(t, d.K, d.nv, d.V, d.spts, d.nsample, xyz, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return HDG_OK;
+}
+
+int hdg_project(hdg_ctx* c, int t, const double* p, const double* ux, const double* uy, const double* uz) {
+  if (!c) return HDG_EINVAL;
+  if (check_type(c, t) || !p || !ux || !uy || !uz) return fail(c, HDG_EINVAL, "bad type or NULL input");
+  TypeData& d = c->td[t];
+  double* tmp = nullptr;
+  if (t == kWedge || t == kPyr) {
+    if (hipMalloc((void**)&tmp, (size_t)4 * d.K * d.nsample * sizeof(double)) != hipSuccess)
+      return fail(c, HDG_ENOMEM, "projection scratch allocation failed");
+  }
+  launch_project(t, d.K, d.nv, d.V, d.spts, d.sw, d.nsample, d.Np, d.Phi, d.gpts, p, ux, uy, uz, tmp, d.U,
+                 c->stream);
+  hipError_t e = hipGetLastError();
+  if (tmp) {
+    hipStreamSynchronize(c->stream);
+    hipFree(tmp);
+  }
+  if (e != hipSuccess) return fail(c, HDG_EHIP, std::string("projection: ") + hipGetErrorString(e));
+  c->traces_valid = false;
+  return HDG_OK;
+}
+
+int hdg_set_state(hdg_ctx* c, int t, const float* p, const float* ux, const float* uy, const float* uz) {
+  if (!c) return HDG_EINVAL;
+  if (check_type(c, t) || !p || !ux || !uy || !uz) return fail(c, HDG_EINVAL, "bad type or NULL input");
+  TypeData& d = c->td[t];
+  const size_t n = (size_t)d.K * d.Np;
+  const float* src[4] = {p, ux, uy, uz};
+  for (int f = 0; f < 4; ++f)
+    HIPCHK(c, hipMemcpyAsync(d.U + f * n, src[f], n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+  c->traces_valid = false;
+  return HDG_OK;
+}
+
+int hdg_get_field(hdg_ctx* c, int which, int t, float* p, float* ux, float* uy, float* uz) {
+  if (!c) return HDG_EINVAL;
+  if (check_type(c, t) || !p || !ux || !uy || !uz || (which != 0 && which != 1))
+    return fail(c, HDG_EINVAL, "bad type, selector or NULL output");
+  TypeData& d = c->td[t];
+  const size_t n = (size_t)d.K * d.Np;
+  const float* base = which == 0 ? d.U : d.R;
+  float* dst[4] = {p, ux, uy, uz};
+  for (int f = 0; f < 4; ++f)
+    HIPCHK(c, hipMemcpyAsync(dst[f], base + f * n, n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+  return HDG_OK;
+}
+
+int hdg_rhs(hdg_ctx* c) {
+  if (!c) return HDG_EINVAL;
+  int rc = ensure_traces(c);
+  if (rc) return rc;
+  return run_stage(c, kModeRhs, 0.f, 0.f, 1.f);
+}
+
+int hdg_step(hdg_ctx* c, double dt, int64_t n_steps) {
+  if (!c) return HDG_EINVAL;
+  if (!(dt > 0.0) || n_steps < 0) return fail(c, HDG_EINVAL, "dt must be positive and n_steps >= 0");
+  int rc = ensure_traces(c);
+  if (rc) return rc;
+  for (int64_t n = 0; n < n_steps; ++n)
+    for (int s = 0; s < 5; ++s)
+      if ((rc = run_stage(c, kModeStage, (float)kRkA[s], (float)kRkB[s], (float)dt))) return rc;
+  return HDG_OK;
+}
+
+int hdg_energy(hdg_ctx* c, double* E) {
+  if (!c || !E) return HDG_EINVAL;
+  double total = 0.0;
+  std::vector<double> part;
+  for (int t = 0; t < 4; ++t) {
+    TypeData& d = c->td[t];
+    if (!d.present) continue;
+    EnergyArgs a{};
+    a.type = t;
+    a.K = d.K;
+    a.Np = d.Np;
+    a.U = d.U;
+    a.geo = d.geo;
+    a.mat = d.mat;
+    a.Mhat = d.Mhat;
+    a.partial = c->partial;
+    const int nb = launch_energy(a, c->stream);
+    HIPCHK(c, hipGetLastError());
+    part.resize(nb);
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (double v : part) total += v;
+  }
+  *E = total;
+  return std::isfinite(total) ? HDG_OK : fail(c, HDG_ENONFINITE, "energy is not finite");
+}
+
+int hdg_profile(hdg_ctx* c, int on) {
+  if (!c) return HDG_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->prof = on != 0;
+  c->ev_used = 0;
+  return HDG_OK;
+}
+
+int hdg_profile_read(hdg_ctx* c, double* ms_out, int64_t* count_out) {
+  if (!c) return HDG_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double ms[4] = {0, 0, 0, 0};
+  int64_t cnt[4] = {0, 0, 0, 0};
+  for (size_t i = 0; i < c->ev_used; ++i) {
+    float v = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&v, c->ev_pool[i][0], c->ev_pool[i][1]));
+    ms[c->ev_type[i]] += v;
+    cnt[c->ev_type[i]] += 1;
+  }
+  for (int t = 0; t < 4; ++t) {
+    if (ms_out) ms_out[t] = ms[t];
+    if (count_out) count_out[t] = cnt[t];
+  }
+  c->ev_used = 0;
+  return HDG_OK;
+}
+
+}  // extern "C"

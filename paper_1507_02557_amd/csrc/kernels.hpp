@@ -1,0 +1,56 @@
+// Host-visible launch interface of the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "geom.hpp"
+#include "stage_common.hpp"
+
+namespace hdg {
+
+struct GeoArgs {
+  int type;
+  int64_t K;
+  const double* V;        // [K][nv][3]
+  const int8_t* ori;      // [K*nf] orientation codes of this type's slots
+  const GeoTables* T;     // device copy
+  const double* vpts;     // volume reference points [nvp][3]
+  int nvp;
+  const double* vw;       // hex node weights [nvp]
+  float* geo;             // volume factors (layout per type)
+  float4* fgeo;           // face factors
+  int fstride;            // 1 (planar tet faces) or Nfq
+  float* isqJ;            // wedge only
+  double* cJ;             // [K] C_J^K
+  double* minJ;           // [K] minimum J over the element's points
+};
+
+struct EnergyArgs {
+  int type;
+  int64_t K;
+  int Np;
+  const float* U;
+  const float* geo;
+  const float2* mat;
+  const double* Mhat;     // tet reference mass [Np][Np]
+  double* partial;        // one per block
+};
+
+void launch_geometry(const GeoArgs& g, hipStream_t s);
+void launch_points(int type, int64_t K, int nv, const double* V, const double* pts, int npts, double* out,
+                   hipStream_t s);
+void launch_project(int type, int64_t K, int nv, const double* V, const double* pts, const double* w, int npts,
+                    int Np, const double* Phi, const double* geo_pts, const double* f0, const double* f1,
+                    const double* f2, const double* f3, double* tmp, float* U, hipStream_t s);
+int launch_energy(const EnergyArgs& a, hipStream_t s);
+void launch_finite(int64_t n, const float* x, int* flag, hipStream_t s);
+
+// Fused stage kernel for one element type; returns 0 or -1 if (type, N) has
+// no instantiation.
+int launch_stage(int type, int N, const StageArgs& a, hipStream_t s);
+// Packed operator table sizes of the stage kernel for (type, N).
+void stage_table_sizes(int type, int N, int* n_floats, int* n_ints);
+int stage_batch(int type, int N);
+
+}  // namespace hdg

@@ -1,0 +1,253 @@
+// FP64 set-up and diagnostic kernels: geometric factors, face normals and
+// surface Jacobians, sample points and projection of initial data, energy.
+#include <hip/hip_runtime.h>
+
+#include "geom.hpp"
+#include "kernels.hpp"
+
+namespace hdg {
+
+// One thread per element: volume factors at the type's points, face factors at
+// the canonical face points, and the inputs of the stable time step.
+__global__ void geometry_kernel(GeoArgs g) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.K) return;
+  const GeoTables& T = *g.T;
+  const int type = g.type;
+  const int nv = T.nv[type], nf = T.nf[type];
+  double V[8][3];
+  for (int v = 0; v < nv; ++v)
+    for (int d = 0; d < 3; ++d) V[v][d] = g.V[(e * nv + v) * 3 + d];
+  double minJ = 1e300;   // over volume points: enters C_J^K (Section 3.4)
+  double minJall;        // over volume and face points: validity check
+  // ---- volume points
+  for (int i = 0; i < g.nvp; ++i) {
+    double x[3], F[3][3], G[3][3];
+    vmap(type, V, g.vpts + 3 * i, x, F);
+    const double J = inv3(F, G);
+    minJ = J < minJ ? J : minJ;
+    if (type == 3) {
+      for (int r = 0; r < 3; ++r)
+        for (int d = 0; d < 3; ++d) g.geo[e * 12 + 3 * r + d] = (float)G[r][d];
+      g.geo[e * 12 + 9] = (float)(1.0 / J);
+      g.geo[e * 12 + 10] = 0.f;
+      g.geo[e * 12 + 11] = 0.f;
+    } else if (type == 1) {
+      double gJ[3];
+      wedge_gradJ(V, g.vpts + 3 * i, gJ);
+      const int64_t base = e * 12 * g.nvp + i;
+      for (int r = 0; r < 3; ++r)
+        for (int d = 0; d < 3; ++d) g.geo[base + (3 * r + d) * g.nvp] = (float)G[r][d];
+      for (int d = 0; d < 3; ++d) g.geo[base + (9 + d) * g.nvp] = (float)(gJ[d] / (2.0 * J));
+    } else {
+      const int64_t base = e * 10 * g.nvp + i;
+      for (int r = 0; r < 3; ++r)
+        for (int d = 0; d < 3; ++d) g.geo[base + (3 * r + d) * g.nvp] = (float)G[r][d];
+      g.geo[base + 9 * g.nvp] = (type == 0) ? (float)(1.0 / (g.vw[i] * J)) : (float)J;
+    }
+  }
+  // ---- faces
+  minJall = minJ;
+  double cj = 0.0;
+  const int Nfq = T.Nfq;
+  for (int f = 0; f < nf; ++f) {
+    const int o = g.ori[e * nf + f];
+    const int fnv = T.fnv[type][f];
+    const double sref = (fnv == 3 ? 2.0 : 4.0) / T.farea[type][f];
+    for (int q = 0; q < Nfq; ++q) {
+      double Xr[3], xq[3], cr[3], x[3], F[3][3], G[3][3];
+      face_point(T, type, V, f, o, q, Xr, xq, cr);
+      vmap(type, V, Xr, x, F);
+      const double J = inv3(F, G);
+      minJall = J < minJall ? J : minJall;
+      const double js = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+      double out[3];
+      for (int d = 0; d < 3; ++d)
+        out[d] = G[0][d] * T.nref[type][f][0] + G[1][d] * T.nref[type][f][1] + G[2][d] * T.nref[type][f][2];
+      const double sg = (cr[0] * out[0] + cr[1] * out[1] + cr[2] * out[2]) >= 0.0 ? 1.0 : -1.0;
+      const double w = (fnv == 3) ? T.tri_w[q] : T.quad_w[q];
+      const double jsr = js * sref;
+      if (type == 1) {
+        cj = jsr / J > cj ? jsr / J : cj;
+        g.isqJ[(e * nf + f) * Nfq + q] = (float)(1.0 / sqrt(J));
+      } else {
+        cj = jsr > cj ? jsr : cj;
+      }
+      if (g.fstride == 1) {
+        if (q == 0)
+          g.fgeo[e * nf + f] = make_float4((float)(sg * cr[0] / js), (float)(sg * cr[1] / js),
+                                           (float)(sg * cr[2] / js), (float)js);
+      } else {
+        g.fgeo[(e * nf + f) * Nfq + q] = make_float4((float)(sg * cr[0] / js), (float)(sg * cr[1] / js),
+                                                     (float)(sg * cr[2] / js), (float)(w * js));
+      }
+    }
+  }
+  g.minJ[e] = minJall;
+  g.cJ[e] = (type == 1) ? cj : cj / minJ;
+}
+
+// Physical coordinates of the sample points: out[(e*npts + i)*3 + d].
+__global__ void points_kernel(int type, int64_t K, int nv, const double* Vall, const double* pts, int npts,
+                              double* out) {
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= K * npts) return;
+  const int64_t e = it / npts;
+  const int i = (int)(it % npts);
+  double V[8][3];
+  for (int v = 0; v < nv; ++v)
+    for (int d = 0; d < 3; ++d) V[v][d] = Vall[(e * nv + v) * 3 + d];
+  double x[3], F[3][3];
+  vmap(type, V, pts + 3 * i, x, F);
+  for (int d = 0; d < 3; ++d) out[it * 3 + d] = x[d];
+}
+
+// Projection step 1: tmp[c][e][q] = w_q * jw(J_q) * f_c(e, q), with
+// jw = sqrt(J) (LSC wedge) or J (pyramid).
+__global__ void project_weight_kernel(int type, int64_t K, int nv, const double* Vall, const double* pts,
+                                      const double* w, int npts, const double* f0, const double* f1,
+                                      const double* f2, const double* f3, double* tmp) {
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= K * npts) return;
+  const int64_t e = it / npts;
+  const int q = (int)(it % npts);
+  double V[8][3];
+  for (int v = 0; v < nv; ++v)
+    for (int d = 0; d < 3; ++d) V[v][d] = Vall[(e * nv + v) * 3 + d];
+  double x[3], F[3][3];
+  vmap(type, V, pts + 3 * q, x, F);
+  const double J = det3(F);
+  const double s = w[q] * (type == 1 ? sqrt(J) : J);
+  const int64_t n = K * npts;
+  tmp[it] = s * f0[it];
+  tmp[n + it] = s * f1[it];
+  tmp[2 * n + it] = s * f2[it];
+  tmp[3 * n + it] = s * f3[it];
+}
+
+// Projection step 2: U[c][e][i] = sum_q Phi[q][i] tmp[c][e][q] / m_i, with
+// m_i = J(a_i, b_j) for the pyramid and 1 for the wedge.
+__global__ void project_apply_kernel(int type, int64_t K, int nv, const double* Vall, const double* Phi, int npts,
+                                     int Np, const double* geo_pts, const double* tmp, float* U) {
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= K * Np) return;
+  const int64_t e = it / Np;
+  const int i = (int)(it % Np);
+  double m = 1.0;
+  if (type == 2) {
+    double V[8][3];
+    for (int v = 0; v < nv; ++v)
+      for (int d = 0; d < 3; ++d) V[v][d] = Vall[(e * nv + v) * 3 + d];
+    double x[3], F[3][3];
+    vmap(type, V, geo_pts + 3 * i, x, F);
+    m = det3(F);
+  }
+  const int64_t n = K * npts;
+  for (int c = 0; c < 4; ++c) {
+    double s = 0.0;
+    for (int q = 0; q < npts; ++q) s += Phi[(int64_t)q * Np + i] * tmp[c * n + e * npts + q];
+    U[(int64_t)c * K * Np + it] = (float)(s / m);
+  }
+}
+
+__global__ void copy_samples_kernel(int64_t n, const double* f0, const double* f1, const double* f2,
+                                    const double* f3, float* U) {
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= n) return;
+  U[it] = (float)f0[it];
+  U[n + it] = (float)f1[it];
+  U[2 * n + it] = (float)f2[it];
+  U[3 * n + it] = (float)f3[it];
+}
+
+// Energy 1/2 sum (p^T M p / kappa + rho u^T M u), one thread per element,
+// FP64 accumulation, one partial sum per block.
+__global__ void energy_kernel(EnergyArgs a) {
+  __shared__ double red[256];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (e < a.K) {
+    const int Np = a.Np;
+    const double kap = a.mat[e].x, rho = 1.0 / a.mat[e].y;
+    const int64_t n = a.K * Np;
+    const float* U = a.U;
+    if (a.type == 3) {
+      const double J = 1.0 / a.geo[e * 12 + 9];
+      for (int i = 0; i < Np; ++i)
+        for (int j = 0; j < Np; ++j) {
+          const double m = a.Mhat[i * Np + j] * J;
+          const int64_t ii = e * Np + i, jj = e * Np + j;
+          acc += m * ((double)U[ii] * U[jj] / kap +
+                      rho * ((double)U[n + ii] * U[n + jj] + (double)U[2 * n + ii] * U[2 * n + jj] +
+                             (double)U[3 * n + ii] * U[3 * n + jj]));
+        }
+    } else {
+      for (int i = 0; i < Np; ++i) {
+        double m = 1.0;
+        if (a.type == 0) m = 1.0 / a.geo[(e * 10 + 9) * Np + i];
+        else if (a.type == 2) m = a.geo[(e * 10 + 9) * Np + i];
+        const int64_t ii = e * Np + i;
+        acc += m * ((double)U[ii] * U[ii] / kap +
+                    rho * ((double)U[n + ii] * U[n + ii] + (double)U[2 * n + ii] * U[2 * n + ii] +
+                           (double)U[3 * n + ii] * U[3 * n + ii]));
+      }
+    }
+  }
+  red[threadIdx.x] = 0.5 * acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.partial[blockIdx.x] = red[0];
+}
+
+// Finite check of a float array: flag[0] = 1 if any entry is NaN or Inf.
+__global__ void finite_kernel(int64_t n, const float* x, int* flag) {
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= n) return;
+  const float v = x[it];
+  if (!(v == v) || v > 3.0e38f || v < -3.0e38f) flag[0] = 1;
+}
+
+// ---- host launchers --------------------------------------------------------
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_geometry(const GeoArgs& g, hipStream_t s) {
+  if (g.K == 0) return;
+  hipLaunchKernelGGL(geometry_kernel, dim3(nblk(g.K, 64)), dim3(64), 0, s, g);
+}
+
+void launch_points(int type, int64_t K, int nv, const double* V, const double* pts, int npts, double* out,
+                   hipStream_t s) {
+  if (K == 0) return;
+  hipLaunchKernelGGL(points_kernel, dim3(nblk(K * npts, 256)), dim3(256), 0, s, type, K, nv, V, pts, npts, out);
+}
+
+void launch_project(int type, int64_t K, int nv, const double* V, const double* pts, const double* w, int npts,
+                    int Np, const double* Phi, const double* geo_pts, const double* f0, const double* f1,
+                    const double* f2, const double* f3, double* tmp, float* U, hipStream_t s) {
+  if (K == 0) return;
+  if (type == 0 || type == 3) {
+    hipLaunchKernelGGL(copy_samples_kernel, dim3(nblk(K * Np, 256)), dim3(256), 0, s, K * Np, f0, f1, f2, f3, U);
+    return;
+  }
+  hipLaunchKernelGGL(project_weight_kernel, dim3(nblk(K * npts, 256)), dim3(256), 0, s, type, K, nv, V, pts, w,
+                     npts, f0, f1, f2, f3, tmp);
+  hipLaunchKernelGGL(project_apply_kernel, dim3(nblk(K * Np, 256)), dim3(256), 0, s, type, K, nv, V, Phi, npts, Np,
+                     geo_pts, tmp, U);
+}
+
+int launch_energy(const EnergyArgs& a, hipStream_t s) {
+  if (a.K == 0) return 0;
+  const unsigned nb = nblk(a.K, 256);
+  hipLaunchKernelGGL(energy_kernel, dim3(nb), dim3(256), 0, s, a);
+  return (int)nb;
+}
+
+void launch_finite(int64_t n, const float* x, int* flag, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(finite_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, n, x, flag);
+}
+
+}  // namespace hdg

@@ -1,0 +1,159 @@
+// Fused stage kernel body for GL nodal hexahedra (Section 2.3.1,
+// Algorithms 1-3; strong form, collocated mass diag(w J)).
+//
+// Volume:  reference derivatives by 1D contractions with D_ij = l_j'(x_i)
+//          along each tensor line, chain rule with G = d(r,s,t)/dx per node.
+// Surface: node (i,j,k) receives l_i(-1) w J^s flux on face r = -1 at local
+//          face point (j,k), and likewise for the other five faces; the
+//          inverse mass 1/(w_ijk J_ijk) is applied per node.
+// Traces:  u(+-1, s_j, t_k) = sum_m l_m(+-1) u_mjk (Algorithm 2) at the local
+//          face point that the canonical point maps to under the face's
+//          orientation (a permutation of the GL tensor grid).
+#pragma once
+
+#include "stage_common.hpp"
+
+namespace hdg {
+
+template <int N, int EPB>
+struct HexStage {
+  static constexpr int n1 = N + 1;
+  static constexpr int Np = n1 * n1 * n1;
+  static constexpr int Nfq = n1 * n1;
+  static constexpr int NT = 256;
+  static constexpr int kEPB = EPB;
+  static constexpr int nphase = 4;
+  static constexpr int kOpsFloats = n1 * n1 + 2 * n1;
+  static constexpr int kOpsInts = 8 * Nfq;
+
+  struct Smem {
+    float D1[n1][n1];
+    float Lf[2][n1];  // l_m(-1), l_m(+1)
+    int qperm[8][Nfq];
+    float u[4][EPB][Np];
+    float un[4][EPB][Np];
+    float g[EPB][6][Nfq][4];
+    float mat[EPB][2];
+  };
+
+  HD static bool active(int ph, int mode) {
+    if (mode == kModeTrace) return ph == 0 || ph == 3;
+    if (mode == kModeRhs) return ph <= 2;
+    return true;
+  }
+
+  HD static void load_ops(int tid, Smem& sm, const StageArgs& a) {
+    for (int i = tid; i < n1 * n1; i += NT) (&sm.D1[0][0])[i] = a.ops[i];
+    for (int i = tid; i < 2 * n1; i += NT) (&sm.Lf[0][0])[i] = a.ops[n1 * n1 + i];
+    for (int i = tid; i < 8 * Nfq; i += NT) (&sm.qperm[0][0])[i] = a.iops[i];
+  }
+
+  // element node index of the m-th node on the line normal to face f through
+  // local face point (l1, l2)
+  HD static int line_node(int f, int m, int l1, int l2) {
+    if (f < 2) return m + n1 * (l1 + n1 * l2);
+    if (f < 4) return l1 + n1 * (m + n1 * l2);
+    return l1 + n1 * (l2 + n1 * m);
+  }
+
+  HD static void phase(int ph, int tid, Smem& sm, const StageArgs& a, int64_t e0) {
+    const int64_t K = a.K;
+    if (ph == 0) {
+      for (int it = tid; it < 4 * EPB * Np; it += NT) {
+        const int f = it / (EPB * Np), r = it % (EPB * Np);
+        const int el = r / Np;
+        (&sm.u[0][0][0])[it] = (e0 + el < K) ? a.U[(int64_t)f * K * Np + e0 * Np + r] : 0.0f;
+      }
+      for (int it = tid; it < EPB; it += NT) {
+        const int64_t e = e0 + it;
+        sm.mat[it][0] = e < K ? a.mat[e].x : 0.f;
+        sm.mat[it][1] = e < K ? a.mat[e].y : 0.f;
+      }
+    } else if (ph == 1) {
+      for (int it = tid; it < EPB * 6 * Nfq; it += NT) {
+        const int el = it / (6 * Nfq), rr = it % (6 * Nfq);
+        const int f = rr / Nfq, q = rr % Nfq;
+        const int64_t e = e0 + el;
+        if (e >= K) continue;
+        const int64_t slot = a.slot0 + e * 6 + f;
+        const float4 g = a.fgeo[(e * 6 + f) * Nfq + q];
+        float4 m, p;
+        face_states(a, slot, Nfq, q, g, m, p);
+        float out[4];
+        upwind_flux(m, p, g, a.tau[slot], false, out);
+        const int l = sm.qperm[a.ori[slot]][q];
+        for (int c = 0; c < 4; ++c) sm.g[el][f][l][c] = out[c];
+      }
+    } else if (ph == 2) {
+      for (int it = tid; it < EPB * Np; it += NT) {
+        const int el = it / Np, node = it % Np;
+        const int64_t e = e0 + el;
+        if (e >= K) continue;
+        const int i = node % n1, j = (node / n1) % n1, k = node / (n1 * n1);
+        float du[4][3];
+        for (int c = 0; c < 4; ++c) {
+          float dr = 0.f, ds = 0.f, dt = 0.f;
+          for (int m = 0; m < n1; ++m) {
+            dr += sm.D1[i][m] * sm.u[c][el][m + n1 * (j + n1 * k)];
+            ds += sm.D1[j][m] * sm.u[c][el][i + n1 * (m + n1 * k)];
+            dt += sm.D1[k][m] * sm.u[c][el][i + n1 * (j + n1 * m)];
+          }
+          du[c][0] = dr;
+          du[c][1] = ds;
+          du[c][2] = dt;
+        }
+        float G[3][3];
+        const float* gp = a.geo + e * 10 * Np + node;
+        for (int r = 0; r < 3; ++r)
+          for (int d = 0; d < 3; ++d) G[r][d] = gp[(3 * r + d) * Np];
+        const float iwJ = gp[9 * Np];
+        float div = 0.f;
+        for (int r = 0; r < 3; ++r)
+          for (int d = 0; d < 3; ++d) div += G[r][d] * du[1 + d][r];
+        float surf[4];
+        for (int c = 0; c < 4; ++c)
+          surf[c] = sm.Lf[0][i] * sm.g[el][0][k * n1 + j][c] + sm.Lf[1][i] * sm.g[el][1][k * n1 + j][c] +
+                    sm.Lf[0][j] * sm.g[el][2][k * n1 + i][c] + sm.Lf[1][j] * sm.g[el][3][k * n1 + i][c] +
+                    sm.Lf[0][k] * sm.g[el][4][j * n1 + i][c] + sm.Lf[1][k] * sm.g[el][5][j * n1 + i][c];
+        const float kap = sm.mat[el][0], irho = sm.mat[el][1];
+        float rhs[4];
+        rhs[0] = kap * (-div + iwJ * surf[0]);
+        for (int d = 0; d < 3; ++d)
+          rhs[1 + d] = irho * (-(G[0][d] * du[0][0] + G[1][d] * du[0][1] + G[2][d] * du[0][2]) + iwJ * surf[1 + d]);
+        const int64_t base = e * Np + node;
+        for (int c = 0; c < 4; ++c) {
+          const int64_t gi = (int64_t)c * K * Np + base;
+          if (a.mode == kModeRhs) {
+            a.R[gi] = rhs[c];
+          } else {
+            const float res = a.a * a.R[gi] + a.dt * rhs[c];
+            const float un = sm.u[c][el][node] + a.b * res;
+            a.R[gi] = res;
+            a.U[gi] = un;
+            sm.un[c][el][node] = un;
+          }
+        }
+      }
+    } else if (ph == 3) {
+      const float(*src)[EPB][Np] = (a.mode == kModeTrace) ? sm.u : sm.un;
+      for (int it = tid; it < EPB * 6 * Nfq; it += NT) {
+        const int el = it / (6 * Nfq), rr = it % (6 * Nfq);
+        const int f = rr / Nfq, q = rr % Nfq;
+        const int64_t e = e0 + el;
+        if (e >= K) continue;
+        const int64_t slot = a.slot0 + e * 6 + f;
+        const int l = sm.qperm[a.ori[slot]][q];
+        const int l1 = l % n1, l2 = l / n1;
+        const float* L = sm.Lf[f & 1];
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int m = 0; m < n1; ++m) {
+          const int nd = line_node(f, m, l1, l2);
+          for (int c = 0; c < 4; ++c) acc[c] += L[m] * src[c][el][nd];
+        }
+        a.tr_out[slot * Nfq + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+      }
+    }
+  }
+};
+
+}  // namespace hdg

@@ -1,0 +1,229 @@
+// Fused stage kernel body for semi-nodal pyramids (Section 2.3.4,
+// Algorithm 7: skew-symmetric form with the quadrature-free operators).
+//
+// Volume:  rhs_u_d = -(1/rho) sum_r G_rd (D^r p),
+//          rhs_p   = (kappa / J_i) sum_r sum_j D^r_ji U^r_j,
+//          U^r_j   = J_j sum_d G_rd,j u_d,j   (premultiplied dofs),
+//          with G, J at (a_i^k, b_j^k) (constant in c) and mass diag(J).
+// Surface: base (quadrilateral) face through the basis values at its local GL
+//          points; triangular faces through the face's equispaced lattice
+//          (the pyramid's trace on a triangle is a degree-N polynomial), as
+//          for tetrahedra.
+#pragma once
+
+#include "stage_common.hpp"
+
+namespace hdg {
+
+template <int N, int EPB>
+struct PyrStage {
+  static constexpr int Np = (N + 1) * (N + 2) * (2 * N + 3) / 6;
+  static constexpr int Nfn = (N + 1) * (N + 2) / 2;
+  static constexpr int Nfq = (N + 1) * (N + 1);
+  static constexpr int NT = 256;
+  static constexpr int kEPB = EPB;
+  static constexpr int nphase = 7;
+  static constexpr bool kDInLds = (3 * Np * Np * 4) <= 48 * 1024;
+  static constexpr int kOpsFloats = 3 * Np * Np + Nfq * Np + 4 * Nfn * Np + Nfq * Nfn;
+  static constexpr int kOpsInts = 8 * Nfq + 6 * Nfn;
+  static constexpr int kDl = kDInLds ? Np : 1;
+
+  struct Smem {
+    float D[3][kDl][kDl];
+    float Fq[Nfq][Np];
+    float Ft[4][Nfn][Np];
+    float Ican[Nfq][Nfn];
+    int qperm[8][Nfq];
+    int tperm[6][Nfn];
+    float u[4][EPB][Np];
+    float un[4][EPB][Np];
+    float ur[3][EPB][Np];
+    float J[EPB][Np];
+    float g[EPB][5][Nfq][4];
+    float c[EPB][4][Nfn][4];
+    float s[EPB][Np][4];
+    float mat[EPB][2];
+  };
+
+  HD static bool active(int ph, int mode) {
+    if (mode == kModeTrace) return ph == 0 || ph >= 5;
+    if (mode == kModeRhs) return ph <= 4;
+    return true;
+  }
+
+  HD static float Dop(const Smem& sm, const StageArgs& a, int r, int i, int j) {
+    if (kDInLds) return sm.D[r][i % kDl][j % kDl];
+    return a.ops[(r * Np + i) * Np + j];
+  }
+
+  HD static void load_ops(int tid, Smem& sm, const StageArgs& a) {
+    if (kDInLds)
+      for (int i = tid; i < 3 * Np * Np; i += NT) (&sm.D[0][0][0])[i] = a.ops[i];
+    const int o1 = 3 * Np * Np, o2 = o1 + Nfq * Np, o3 = o2 + 4 * Nfn * Np;
+    for (int i = tid; i < Nfq * Np; i += NT) (&sm.Fq[0][0])[i] = a.ops[o1 + i];
+    for (int i = tid; i < 4 * Nfn * Np; i += NT) (&sm.Ft[0][0][0])[i] = a.ops[o2 + i];
+    for (int i = tid; i < Nfq * Nfn; i += NT) (&sm.Ican[0][0])[i] = a.ops[o3 + i];
+    for (int i = tid; i < 8 * Nfq; i += NT) (&sm.qperm[0][0])[i] = a.iops[i];
+    for (int i = tid; i < 6 * Nfn; i += NT) (&sm.tperm[0][0])[i] = a.iops[8 * Nfq + i];
+  }
+
+  HD static void phase(int ph, int tid, Smem& sm, const StageArgs& a, int64_t e0) {
+    const int64_t K = a.K;
+    if (ph == 0) {
+      for (int it = tid; it < 4 * EPB * Np; it += NT) {
+        const int f = it / (EPB * Np), r = it % (EPB * Np);
+        const int el = r / Np;
+        (&sm.u[0][0][0])[it] = (e0 + el < K) ? a.U[(int64_t)f * K * Np + e0 * Np + r] : 0.0f;
+      }
+      for (int it = tid; it < EPB * Np; it += NT) {
+        const int el = it / Np, i = it % Np;
+        const int64_t e = e0 + el;
+        sm.J[el][i] = e < K ? a.geo[(e * 10 + 9) * Np + i] : 1.0f;
+      }
+      for (int it = tid; it < EPB; it += NT) {
+        const int64_t e = e0 + it;
+        sm.mat[it][0] = e < K ? a.mat[e].x : 0.f;
+        sm.mat[it][1] = e < K ? a.mat[e].y : 0.f;
+      }
+    } else if (ph == 1) {
+      for (int it = tid; it < EPB * Np; it += NT) {
+        const int el = it / Np, i = it % Np;
+        const int64_t e = e0 + el;
+        if (e >= K) {
+          for (int r = 0; r < 3; ++r) sm.ur[r][el][i] = 0.f;
+          continue;
+        }
+        const float* gp = a.geo + e * 10 * Np + i;
+        for (int r = 0; r < 3; ++r)
+          sm.ur[r][el][i] = gp[9 * Np] * (gp[(3 * r) * Np] * sm.u[1][el][i] + gp[(3 * r + 1) * Np] * sm.u[2][el][i] +
+                                          gp[(3 * r + 2) * Np] * sm.u[3][el][i]);
+      }
+      for (int it = tid; it < EPB * 5 * Nfq; it += NT) {
+        const int el = it / (5 * Nfq), rr = it % (5 * Nfq);
+        const int f = rr / Nfq, q = rr % Nfq;
+        const int64_t e = e0 + el;
+        if (e >= K) continue;
+        const int64_t slot = a.slot0 + e * 5 + f;
+        const float4 g = a.fgeo[(e * 5 + f) * Nfq + q];
+        float4 m, p;
+        face_states(a, slot, Nfq, q, g, m, p);
+        float out[4];
+        upwind_flux(m, p, g, a.tau[slot], true, out);
+        const int l = (f == 0) ? sm.qperm[a.ori[slot]][q] : q;
+        for (int c = 0; c < 4; ++c) sm.g[el][f][l][c] = out[c];
+      }
+    } else if (ph == 2) {
+      for (int it = tid; it < EPB * 4 * Nfn; it += NT) {
+        const int el = it / (4 * Nfn), rr = it % (4 * Nfn);
+        const int tf = rr / Nfn, m = rr % Nfn;
+        const int64_t e = e0 + el;
+        if (e >= K) continue;
+        const int o = a.ori[a.slot0 + e * 5 + 1 + tf];
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < Nfq; ++q) {
+          const float w = sm.Ican[q][m];
+          for (int c = 0; c < 4; ++c) acc[c] += w * sm.g[el][1 + tf][q][c];
+        }
+        const int l = sm.tperm[o][m];
+        for (int c = 0; c < 4; ++c) sm.c[el][tf][l][c] = acc[c];
+      }
+    } else if (ph == 3) {
+      for (int it = tid; it < EPB * Np; it += NT) {
+        const int el = it / Np, i = it % Np;
+        if (e0 + el >= K) continue;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int l = 0; l < Nfq; ++l) {
+          const float w = sm.Fq[l][i];
+          for (int c = 0; c < 4; ++c) acc[c] += w * sm.g[el][0][l][c];
+        }
+        for (int tf = 0; tf < 4; ++tf)
+          for (int l = 0; l < Nfn; ++l) {
+            const float w = sm.Ft[tf][l][i];
+            for (int c = 0; c < 4; ++c) acc[c] += w * sm.c[el][tf][l][c];
+          }
+        for (int c = 0; c < 4; ++c) sm.s[el][i][c] = acc[c];
+      }
+    } else if (ph == 4) {
+      for (int it = tid; it < EPB * Np; it += NT) {
+        const int el = it / Np, i = it % Np;
+        const int64_t e = e0 + el;
+        if (e >= K) continue;
+        float Dp[3] = {0.f, 0.f, 0.f}, volp = 0.f;
+        for (int j = 0; j < Np; ++j) {
+          const float pj = sm.u[0][el][j];
+          for (int r = 0; r < 3; ++r) {
+            Dp[r] += Dop(sm, a, r, i, j) * pj;
+            volp += Dop(sm, a, r, j, i) * sm.ur[r][el][j];
+          }
+        }
+        const float* gp = a.geo + e * 10 * Np + i;
+        float G[3][3];
+        for (int r = 0; r < 3; ++r)
+          for (int d = 0; d < 3; ++d) G[r][d] = gp[(3 * r + d) * Np];
+        const float iJ = 1.0f / sm.J[el][i];
+        const float kap = sm.mat[el][0], irho = sm.mat[el][1];
+        float rhs[4];
+        rhs[0] = kap * iJ * (volp + sm.s[el][i][0]);
+        for (int d = 0; d < 3; ++d)
+          rhs[1 + d] = irho * (-(G[0][d] * Dp[0] + G[1][d] * Dp[1] + G[2][d] * Dp[2]) + iJ * sm.s[el][i][1 + d]);
+        const int64_t base = e * Np + i;
+        for (int c = 0; c < 4; ++c) {
+          const int64_t gi = (int64_t)c * K * Np + base;
+          if (a.mode == kModeRhs) {
+            a.R[gi] = rhs[c];
+          } else {
+            const float res = a.a * a.R[gi] + a.dt * rhs[c];
+            const float un = sm.u[c][el][i] + a.b * res;
+            a.R[gi] = res;
+            a.U[gi] = un;
+            sm.un[c][el][i] = un;
+          }
+        }
+      }
+    } else if (ph == 5) {
+      // base-face traces at canonical points; triangle-face lattice values
+      const float(*src)[EPB][Np] = (a.mode == kModeTrace) ? sm.u : sm.un;
+      for (int it = tid; it < EPB * Nfq; it += NT) {
+        const int el = it / Nfq, q = it % Nfq;
+        const int64_t e = e0 + el;
+        if (e >= K) continue;
+        const int64_t slot = a.slot0 + e * 5;
+        const int l = sm.qperm[a.ori[slot]][q];
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < Np; ++j) {
+          const float w = sm.Fq[l][j];
+          for (int c = 0; c < 4; ++c) acc[c] += w * src[c][el][j];
+        }
+        a.tr_out[slot * Nfq + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+      }
+      for (int it = tid; it < EPB * 4 * Nfn; it += NT) {
+        const int el = it / (4 * Nfn), rr = it % (4 * Nfn);
+        const int tf = rr / Nfn, l = rr % Nfn;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < Np; ++j) {
+          const float w = sm.Ft[tf][l][j];
+          for (int c = 0; c < 4; ++c) acc[c] += w * src[c][el][j];
+        }
+        for (int c = 0; c < 4; ++c) sm.c[el][tf][l][c] = acc[c];
+      }
+    } else if (ph == 6) {
+      for (int it = tid; it < EPB * 4 * Nfq; it += NT) {
+        const int el = it / (4 * Nfq), rr = it % (4 * Nfq);
+        const int tf = rr / Nfq, q = rr % Nfq;
+        const int64_t e = e0 + el;
+        if (e >= K) continue;
+        const int64_t slot = a.slot0 + e * 5 + 1 + tf;
+        const int o = a.ori[slot];
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int m = 0; m < Nfn; ++m) {
+          const float w = sm.Ican[q][m];
+          const int l = sm.tperm[o][m];
+          for (int c = 0; c < 4; ++c) acc[c] += w * sm.c[el][tf][l][c];
+        }
+        a.tr_out[slot * Nfq + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+      }
+    }
+  }
+};
+
+}  // namespace hdg

@@ -1,0 +1,291 @@
+// Fused stage kernel body for LSC-DG wedges (Sections 2.1.3 and 2.3.3,
+// Algorithms 5-6: skew-symmetric form, basis phi/sqrt(J), mass = I).
+//
+// The basis is a tensor product phi_{js,jt} = phi^tri_jt(r,t) phi^1D_js(s),
+// and so is the cubature (triangle rule x GL in s), so every evaluation and
+// every test integral is done by sum factorisation: contract the 1D index
+// first, then the triangle index.  The trial integrand at cubature point q is
+//   B_r = w_q (G U)_r,  B_h = w_q (grad J / 2J) . U,
+//   C_d = w_q (sum_r G_rd d_r P - P (grad J / 2J)_d),
+// with P, U the polynomial parts sum_j u_j phi_j, and the test integrals are
+//   rhs_p,i   = kappa (sum_q grad_rst phi_i . B - phi_i B_h + surface),
+//   rhs_u_d,i = (1/rho) (-sum_q phi_i C_d + surface).
+// The intermediate values stay in LDS (the paper writes them to global
+// memory between two kernels).
+#pragma once
+
+#include "stage_common.hpp"
+
+namespace hdg {
+
+template <int N, int EPB>
+struct WedgeStage {
+  static constexpr int n1 = N + 1;
+  static constexpr int Ntri = (N + 1) * (N + 2) / 2;
+  static constexpr int Np = n1 * Ntri;
+  static constexpr int Nct = n1 * n1;
+  static constexpr int Nq = n1 * Nct;
+  static constexpr int Nfq = n1 * n1;
+  static constexpr int Nfn = Ntri;
+  static constexpr int NT = 256;
+  static constexpr int kEPB = EPB;
+  static constexpr int nphase = 7;
+  // ops: Pt, Ptr, Ptt [Nct][Ntri]; tri_w [Nct]; P1, dP1 [n1][n1]; w1 [n1];
+  //      P1f [2][n1]; Ftri [Nfn][Ntri]; Fedge [3][n1][Ntri]; Ican [Nfq][Nfn]
+  static constexpr int oPt = 0, oPtr = oPt + Nct * Ntri, oPtt = oPtr + Nct * Ntri, oTw = oPtt + Nct * Ntri;
+  static constexpr int oP1 = oTw + Nct, odP1 = oP1 + n1 * n1, ow1 = odP1 + n1 * n1, oP1f = ow1 + n1;
+  static constexpr int oFt = oP1f + 2 * n1, oFe = oFt + Nfn * Ntri, oIc = oFe + 3 * n1 * Ntri;
+  static constexpr int kOpsFloats = oIc + Nfq * Nfn;
+  static constexpr int kOpsInts = 8 * Nfq + 6 * Nfn;
+
+  struct Smem {
+    float ops[kOpsFloats];
+    int qperm[8][Nfq];
+    int tperm[6][Nfn];
+    float u[4][EPB][Np];
+    float un[4][EPB][Np];
+    float A[5][EPB][n1][Ntri];
+    float B[7][EPB][Nq];
+    float T[5][EPB][n1][Ntri];
+    float g[EPB][5][Nfq][4];
+    float c[EPB][2][Nfn][4];
+    float s[EPB][Np][4];
+    float mat[EPB][2];
+  };
+
+  HD static bool active(int ph, int mode) {
+    if (mode == kModeTrace) return ph == 0 || ph >= 5;
+    if (mode == kModeRhs) return ph <= 4;
+    return true;
+  }
+
+  HD static void load_ops(int tid, Smem& sm, const StageArgs& a) {
+    for (int i = tid; i < kOpsFloats; i += NT) sm.ops[i] = a.ops[i];
+    for (int i = tid; i < 8 * Nfq; i += NT) (&sm.qperm[0][0])[i] = a.iops[i];
+    for (int i = tid; i < 6 * Nfn; i += NT) (&sm.tperm[0][0])[i] = a.iops[8 * Nfq + i];
+  }
+
+  HD static void phase(int ph, int tid, Smem& sm, const StageArgs& a, int64_t e0) {
+    const int64_t K = a.K;
+    const float* O = sm.ops;
+    const float* Pt = O + oPt;
+    const float* Ptr = O + oPtr;
+    const float* Ptt = O + oPtt;
+    const float* Tw = O + oTw;
+    const float* P1 = O + oP1;
+    const float* dP1 = O + odP1;
+    const float* w1 = O + ow1;
+    const float* P1f = O + oP1f;
+    const float* Ft = O + oFt;
+    const float* Fe = O + oFe;
+    const float* Ic = O + oIc;
+    if (ph == 0) {
+      for (int it = tid; it < 4 * EPB * Np; it += NT) {
+        const int f = it / (EPB * Np), r = it % (EPB * Np);
+        const int el = r / Np;
+        (&sm.u[0][0][0])[it] = (e0 + el < K) ? a.U[(int64_t)f * K * Np + e0 * Np + r] : 0.0f;
+      }
+      for (int it = tid; it < EPB; it += NT) {
+        const int64_t e = e0 + it;
+        sm.mat[it][0] = e < K ? a.mat[e].x : 0.f;
+        sm.mat[it][1] = e < K ? a.mat[e].y : 0.f;
+      }
+    } else if (ph == 1) {
+      for (int it = tid; it < EPB * 5 * n1 * Ntri; it += NT) {
+        const int el = it / (5 * n1 * Ntri), rr = it % (5 * n1 * Ntri);
+        const int c = rr / (n1 * Ntri), r2 = rr % (n1 * Ntri);
+        const int qs = r2 / Ntri, jt = r2 % Ntri;
+        const float* op = (c < 4) ? P1 : dP1;
+        const int src = (c < 4) ? c : 0;
+        float acc = 0.f;
+        for (int js = 0; js < n1; ++js) acc += op[qs * n1 + js] * sm.u[src][el][js * Ntri + jt];
+        sm.A[c][el][qs][jt] = acc;
+      }
+      for (int it = tid; it < EPB * 5 * Nfq; it += NT) {
+        const int el = it / (5 * Nfq), rr = it % (5 * Nfq);
+        const int f = rr / Nfq, q = rr % Nfq;
+        const int64_t e = e0 + el;
+        if (e >= K) continue;
+        const int64_t slot = a.slot0 + e * 5 + f;
+        const float4 g = a.fgeo[(e * 5 + f) * Nfq + q];
+        float4 m, p;
+        face_states(a, slot, Nfq, q, g, m, p);
+        float out[4];
+        upwind_flux(m, p, g, a.tau[slot], true, out);
+        const float isj = a.isqJ[(e * 5 + f) * Nfq + q];
+        const int l = (f < 2) ? q : sm.qperm[a.ori[slot]][q];
+        for (int c = 0; c < 4; ++c) sm.g[el][f][l][c] = out[c] * isj;
+      }
+    } else if (ph == 2) {
+      for (int it = tid; it < EPB * Nq; it += NT) {
+        const int el = it / Nq, q = it % Nq;
+        const int qs = q / Nct, qt = q % Nct;
+        const int64_t e = e0 + el;
+        if (e >= K) {
+          for (int k = 0; k < 7; ++k) sm.B[k][el][q] = 0.f;
+          continue;
+        }
+        float P = 0.f, dPr = 0.f, dPt = 0.f, dPs = 0.f, U[3] = {0.f, 0.f, 0.f};
+        for (int jt = 0; jt < Ntri; ++jt) {
+          const float pt = Pt[qt * Ntri + jt];
+          const float a0 = sm.A[0][el][qs][jt];
+          P += pt * a0;
+          dPr += Ptr[qt * Ntri + jt] * a0;
+          dPt += Ptt[qt * Ntri + jt] * a0;
+          dPs += pt * sm.A[4][el][qs][jt];
+          for (int d = 0; d < 3; ++d) U[d] += pt * sm.A[1 + d][el][qs][jt];
+        }
+        const float* gp = a.geo + e * 12 * Nq + q;
+        float G[3][3], hJ[3];
+        for (int r = 0; r < 3; ++r)
+          for (int d = 0; d < 3; ++d) G[r][d] = gp[(3 * r + d) * Nq];
+        for (int d = 0; d < 3; ++d) hJ[d] = gp[(9 + d) * Nq];
+        const float w = Tw[qt] * w1[qs];
+        const float dP[3] = {dPr, dPs, dPt};
+        for (int r = 0; r < 3; ++r) sm.B[r][el][q] = w * (G[r][0] * U[0] + G[r][1] * U[1] + G[r][2] * U[2]);
+        sm.B[3][el][q] = w * (hJ[0] * U[0] + hJ[1] * U[1] + hJ[2] * U[2]);
+        for (int d = 0; d < 3; ++d)
+          sm.B[4 + d][el][q] = w * (G[0][d] * dP[0] + G[1][d] * dP[1] + G[2][d] * dP[2] - P * hJ[d]);
+      }
+      for (int it = tid; it < EPB * 2 * Nfn; it += NT) {
+        const int el = it / (2 * Nfn), rr = it % (2 * Nfn);
+        const int tf = rr / Nfn, m = rr % Nfn;
+        const int64_t e = e0 + el;
+        if (e >= K) continue;
+        const int o = a.ori[a.slot0 + e * 5 + tf];
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < Nfq; ++q) {
+          const float w = Ic[q * Nfn + m];
+          for (int c = 0; c < 4; ++c) acc[c] += w * sm.g[el][tf][q][c];
+        }
+        const int l = sm.tperm[o][m];
+        for (int c = 0; c < 4; ++c) sm.c[el][tf][l][c] = acc[c];
+      }
+    } else if (ph == 3) {
+      for (int it = tid; it < EPB * n1 * Ntri; it += NT) {
+        const int el = it / (n1 * Ntri), rr = it % (n1 * Ntri);
+        const int qs = rr / Ntri, jt = rr % Ntri;
+        float t0 = 0.f, t1 = 0.f, t2 = 0.f, t3 = 0.f, t4 = 0.f;
+        for (int qt = 0; qt < Nct; ++qt) {
+          const int q = qs * Nct + qt;
+          const float pt = Pt[qt * Ntri + jt];
+          t0 += Ptr[qt * Ntri + jt] * sm.B[0][el][q] + Ptt[qt * Ntri + jt] * sm.B[2][el][q] - pt * sm.B[3][el][q];
+          t1 += pt * sm.B[1][el][q];
+          t2 += pt * sm.B[4][el][q];
+          t3 += pt * sm.B[5][el][q];
+          t4 += pt * sm.B[6][el][q];
+        }
+        sm.T[0][el][qs][jt] = t0;
+        sm.T[1][el][qs][jt] = t1;
+        sm.T[2][el][qs][jt] = t2;
+        sm.T[3][el][qs][jt] = t3;
+        sm.T[4][el][qs][jt] = t4;
+      }
+      for (int it = tid; it < EPB * Np; it += NT) {
+        const int el = it / Np, m = it % Np;
+        const int js = m / Ntri, jt = m % Ntri;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int tf = 0; tf < 2; ++tf) {
+          const float s1 = P1f[tf * n1 + js];
+          for (int l = 0; l < Nfn; ++l) {
+            const float w = s1 * Ft[l * Ntri + jt];
+            for (int c = 0; c < 4; ++c) acc[c] += w * sm.c[el][tf][l][c];
+          }
+        }
+        for (int ef = 0; ef < 3; ++ef)
+          for (int l2 = 0; l2 < n1; ++l2) {
+            const float s1 = P1[l2 * n1 + js];
+            for (int l1 = 0; l1 < n1; ++l1) {
+              const float w = s1 * Fe[(ef * n1 + l1) * Ntri + jt];
+              for (int c = 0; c < 4; ++c) acc[c] += w * sm.g[el][2 + ef][l2 * n1 + l1][c];
+            }
+          }
+        for (int c = 0; c < 4; ++c) sm.s[el][m][c] = acc[c];
+      }
+    } else if (ph == 4) {
+      for (int it = tid; it < EPB * Np; it += NT) {
+        const int el = it / Np, m = it % Np;
+        const int js = m / Ntri, jt = m % Ntri;
+        const int64_t e = e0 + el;
+        if (e >= K) continue;
+        float vp = 0.f, vu[3] = {0.f, 0.f, 0.f};
+        for (int qs = 0; qs < n1; ++qs) {
+          const float p1 = P1[qs * n1 + js];
+          vp += p1 * sm.T[0][el][qs][jt] + dP1[qs * n1 + js] * sm.T[1][el][qs][jt];
+          for (int d = 0; d < 3; ++d) vu[d] -= p1 * sm.T[2 + d][el][qs][jt];
+        }
+        const float kap = sm.mat[el][0], irho = sm.mat[el][1];
+        float rhs[4];
+        rhs[0] = kap * (vp + sm.s[el][m][0]);
+        for (int d = 0; d < 3; ++d) rhs[1 + d] = irho * (vu[d] + sm.s[el][m][1 + d]);
+        const int64_t base = e * Np + m;
+        for (int c = 0; c < 4; ++c) {
+          const int64_t gi = (int64_t)c * K * Np + base;
+          if (a.mode == kModeRhs) {
+            a.R[gi] = rhs[c];
+          } else {
+            const float res = a.a * a.R[gi] + a.dt * rhs[c];
+            const float un = sm.u[c][el][m] + a.b * res;
+            a.R[gi] = res;
+            a.U[gi] = un;
+            sm.un[c][el][m] = un;
+          }
+        }
+      }
+    } else if (ph == 5) {
+      const float(*src)[EPB][Np] = (a.mode == kModeTrace) ? sm.u : sm.un;
+      for (int it = tid; it < EPB * 2 * Nfn; it += NT) {
+        const int el = it / (2 * Nfn), rr = it % (2 * Nfn);
+        const int tf = rr / Nfn, l = rr % Nfn;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int js = 0; js < n1; ++js) {
+          const float s1 = P1f[tf * n1 + js];
+          for (int jt = 0; jt < Ntri; ++jt) {
+            const float w = s1 * Ft[l * Ntri + jt];
+            for (int c = 0; c < 4; ++c) acc[c] += w * src[c][el][js * Ntri + jt];
+          }
+        }
+        for (int c = 0; c < 4; ++c) sm.c[el][tf][l][c] = acc[c];
+      }
+      for (int it = tid; it < EPB * 3 * Nfq; it += NT) {
+        const int el = it / (3 * Nfq), rr = it % (3 * Nfq);
+        const int ef = rr / Nfq, q = rr % Nfq;
+        const int64_t e = e0 + el;
+        if (e >= K) continue;
+        const int f = 2 + ef;
+        const int64_t slot = a.slot0 + e * 5 + f;
+        const int l = sm.qperm[a.ori[slot]][q];
+        const int l1 = l % n1, l2 = l / n1;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int js = 0; js < n1; ++js) {
+          const float s1 = P1[l2 * n1 + js];
+          for (int jt = 0; jt < Ntri; ++jt) {
+            const float w = s1 * Fe[(ef * n1 + l1) * Ntri + jt];
+            for (int c = 0; c < 4; ++c) acc[c] += w * src[c][el][js * Ntri + jt];
+          }
+        }
+        const float isj = a.isqJ[(e * 5 + f) * Nfq + q];
+        a.tr_out[slot * Nfq + q] = make_float4(acc[0] * isj, acc[1] * isj, acc[2] * isj, acc[3] * isj);
+      }
+    } else if (ph == 6) {
+      for (int it = tid; it < EPB * 2 * Nfq; it += NT) {
+        const int el = it / (2 * Nfq), rr = it % (2 * Nfq);
+        const int tf = rr / Nfq, q = rr % Nfq;
+        const int64_t e = e0 + el;
+        if (e >= K) continue;
+        const int64_t slot = a.slot0 + e * 5 + tf;
+        const int o = a.ori[slot];
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int m = 0; m < Nfn; ++m) {
+          const float w = Ic[q * Nfn + m];
+          const int l = sm.tperm[o][m];
+          for (int c = 0; c < 4; ++c) acc[c] += w * sm.c[el][tf][l][c];
+        }
+        const float isj = a.isqJ[(e * 5 + tf) * Nfq + q];
+        a.tr_out[slot * Nfq + q] = make_float4(acc[0] * isj, acc[1] * isj, acc[2] * isj, acc[3] * isj);
+      }
+    }
+  }
+};
+
+}  // namespace hdg

@@ -1,0 +1,90 @@
+// Instantiation and dispatch of the fused stage kernels (one per element type
+// and order N = 1..5).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "stage_config.hpp"
+#include "stage_hex.hpp"
+#include "stage_pyr.hpp"
+#include "stage_tet.hpp"
+#include "stage_wedge.hpp"
+
+namespace hdg {
+
+template <class S>
+__global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
+  __shared__ typename S::Smem sm;
+  S::load_ops(threadIdx.x, sm, a);
+  __syncthreads();
+  constexpr int EPB = S::kEPB;
+  const int64_t nb = (a.K + EPB - 1) / EPB;
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    for (int ph = 0; ph < S::nphase; ++ph) {
+      if (!S::active(ph, a.mode)) continue;
+      S::phase(ph, threadIdx.x, sm, a, b * EPB);
+      __syncthreads();
+    }
+  }
+}
+
+template <class S>
+static int go(const StageArgs& a, hipStream_t s) {
+  static_assert(sizeof(typename S::Smem) <= 160 * 1024, "LDS budget exceeded");
+  if (a.K == 0) return 0;
+  const int64_t nb = (a.K + S::kEPB - 1) / S::kEPB;
+  const unsigned grid = (unsigned)(nb < 2048 ? nb : 2048);
+  hipLaunchKernelGGL(stage_kernel<S>, dim3(grid), dim3(S::NT), 0, s, a);
+  return 0;
+}
+
+template <class S>
+static void sizes(int* nf, int* ni) {
+  *nf = S::kOpsFloats;
+  *ni = S::kOpsInts;
+}
+
+template <int N>
+static int launch_n(int type, const StageArgs& a, hipStream_t s) {
+  switch (type) {
+    case 0: return go<HexStage<N, epb(0, N)>>(a, s);
+    case 1: return go<WedgeStage<N, epb(1, N)>>(a, s);
+    case 2: return go<PyrStage<N, epb(2, N)>>(a, s);
+    case 3: return go<TetStage<N, epb(3, N)>>(a, s);
+  }
+  return -1;
+}
+
+template <int N>
+static void sizes_n(int type, int* nf, int* ni) {
+  switch (type) {
+    case 0: sizes<HexStage<N, epb(0, N)>>(nf, ni); break;
+    case 1: sizes<WedgeStage<N, epb(1, N)>>(nf, ni); break;
+    case 2: sizes<PyrStage<N, epb(2, N)>>(nf, ni); break;
+    default: sizes<TetStage<N, epb(3, N)>>(nf, ni); break;
+  }
+}
+
+int launch_stage(int type, int N, const StageArgs& a, hipStream_t s) {
+  switch (N) {
+    case 1: return launch_n<1>(type, a, s);
+    case 2: return launch_n<2>(type, a, s);
+    case 3: return launch_n<3>(type, a, s);
+    case 4: return launch_n<4>(type, a, s);
+    case 5: return launch_n<5>(type, a, s);
+  }
+  return -1;
+}
+
+void stage_table_sizes(int type, int N, int* nf, int* ni) {
+  switch (N) {
+    case 1: sizes_n<1>(type, nf, ni); break;
+    case 2: sizes_n<2>(type, nf, ni); break;
+    case 3: sizes_n<3>(type, nf, ni); break;
+    case 4: sizes_n<4>(type, nf, ni); break;
+    default: sizes_n<5>(type, nf, ni); break;
+  }
+}
+
+int stage_batch(int type, int N) { return epb(type, N); }
+
+}  // namespace hdg

@@ -1,0 +1,192 @@
+"""Thin ctypes binding of the C ABI in include/hdg.h.
+
+Argument marshalling only: every computation runs in the HIP library
+``libhdg.so`` built in-tree by ``paper_1507_02557_amd.build``.  PyTorch supplies
+device memory and the current stream.  Loading fails loudly if the library is
+missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HEX, WEDGE, PYR, TET = 0, 1, 2, 3
+BC_FREE_SURFACE, BC_RIGID_WALL = 0, 1
+PREC_FP32 = 0
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhdg.so")
+
+# (name, restype, argtypes) of every exported symbol
+_P = ctypes.c_void_p
+_SIGS = [
+    ("hdg_create", ctypes.c_int, [ctypes.POINTER(_P), _P, ctypes.c_int, ctypes.c_int, _P]),
+    ("hdg_destroy", None, [_P]),
+    ("hdg_last_error", ctypes.c_char_p, [_P]),
+    ("hdg_type_info", ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    ("hdg_dt", ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double)]),
+    ("hdg_get_points", ctypes.c_int, [_P, ctypes.c_int, _P]),
+    ("hdg_project", ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
+    ("hdg_set_state", ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
+    ("hdg_get_field", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P]),
+    ("hdg_rhs", ctypes.c_int, [_P]),
+    ("hdg_step", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int64]),
+    ("hdg_energy", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    ("hdg_profile", ctypes.c_int, [_P, ctypes.c_int]),
+    ("hdg_profile_read", ctypes.c_int, [_P, _P, _P]),
+]
+EXPORTS = [s[0] for s in _SIGS]
+
+
+class HdgMesh(ctypes.Structure):
+    _fields_ = [("n_vert", ctypes.c_int64), ("xyz", _P), ("n_elem", ctypes.c_int64), ("type", _P),
+                ("verts", _P), ("kappa", _P), ("rho", _P), ("bc", ctypes.c_int32)]
+
+
+class HdgError(RuntimeError):
+    pass
+
+
+_LIBS: dict = {}
+
+
+def load_library(path: str | None = None) -> ctypes.CDLL:
+    path = path or LIB_PATH
+    if path in _LIBS:
+        return _LIBS[path]
+    if not os.path.exists(path):
+        raise HdgError(f"HIP library not built: {path} (run paper_1507_02557_amd.build)")
+    lib = ctypes.CDLL(path)
+    for name, res, args in _SIGS:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIBS[path] = lib
+    return lib
+
+
+def _ptr(t: torch.Tensor) -> int:
+    if not t.is_contiguous():
+        raise HdgError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+class Solver:
+    """One solver context (mesh, order N) on one device.
+
+    ``device`` is the torch device whose memory the library addresses; the
+    HIP library requires a CUDA (HIP) device.
+    """
+
+    def __init__(self, mesh, N: int, bc: int = BC_RIGID_WALL, precision: int = PREC_FP32,
+                 device: str | torch.device = "cuda", lib_path: str | None = None):
+        self.device = torch.device(device)
+        self._lib = load_library(lib_path)
+        if lib_path is None and (self.device.type != "cuda" or not torch.cuda.is_available()):
+            raise HdgError("the HIP library needs a GPU device; none is available")
+        self.N = N
+        xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float64)
+        et = np.ascontiguousarray(mesh.etype, dtype=np.int8)
+        ev = np.ascontiguousarray(mesh.everts, dtype=np.int64)
+        ka = np.ascontiguousarray(mesh.kappa, dtype=np.float64)
+        rh = np.ascontiguousarray(mesh.rho, dtype=np.float64)
+        m = HdgMesh(xyz.shape[0], xyz.ctypes.data, et.shape[0], et.ctypes.data, ev.ctypes.data,
+                    ka.ctypes.data, rh.ctypes.data, bc)
+        h = _P()
+        rc = self._lib.hdg_create(ctypes.byref(h), ctypes.byref(m), N, precision, self._stream())
+        if rc != 0:
+            raise HdgError(f"hdg_create failed ({rc}): {self._lib.hdg_last_error(None).decode()}")
+        self._h = h
+        self.n_elem = et.shape[0]
+        self.info = {}
+        for t in (HEX, WEDGE, PYR, TET):
+            K, Np, ns = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+            self._check(self._lib.hdg_type_info(h, t, ctypes.byref(K), ctypes.byref(Np), ctypes.byref(ns)))
+            self.info[t] = (K.value, Np.value, ns.value)
+        self.types = [t for t in (HEX, WEDGE, PYR, TET) if self.info[t][0] > 0]
+
+    def _stream(self):
+        if self.device.type == "cuda":
+            return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        return None
+
+    def _check(self, rc: int):
+        if rc != 0:
+            raise HdgError(f"hdg call failed ({rc}): {self._lib.hdg_last_error(self._h).decode()}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hdg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def dt(self, cfl: float = 0.5):
+        out = np.zeros(self.n_elem, dtype=np.float64)
+        mn = ctypes.c_double()
+        self._check(self._lib.hdg_dt(self._h, cfl, out.ctypes.data, ctypes.byref(mn)))
+        return out, mn.value
+
+    def points(self, t: int) -> torch.Tensor:
+        K, _, ns = self.info[t]
+        x = torch.empty((K, ns, 3), dtype=torch.float64, device=self.device)
+        self._check(self._lib.hdg_get_points(self._h, t, _ptr(x)))
+        return x
+
+    def project(self, t: int, fields):
+        f = [torch.as_tensor(v, dtype=torch.float64, device=self.device).contiguous() for v in fields]
+        self._check(self._lib.hdg_project(self._h, t, *[_ptr(v) for v in f]))
+        if self.device.type == "cuda":
+            torch.cuda.current_stream(self.device).synchronize()
+
+    def set_state(self, t: int, fields):
+        f = [torch.as_tensor(v, dtype=torch.float32, device=self.device).contiguous() for v in fields]
+        self._check(self._lib.hdg_set_state(self._h, t, *[_ptr(v) for v in f]))
+        if self.device.type == "cuda":
+            torch.cuda.current_stream(self.device).synchronize()
+
+    def get_field(self, t: int, which: int = 0):
+        K, Np, _ = self.info[t]
+        out = [torch.empty((K, Np), dtype=torch.float32, device=self.device) for _ in range(4)]
+        self._check(self._lib.hdg_get_field(self._h, which, t, *[_ptr(v) for v in out]))
+        return torch.stack(out, 1)  # (K, 4, Np)
+
+    def state(self):
+        return {t: self.get_field(t, 0) for t in self.types}
+
+    def rhs(self):
+        self._check(self._lib.hdg_rhs(self._h))
+        return {t: self.get_field(t, 1) for t in self.types}
+
+    def step(self, dt: float, n_steps: int = 1):
+        self._check(self._lib.hdg_step(self._h, float(dt), int(n_steps)))
+
+    def energy(self) -> float:
+        E = ctypes.c_double()
+        self._check(self._lib.hdg_energy(self._h, ctypes.byref(E)))
+        return E.value
+
+    def profile(self, on: bool):
+        self._check(self._lib.hdg_profile(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        ms = np.zeros(4, dtype=np.float64)
+        cnt = np.zeros(4, dtype=np.int64)
+        self._check(self._lib.hdg_profile_read(self._h, ms.ctypes.data, cnt.ctypes.data))
+        return ms, cnt
+
+    def project_function(self, func, time: float = 0.0):
+        """Sample func(x, y, z, t) -> (p, ux, uy, uz) at each type's points and project."""
+        for t in self.types:
+            x = self.points(t)
+            vals = func(x[..., 0], x[..., 1], x[..., 2], time)
+            self.project(t, [v.reshape(x.shape[0], -1) for v in vals])

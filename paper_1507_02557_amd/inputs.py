@@ -235,8 +235,15 @@ def four_slab_mesh(n: int, seed: int = 0, jitter: float = 0.1,
 
 
 # ---------------------------------------------------------------------------
-# Closed-form fields (kappa = rho = 1)
+# Closed-form fields (kappa = rho = 1); accept numpy arrays or torch tensors
 # ---------------------------------------------------------------------------
+
+def _xp(x):
+    if type(x).__module__.startswith("torch"):
+        import torch
+        return torch
+    return np
+
 
 def standing_mode_rigid(x, y, z, t):
     """Rigid-wall (u.n = 0) resonant mode of p_t + div u = 0, u_t + grad p = 0.
@@ -245,10 +252,11 @@ def standing_mode_rigid(x, y, z, t):
     u_x = sin(pi x) cos(pi y) cos(pi z) sin(sqrt(3) pi t) / sqrt(3), cyclic.
     Returns (p, ux, uy, uz).
     """
+    xp = _xp(x)
     pi = np.pi
     w = np.sqrt(3.0) * pi
-    cx, cy, cz = np.cos(pi * x), np.cos(pi * y), np.cos(pi * z)
-    sx, sy, sz = np.sin(pi * x), np.sin(pi * y), np.sin(pi * z)
+    cx, cy, cz = xp.cos(pi * x), xp.cos(pi * y), xp.cos(pi * z)
+    sx, sy, sz = xp.sin(pi * x), xp.sin(pi * y), xp.sin(pi * z)
     st = np.sin(w * t) / np.sqrt(3.0)
     return (cx * cy * cz * np.cos(w * t), sx * cy * cz * st, cx * sy * cz * st, cx * cy * sz * st)
 
@@ -260,10 +268,11 @@ def standing_mode_free(x, y, z, t):
     u_x = -cos(pi x) sin(pi y) sin(pi z) sin(sqrt(3) pi t) / sqrt(3), cyclic.
     Returns (p, ux, uy, uz).
     """
+    xp = _xp(x)
     pi = np.pi
     w = np.sqrt(3.0) * pi
-    cx, cy, cz = np.cos(pi * x), np.cos(pi * y), np.cos(pi * z)
-    sx, sy, sz = np.sin(pi * x), np.sin(pi * y), np.sin(pi * z)
+    cx, cy, cz = xp.cos(pi * x), xp.cos(pi * y), xp.cos(pi * z)
+    sx, sy, sz = xp.sin(pi * x), xp.sin(pi * y), xp.sin(pi * z)
     st = -np.sin(w * t) / np.sqrt(3.0)
     return (sx * sy * sz * np.cos(w * t), cx * sy * sz * st, sx * cy * sz * st, sx * sy * cz * st)
 
@@ -276,7 +285,8 @@ def pulse_centre(seed: int) -> np.ndarray:
 
 def gaussian_pulse(x, y, z, centre, width: float = 0.05):
     """p = exp(-|x - x0|^2 / (2 width^2)), u = 0.  Returns (p, ux, uy, uz)."""
-    r2 = (x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2
-    p = np.exp(-r2 / (2.0 * width * width))
-    zero = np.zeros_like(p)
-    return (p, zero, zero.copy(), zero.copy())
+    xp = _xp(x)
+    r2 = (x - float(centre[0])) ** 2 + (y - float(centre[1])) ** 2 + (z - float(centre[2])) ** 2
+    p = xp.exp(-r2 / (2.0 * width * width))
+    zero = xp.zeros_like(p)
+    return (p, zero, zero.clone() if xp is not np else zero.copy(), zero.clone() if xp is not np else zero.copy())

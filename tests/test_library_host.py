@@ -1,0 +1,91 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library must load, export every function include/hdg.h declares, and
+reject invalid arguments and invalid meshes before touching the device.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1507_02557_amd import hdg
+from paper_1507_02557_amd.inputs import Mesh, TET
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "hdg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hdg_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    lib = hdg.load_library()
+    declared = _header_functions()
+    assert declared, "no declarations parsed"
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(hdg.EXPORTS) == declared
+
+
+def _create(mesh, N=2, bc=1):
+    lib = hdg.load_library()
+    xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float64)
+    et = np.ascontiguousarray(mesh.etype, dtype=np.int8)
+    ev = np.ascontiguousarray(mesh.everts, dtype=np.int64)
+    ka = np.ascontiguousarray(mesh.kappa, dtype=np.float64)
+    rh = np.ascontiguousarray(mesh.rho, dtype=np.float64)
+    m = hdg.HdgMesh(xyz.shape[0], xyz.ctypes.data, et.shape[0], et.ctypes.data, ev.ctypes.data,
+                    ka.ctypes.data, rh.ctypes.data, bc)
+    h = ctypes.c_void_p()
+    rc = lib.hdg_create(ctypes.byref(h), ctypes.byref(m), N, 0, None)
+    return rc, h, lib.hdg_last_error(None).decode()
+
+
+def _tets(verts, xyz):
+    n = len(verts)
+    ev = -np.ones((n, 8), dtype=np.int64)
+    for i, v in enumerate(verts):
+        ev[i, :4] = v
+    return Mesh(xyz=np.asarray(xyz, dtype=np.float64), etype=np.full(n, TET, dtype=np.int8), everts=ev,
+                kappa=np.ones(n), rho=np.ones(n))
+
+
+XYZ = [[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [0, 0, -1], [1, 1, 1]]
+
+
+@pytest.mark.parametrize("N", [0, 6, 9])
+def test_create_rejects_unsupported_order(N):
+    rc, h, msg = _create(_tets([[0, 1, 2, 3]], XYZ), N=N)
+    assert rc == -1 and not h.value and "order" in msg
+
+
+def test_create_rejects_non_manifold_face():
+    # three tetrahedra sharing the face (0,1,2)
+    rc, h, msg = _create(_tets([[0, 1, 2, 3], [0, 2, 1, 4], [0, 1, 2, 5]], XYZ))
+    assert rc == -2 and not h.value and "more than two" in msg
+
+
+def test_create_rejects_bad_vertex_id():
+    rc, h, msg = _create(_tets([[0, 1, 2, 17]], XYZ))
+    assert rc == -1 and "vertex" in msg
+
+
+def test_create_rejects_bad_material_and_bc():
+    m = _tets([[0, 1, 2, 3]], XYZ)
+    m.rho[:] = 0.0
+    rc, _, msg = _create(m)
+    assert rc == -1 and "rho" in msg
+    rc, _, msg = _create(_tets([[0, 1, 2, 3]], XYZ), bc=7)
+    assert rc == -1 and "boundary" in msg
+
+
+def test_binding_fails_loudly_without_a_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(hdg.HdgError):
+        hdg.Solver(_tets([[0, 1, 2, 3]], XYZ), 2)
