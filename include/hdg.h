@@ -145,6 +145,26 @@ int hdg_rhs(hdg_ctx* ctx);
  * type and stage.  Asynchronous on the context's stream. */
 int hdg_step(hdg_ctx* ctx, double dt, int64_t n_steps);
 
+/* Multi-rate set-up (Section 2.4).  Levels l = 1 (coarsest) .. L = n_levels
+ * (1 <= L <= 8) with dtau_l = 2^(L-l) dtau_min, dtau_min the smallest local
+ * step of hdg_dt(cfl).  Each element takes the coarsest level whose step does
+ * not exceed its own stable step; then elements move to finer levels until
+ * face neighbours differ by at most one level.  Outputs (host, may be NULL):
+ * dt_min_out, level_counts_out [n_levels] (elements per level 1..L),
+ * level_out [n_elem] (level per element, mesh order). */
+int hdg_mrab_setup(hdg_ctx* ctx, int n_levels, double cfl, double* dt_min_out, int64_t* level_counts_out,
+                   int8_t* level_out);
+
+/* Advance by n_coarse multi-rate Adams-Bashforth-3 coarse steps (dtau_1 each;
+ * Section 2.4).  Per substep of dtau_min, the active levels evaluate their
+ * right-hand side (a coarser neighbour in mid-step supplies the AB3 dense
+ * output of its step at the half point) and take an AB3 step of their own
+ * dtau_l.  The first call after hdg_mrab_setup or a state change runs a
+ * start-up of two coarse steps of LSERK4 at dtau_min that fills the history.
+ * *t_advanced (host, may be NULL) receives the simulated time advanced.
+ * Errors: HDG_ESTATE if hdg_mrab_setup was not called. */
+int hdg_mrab_advance(hdg_ctx* ctx, int64_t n_coarse, double* t_advanced);
+
 /* Energy E = 1/2 sum_K (p^T M p / kappa + rho u^T M u) of the current state,
  * accumulated in FP64 on the device (synchronises the stream). */
 int hdg_energy(hdg_ctx* ctx, double* E);

@@ -53,6 +53,11 @@ struct TypeData {
   double* gpts = nullptr;      // pyramid geometry points [Np][3]
   double* Mhat = nullptr;      // tet reference mass
   std::vector<double> cJ, minJ, crk;
+  // multi-rate
+  int* elist = nullptr;        // elements sorted by level, finest first
+  int8_t* elevel = nullptr;    // level per element
+  float* H = nullptr;          // right-hand-side history [3][4][K][Np]
+  int64_t n_from[10] = {};     // number of elements with level >= l
 };
 
 }  // namespace
@@ -80,6 +85,16 @@ struct hdg_ctx {
   int* flag = nullptr;
   std::vector<void*> allocs;
   bool prof = false;
+  // host copies of the connectivity (multi-rate binning)
+  std::vector<int64_t> slot_elem_h;
+  std::vector<int> nbr_h;
+  std::vector<int> etype_h, eidx_h;
+  // multi-rate state
+  int L = 0;
+  double mr_dtmin = 0.0;
+  int8_t* slevel = nullptr;
+  int64_t hcount[10] = {};
+  bool mr_ready = false;
   std::vector<std::array<hipEvent_t, 2>> ev_pool;
   std::vector<int> ev_type;
   size_t ev_used = 0;
@@ -201,6 +216,7 @@ int ensure_traces(hdg_ctx* c) {
     if (!d.present) continue;
     StageArgs a{};
     a.K = d.K;
+    a.n_items = d.K;
     a.U = d.U;
     a.R = d.R;
     a.geo = d.geo;
@@ -246,6 +262,7 @@ int run_stage(hdg_ctx* c, int mode, float ra, float rb, float dt) {
     if (!d.present) continue;
     StageArgs a{};
     a.K = d.K;
+    a.n_items = d.K;
     a.U = d.U;
     a.R = d.R;
     a.geo = d.geo;
@@ -368,6 +385,10 @@ int create_impl(hdg_ctx* c, const hdg_mesh* m, int N) {
     taup_max[e] = std::max(taup_max[e], 1.0 / avg);
     tauu_max[e] = std::max(tauu_max[e], avg);
   }
+  c->slot_elem_h = slot_elem;
+  c->nbr_h = nbr;
+  c->etype_h = etype_local;
+  c->eidx_h = eidx;
   int rc;
   if ((rc = upload(c, &c->nbr, nbr))) return rc;
   if ((rc = upload(c, &c->ori, ori))) return rc;
@@ -614,6 +635,7 @@ int hdg_project(hdg_ctx* c, int t, const double* p, const double* ux, const doub
   }
   if (e != hipSuccess) return fail(c, HDG_EHIP, std::string("projection: ") + hipGetErrorString(e));
   c->traces_valid = false;
+  c->mr_ready = false;
   return HDG_OK;
 }
 
@@ -626,6 +648,7 @@ int hdg_set_state(hdg_ctx* c, int t, const float* p, const float* ux, const floa
   for (int f = 0; f < 4; ++f)
     HIPCHK(c, hipMemcpyAsync(d.U + f * n, src[f], n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
   c->traces_valid = false;
+  c->mr_ready = false;
   return HDG_OK;
 }
 
@@ -654,9 +677,207 @@ int hdg_step(hdg_ctx* c, double dt, int64_t n_steps) {
   if (!(dt > 0.0) || n_steps < 0) return fail(c, HDG_EINVAL, "dt must be positive and n_steps >= 0");
   int rc = ensure_traces(c);
   if (rc) return rc;
+  c->mr_ready = false;
   for (int64_t n = 0; n < n_steps; ++n)
     for (int s = 0; s < 5; ++s)
       if ((rc = run_stage(c, kModeStage, (float)kRkA[s], (float)kRkB[s], (float)dt))) return rc;
+  return HDG_OK;
+}
+
+// ---- multi-rate AB3 (Section 2.4) -----------------------------------------
+namespace {
+
+// AB3 dense-output weights beta_j(theta) for r_s, r_{s-1}, r_{s-2}: the
+// integral over [0, theta] of the quadratic through the last three
+// right-hand sides (unit step).
+void ab3_beta(double th, double b[3]) {
+  b[0] = th + 0.75 * th * th + th * th * th / 6.0;
+  b[1] = -(th * th + th * th * th / 3.0);
+  b[2] = 0.25 * th * th + th * th * th / 6.0;
+}
+
+// Lowest active level at substep k of a coarse step: level l is active when
+// k is a multiple of 2^(L-l).
+int lmin_of(int L, int k) {
+  for (int l = 1; l <= L; ++l)
+    if (k % (1 << (L - l)) == 0) return l;
+  return L;
+}
+
+StageArgs mr_args(hdg_ctx* c, TypeData& d, int lmin, int k, int dense) {
+  StageArgs a{};
+  a.K = d.K;
+  a.n_items = d.n_from[lmin];
+  a.elist = d.elist;
+  a.elevel = d.elevel;
+  a.slevel = c->slevel;
+  a.H = d.H;
+  a.tr_half = c->trace[1 - c->cur];
+  a.U = d.U;
+  a.R = d.R;
+  a.geo = d.geo;
+  a.mat = d.mat;
+  a.nbr = c->nbr;
+  a.ori = c->ori;
+  a.tau = c->tau;
+  a.fgeo = d.fgeo;
+  a.isqJ = d.isqJ;
+  a.tr_in = c->trace[c->cur];
+  a.tr_out = c->trace[c->cur];
+  a.slot0 = d.slot0;
+  a.ops = d.ops;
+  a.iops = d.iops;
+  a.mr.L = c->L;
+  a.mr.ksub = k;
+  a.mr.dense = dense;
+  double b1[3], bh[3];
+  ab3_beta(1.0, b1);
+  ab3_beta(0.5, bh);
+  for (int l = 1; l <= c->L; ++l) {
+    for (int j = 0; j < 3; ++j) {
+      a.mr.b1[l][j] = (float)b1[j];
+      a.mr.bh[l][j] = (float)bh[j];
+    }
+    a.mr.dtl[l] = (float)(std::ldexp(c->mr_dtmin, c->L - l));
+  }
+  return a;
+}
+
+// Right-hand sides of the active elements into their levels' history.
+int mr_rhs(hdg_ctx* c, int k, int dense) {
+  const int lmin = lmin_of(c->L, k);
+  for (int t = 0; t < 4; ++t) {
+    TypeData& d = c->td[t];
+    if (!d.present || d.n_from[lmin] == 0) continue;
+    StageArgs a = mr_args(c, d, lmin, k, dense);
+    a.mode = kModeRhsHist;
+    for (int l = lmin; l <= c->L; ++l) a.mr.hs[l][0] = (int)(c->hcount[l] % 3);
+    hipEvent_t stop;
+    int rc = prof_begin(c, t, &stop);
+    if (rc) return rc;
+    if (launch_stage(t, c->N, a, c->stream)) return fail(c, HDG_EINVAL, "no stage kernel for this order");
+    if (stop) HIPCHK(c, hipEventRecord(stop, c->stream));
+  }
+  for (int l = lmin; l <= c->L; ++l) c->hcount[l]++;
+  HIPCHK(c, hipGetLastError());
+  return HDG_OK;
+}
+
+// AB3 update of the active elements, their traces and mid-step traces.
+int mr_update(hdg_ctx* c, int k) {
+  const int lmin = lmin_of(c->L, k);
+  for (int t = 0; t < 4; ++t) {
+    TypeData& d = c->td[t];
+    if (!d.present || d.n_from[lmin] == 0) continue;
+    StageArgs a = mr_args(c, d, lmin, k, 0);
+    for (int l = lmin; l <= c->L; ++l)
+      for (int j = 0; j < 3; ++j) a.mr.hs[l][j] = (int)((c->hcount[l] - 1 - j + 3 * 1000) % 3);
+    hipEvent_t stop;
+    int rc = prof_begin(c, t, &stop);
+    if (rc) return rc;
+    if (launch_mrab_update(t, c->N, a, c->stream)) return fail(c, HDG_EINVAL, "no stage kernel for this order");
+    if (stop) HIPCHK(c, hipEventRecord(stop, c->stream));
+  }
+  HIPCHK(c, hipGetLastError());
+  return HDG_OK;
+}
+
+}  // namespace
+
+int hdg_mrab_setup(hdg_ctx* c, int n_levels, double cfl, double* dt_min_out, int64_t* level_counts_out,
+                   int8_t* level_out) {
+  if (!c) return HDG_EINVAL;
+  if (n_levels < 1 || n_levels > 8) return fail(c, HDG_EINVAL, "n_levels must be in [1, 8]");
+  std::vector<double> dte(c->n_elem);
+  double dtmin = 0.0;
+  int rc = hdg_dt(c, cfl, dte.data(), &dtmin);
+  if (rc) return rc;
+  const int L = n_levels;
+  std::vector<int> lev(c->n_elem);
+  for (int64_t e = 0; e < c->n_elem; ++e) {
+    int j = (int)std::floor(std::log2(dte[e] / dtmin * (1.0 + 1e-12)));
+    j = std::max(0, std::min(L - 1, j));
+    lev[e] = L - j;
+  }
+  // neighbours differ by at most one level: move coarser elements finer
+  for (;;) {
+    std::vector<int> nw(lev);
+    for (size_t s = 0; s < c->nbr_h.size(); ++s) {
+      if (c->nbr_h[s] < 0) continue;
+      const int64_t a = c->slot_elem_h[s], b = c->slot_elem_h[c->nbr_h[s]];
+      nw[a] = std::max(nw[a], lev[b] - 1);
+    }
+    if (nw == lev) break;
+    lev.swap(nw);
+  }
+  c->L = L;
+  c->mr_dtmin = dtmin;
+  std::vector<int8_t> slev(c->nslot);
+  for (int64_t s = 0; s < c->nslot; ++s) slev[s] = (int8_t)lev[c->slot_elem_h[s]];
+  if (!c->slevel && (rc = dalloc(c, &c->slevel, c->nslot))) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->slevel, slev.data(), c->nslot, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<int64_t> cnt(L + 1, 0);
+  for (int t = 0; t < 4; ++t) {
+    TypeData& d = c->td[t];
+    if (!d.present) continue;
+    std::vector<int> order(d.K);
+    std::vector<int8_t> el(d.K);
+    for (int64_t k = 0; k < d.K; ++k) {
+      order[k] = (int)k;
+      el[k] = (int8_t)lev[d.elems[k]];
+      cnt[el[k]]++;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return el[x] > el[y]; });
+    for (int l = 0; l <= 9; ++l) d.n_from[l] = 0;
+    for (int64_t k = 0; k < d.K; ++k)
+      for (int l = 1; l <= el[k]; ++l) d.n_from[l]++;
+    if (!d.elist && (rc = dalloc(c, &d.elist, d.K))) return rc;
+    if (!d.elevel && (rc = dalloc(c, &d.elevel, d.K))) return rc;
+    if (!d.H && (rc = dalloc(c, &d.H, (size_t)3 * 4 * d.K * d.Np))) return rc;
+    HIPCHK(c, hipMemcpyAsync(d.elist, order.data(), d.K * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d.elevel, el.data(), d.K, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(d.H, 0, (size_t)3 * 4 * d.K * d.Np * sizeof(float), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  if (dt_min_out) *dt_min_out = dtmin;
+  if (level_counts_out)
+    for (int l = 1; l <= L; ++l) level_counts_out[l - 1] = cnt[l];
+  if (level_out)
+    for (int64_t e = 0; e < c->n_elem; ++e) level_out[e] = (int8_t)lev[e];
+  c->mr_ready = false;
+  return HDG_OK;
+}
+
+int hdg_mrab_advance(hdg_ctx* c, int64_t n_coarse, double* t_advanced) {
+  if (!c) return HDG_EINVAL;
+  if (c->L < 1) return fail(c, HDG_ESTATE, "hdg_mrab_setup has not been called");
+  if (n_coarse < 0) return fail(c, HDG_EINVAL, "n_coarse must be >= 0");
+  int rc = ensure_traces(c);
+  if (rc) return rc;
+  const int L = c->L;
+  const int nsub = 1 << (L - 1);
+  double tadv = 0.0;
+  if (!c->mr_ready) {
+    // start-up: LSERK4 at dtau_min for two coarse steps, recording each
+    // level's right-hand side at the boundaries that are multiples of dtau_l
+    for (int l = 0; l <= 9; ++l) c->hcount[l] = 0;
+    for (int j = 0; j < 2 * nsub; ++j) {
+      if ((rc = mr_rhs(c, j % nsub, 0))) return rc;
+      for (int s = 0; s < 5; ++s)
+        if ((rc = run_stage(c, kModeStage, (float)kRkA[s], (float)kRkB[s], (float)c->mr_dtmin))) return rc;
+    }
+    tadv += 2.0 * nsub * c->mr_dtmin;
+    c->mr_ready = true;
+  }
+  for (int64_t n = 0; n < n_coarse; ++n) {
+    for (int k = 0; k < nsub; ++k) {
+      if ((rc = mr_rhs(c, k, 1))) return rc;
+      if ((rc = mr_update(c, k))) return rc;
+    }
+    tadv += nsub * c->mr_dtmin;
+  }
+  if (t_advanced) *t_advanced = tadv;
   return HDG_OK;
 }
 

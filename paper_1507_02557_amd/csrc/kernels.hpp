@@ -49,6 +49,8 @@ void launch_finite(int64_t n, const float* x, int* flag, hipStream_t s);
 // Fused stage kernel for one element type; returns 0 or -1 if (type, N) has
 // no instantiation.
 int launch_stage(int type, int N, const StageArgs& a, hipStream_t s);
+// Multi-rate AB3 update of the items of a (state, traces, mid-step traces).
+int launch_mrab_update(int type, int N, const StageArgs& a, hipStream_t s);
 // Packed operator table sizes of the stage kernel for (type, N).
 void stage_table_sizes(int type, int N, int* n_floats, int* n_ints);
 int stage_batch(int type, int N);

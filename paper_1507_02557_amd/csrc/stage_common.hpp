@@ -23,8 +23,26 @@
 
 namespace hdg {
 
+// Multi-rate (MRAB3) parameters of one launch, indexed by level 1..L.
+struct MrabParams {
+  int L;                 // number of levels (0: single rate)
+  int ksub;              // substep index within the coarse step
+  int dense;             // 1: read a coarser neighbour's mid-step trace when it is mid-step
+  int hs[9][3];          // history slot of r_s, r_{s-1}, r_{s-2} per level (rhs mode: [l][0] = new slot)
+  float b1[9][3];        // AB3 weights beta_j(1) per level (order-limited at start)
+  float bh[9][3];        // dense-output weights beta_j(1/2) per level
+  float dtl[9];          // dtau_l
+};
+
 struct StageArgs {
-  int64_t K;             // elements of this type
+  int64_t K;             // elements of this type (field stride)
+  int64_t n_items;       // elements processed by this launch
+  const int* elist;      // element of each item (NULL: item i is element i)
+  const int8_t* elevel;  // level per element (multi-rate)
+  const int8_t* slevel;  // level of each slot's element [nslot] (multi-rate)
+  float* H;              // right-hand-side history [3][4][K][Np] (multi-rate)
+  float4* tr_half;       // mid-step traces [nslot][Nfq] (multi-rate)
+  MrabParams mr;
   float* U;              // state [4][K][Np], fields p, ux, uy, uz
   float* R;              // LSERK residual (or rhs) [4][K][Np]
   const float* geo;      // per-type volume geometry
@@ -40,10 +58,23 @@ struct StageArgs {
   const float* ops;      // packed FP32 operator tables
   const int* iops;       // packed integer tables
   float a, b, dt;        // res = a res + dt rhs; U = U + b res
-  int mode;              // 0: full stage, 1: traces of U only, 2: rhs into R only
+  int mode;              // kModeStage, kModeTrace, kModeRhs or kModeRhsHist
 };
 
-enum { kModeStage = 0, kModeTrace = 1, kModeRhs = 2 };
+enum { kModeStage = 0, kModeTrace = 1, kModeRhs = 2, kModeRhsHist = 3 };
+
+// Element processed by item i, or -1 past the end of the launch.
+HD inline int64_t item(const StageArgs& a, int64_t i) {
+  if (i >= a.n_items) return -1;
+  return a.elist ? (int64_t)a.elist[i] : i;
+}
+
+// Where a right-hand side goes: the rhs buffer, or the history slot of the
+// element's level.
+HD inline float* rhs_dst(const StageArgs& a, int64_t e, int Np) {
+  if (a.mode == kModeRhsHist) return a.H + (int64_t)a.mr.hs[a.elevel[e]][0] * 4 * a.K * Np;
+  return a.R;
+}
 
 // Neighbour state on a boundary face (mirror principle):
 // rigid wall p+ = p-, u+ = u- - 2 (n.u-) n; free surface p+ = -p-, u+ = u-.
@@ -80,8 +111,64 @@ HD inline void upwind_flux(float4 m, float4 p, float4 g, float2 tau, bool skew, 
 HD inline void face_states(const StageArgs& a, int64_t slot, int nfq, int q, float4 g, float4& m, float4& p) {
   m = a.tr_in[slot * nfq + q];
   const int nb = a.nbr[slot];
-  if (nb >= 0) p = a.tr_in[(int64_t)nb * nfq + q];
-  else p = mirror_state(m, -nb - 1, g.x, g.y, g.z);
+  if (nb >= 0) {
+    const float4* src = a.tr_in;
+    if (a.mr.dense) {
+      // a coarser neighbour that is mid-step supplies its dense-output trace
+      const int ln = a.slevel[nb];
+      if (ln < a.slevel[slot] && (a.mr.ksub & ((1 << (a.mr.L - ln)) - 1)) != 0) src = a.tr_half;
+    }
+    p = src[(int64_t)nb * nfq + q];
+  } else {
+    p = mirror_state(m, -nb - 1, g.x, g.y, g.z);
+  }
 }
+
+// Multi-rate update of one batch, as a sequence of barrier-separated steps:
+// load the state; u_new = u + dtau_l sum_j beta_j(1) r_{s-j} (written to U);
+// traces of u_new into tr_out; u_half = u + dtau_l sum_j beta_j(1/2) r_{s-j};
+// traces of u_half into tr_half (the dense output at the middle of the step).
+template <class S>
+struct MrabUpdate {
+  static constexpr int T = S::nphase - S::kTraceBegin;
+  static constexpr int nstep = 3 + 2 * T;
+
+  HD static void combine(int tid, typename S::Smem& sm, const StageArgs& a, int64_t e0, bool half) {
+    constexpr int EPB = S::kEPB, Np = S::Np;
+    const int64_t K = a.K;
+    const int64_t hstr = 4 * K * Np;
+    for (int it = tid; it < 4 * EPB * Np; it += S::NT) {
+      const int c = it / (EPB * Np), r = it % (EPB * Np);
+      const int el = r / Np, i = r % Np;
+      const int64_t e = item(a, e0 + el);
+      if (e < 0) continue;
+      const int lv = a.elevel[e];
+      const float* w = half ? a.mr.bh[lv] : a.mr.b1[lv];
+      const int64_t gi = (int64_t)c * K * Np + e * Np + i;
+      const float acc = w[0] * a.H[a.mr.hs[lv][0] * hstr + gi] + w[1] * a.H[a.mr.hs[lv][1] * hstr + gi] +
+                        w[2] * a.H[a.mr.hs[lv][2] * hstr + gi];
+      const float un = sm.u[c][el][i] + a.mr.dtl[lv] * acc;
+      sm.un[c][el][i] = un;
+      if (!half) a.U[gi] = un;
+    }
+  }
+
+  HD static void step(int st, int tid, typename S::Smem& sm, const StageArgs& a, int64_t e0) {
+    StageArgs b = a;
+    b.mode = kModeStage;
+    if (st == 0) {
+      S::phase(0, tid, sm, a, e0);
+    } else if (st == 1) {
+      combine(tid, sm, a, e0, false);
+    } else if (st < 2 + T) {
+      S::phase(S::kTraceBegin + st - 2, tid, sm, b, e0);
+    } else if (st == 2 + T) {
+      combine(tid, sm, a, e0, true);
+    } else {
+      b.tr_out = a.tr_half;
+      S::phase(S::kTraceBegin + st - 3 - T, tid, sm, b, e0);
+    }
+  }
+};
 
 }  // namespace hdg

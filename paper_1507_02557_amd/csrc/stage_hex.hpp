@@ -23,6 +23,7 @@ struct HexStage {
   static constexpr int NT = 256;
   static constexpr int kEPB = EPB;
   static constexpr int nphase = 4;
+  static constexpr int kTraceBegin = 3;  // first phase that writes traces
   static constexpr int kOpsFloats = n1 * n1 + 2 * n1;
   static constexpr int kOpsInts = 8 * Nfq;
 
@@ -38,7 +39,7 @@ struct HexStage {
 
   HD static bool active(int ph, int mode) {
     if (mode == kModeTrace) return ph == 0 || ph == 3;
-    if (mode == kModeRhs) return ph <= 2;
+    if (mode == kModeRhs || mode == kModeRhsHist) return ph <= 2;
     return true;
   }
 
@@ -61,20 +62,21 @@ struct HexStage {
     if (ph == 0) {
       for (int it = tid; it < 4 * EPB * Np; it += NT) {
         const int f = it / (EPB * Np), r = it % (EPB * Np);
-        const int el = r / Np;
-        (&sm.u[0][0][0])[it] = (e0 + el < K) ? a.U[(int64_t)f * K * Np + e0 * Np + r] : 0.0f;
+        const int el = r / Np, i = r % Np;
+        const int64_t e = item(a, e0 + el);
+        (&sm.u[0][0][0])[it] = (e >= 0) ? a.U[(int64_t)f * K * Np + e * Np + i] : 0.0f;
       }
       for (int it = tid; it < EPB; it += NT) {
-        const int64_t e = e0 + it;
-        sm.mat[it][0] = e < K ? a.mat[e].x : 0.f;
-        sm.mat[it][1] = e < K ? a.mat[e].y : 0.f;
+        const int64_t e = item(a, e0 + it);
+        sm.mat[it][0] = e >= 0 ? a.mat[e].x : 0.f;
+        sm.mat[it][1] = e >= 0 ? a.mat[e].y : 0.f;
       }
     } else if (ph == 1) {
       for (int it = tid; it < EPB * 6 * Nfq; it += NT) {
         const int el = it / (6 * Nfq), rr = it % (6 * Nfq);
         const int f = rr / Nfq, q = rr % Nfq;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         const int64_t slot = a.slot0 + e * 6 + f;
         const float4 g = a.fgeo[(e * 6 + f) * Nfq + q];
         float4 m, p;
@@ -87,8 +89,8 @@ struct HexStage {
     } else if (ph == 2) {
       for (int it = tid; it < EPB * Np; it += NT) {
         const int el = it / Np, node = it % Np;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         const int i = node % n1, j = (node / n1) % n1, k = node / (n1 * n1);
         float du[4][3];
         for (int c = 0; c < 4; ++c) {
@@ -123,8 +125,8 @@ struct HexStage {
         const int64_t base = e * Np + node;
         for (int c = 0; c < 4; ++c) {
           const int64_t gi = (int64_t)c * K * Np + base;
-          if (a.mode == kModeRhs) {
-            a.R[gi] = rhs[c];
+          if (a.mode == kModeRhs || a.mode == kModeRhsHist) {
+            rhs_dst(a, e, Np)[gi] = rhs[c];
           } else {
             const float res = a.a * a.R[gi] + a.dt * rhs[c];
             const float un = sm.u[c][el][node] + a.b * res;
@@ -139,8 +141,8 @@ struct HexStage {
       for (int it = tid; it < EPB * 6 * Nfq; it += NT) {
         const int el = it / (6 * Nfq), rr = it % (6 * Nfq);
         const int f = rr / Nfq, q = rr % Nfq;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         const int64_t slot = a.slot0 + e * 6 + f;
         const int l = sm.qperm[a.ori[slot]][q];
         const int l1 = l % n1, l2 = l / n1;

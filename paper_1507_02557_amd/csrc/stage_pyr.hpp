@@ -23,6 +23,7 @@ struct PyrStage {
   static constexpr int NT = 256;
   static constexpr int kEPB = EPB;
   static constexpr int nphase = 7;
+  static constexpr int kTraceBegin = 5;  // first phase that writes traces
   static constexpr bool kDInLds = (3 * Np * Np * 4) <= 48 * 1024;
   static constexpr int kOpsFloats = 3 * Np * Np + Nfq * Np + 4 * Nfn * Np + Nfq * Nfn;
   static constexpr int kOpsInts = 8 * Nfq + 6 * Nfn;
@@ -47,7 +48,7 @@ struct PyrStage {
 
   HD static bool active(int ph, int mode) {
     if (mode == kModeTrace) return ph == 0 || ph >= 5;
-    if (mode == kModeRhs) return ph <= 4;
+    if (mode == kModeRhs || mode == kModeRhsHist) return ph <= 4;
     return true;
   }
 
@@ -72,24 +73,25 @@ struct PyrStage {
     if (ph == 0) {
       for (int it = tid; it < 4 * EPB * Np; it += NT) {
         const int f = it / (EPB * Np), r = it % (EPB * Np);
-        const int el = r / Np;
-        (&sm.u[0][0][0])[it] = (e0 + el < K) ? a.U[(int64_t)f * K * Np + e0 * Np + r] : 0.0f;
+        const int el = r / Np, i = r % Np;
+        const int64_t e = item(a, e0 + el);
+        (&sm.u[0][0][0])[it] = (e >= 0) ? a.U[(int64_t)f * K * Np + e * Np + i] : 0.0f;
       }
       for (int it = tid; it < EPB * Np; it += NT) {
         const int el = it / Np, i = it % Np;
-        const int64_t e = e0 + el;
-        sm.J[el][i] = e < K ? a.geo[(e * 10 + 9) * Np + i] : 1.0f;
+        const int64_t e = item(a, e0 + el);
+        sm.J[el][i] = e >= 0 ? a.geo[(e * 10 + 9) * Np + i] : 1.0f;
       }
       for (int it = tid; it < EPB; it += NT) {
-        const int64_t e = e0 + it;
-        sm.mat[it][0] = e < K ? a.mat[e].x : 0.f;
-        sm.mat[it][1] = e < K ? a.mat[e].y : 0.f;
+        const int64_t e = item(a, e0 + it);
+        sm.mat[it][0] = e >= 0 ? a.mat[e].x : 0.f;
+        sm.mat[it][1] = e >= 0 ? a.mat[e].y : 0.f;
       }
     } else if (ph == 1) {
       for (int it = tid; it < EPB * Np; it += NT) {
         const int el = it / Np, i = it % Np;
-        const int64_t e = e0 + el;
-        if (e >= K) {
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) {
           for (int r = 0; r < 3; ++r) sm.ur[r][el][i] = 0.f;
           continue;
         }
@@ -101,8 +103,8 @@ struct PyrStage {
       for (int it = tid; it < EPB * 5 * Nfq; it += NT) {
         const int el = it / (5 * Nfq), rr = it % (5 * Nfq);
         const int f = rr / Nfq, q = rr % Nfq;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         const int64_t slot = a.slot0 + e * 5 + f;
         const float4 g = a.fgeo[(e * 5 + f) * Nfq + q];
         float4 m, p;
@@ -116,8 +118,8 @@ struct PyrStage {
       for (int it = tid; it < EPB * 4 * Nfn; it += NT) {
         const int el = it / (4 * Nfn), rr = it % (4 * Nfn);
         const int tf = rr / Nfn, m = rr % Nfn;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         const int o = a.ori[a.slot0 + e * 5 + 1 + tf];
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int q = 0; q < Nfq; ++q) {
@@ -130,7 +132,7 @@ struct PyrStage {
     } else if (ph == 3) {
       for (int it = tid; it < EPB * Np; it += NT) {
         const int el = it / Np, i = it % Np;
-        if (e0 + el >= K) continue;
+        if (item(a, e0 + el) < 0) continue;
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int l = 0; l < Nfq; ++l) {
           const float w = sm.Fq[l][i];
@@ -146,8 +148,8 @@ struct PyrStage {
     } else if (ph == 4) {
       for (int it = tid; it < EPB * Np; it += NT) {
         const int el = it / Np, i = it % Np;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         float Dp[3] = {0.f, 0.f, 0.f}, volp = 0.f;
         for (int j = 0; j < Np; ++j) {
           const float pj = sm.u[0][el][j];
@@ -169,8 +171,8 @@ struct PyrStage {
         const int64_t base = e * Np + i;
         for (int c = 0; c < 4; ++c) {
           const int64_t gi = (int64_t)c * K * Np + base;
-          if (a.mode == kModeRhs) {
-            a.R[gi] = rhs[c];
+          if (a.mode == kModeRhs || a.mode == kModeRhsHist) {
+            rhs_dst(a, e, Np)[gi] = rhs[c];
           } else {
             const float res = a.a * a.R[gi] + a.dt * rhs[c];
             const float un = sm.u[c][el][i] + a.b * res;
@@ -185,8 +187,8 @@ struct PyrStage {
       const float(*src)[EPB][Np] = (a.mode == kModeTrace) ? sm.u : sm.un;
       for (int it = tid; it < EPB * Nfq; it += NT) {
         const int el = it / Nfq, q = it % Nfq;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         const int64_t slot = a.slot0 + e * 5;
         const int l = sm.qperm[a.ori[slot]][q];
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
@@ -210,8 +212,8 @@ struct PyrStage {
       for (int it = tid; it < EPB * 4 * Nfq; it += NT) {
         const int el = it / (4 * Nfq), rr = it % (4 * Nfq);
         const int tf = rr / Nfq, q = rr % Nfq;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         const int64_t slot = a.slot0 + e * 5 + 1 + tf;
         const int o = a.ori[slot];
         float acc[4] = {0.f, 0.f, 0.f, 0.f};

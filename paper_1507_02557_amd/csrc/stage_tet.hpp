@@ -25,6 +25,7 @@ struct TetStage {
   static constexpr int NT = 256;
   static constexpr int kEPB = EPB;
   static constexpr int nphase = 6;
+  static constexpr int kTraceBegin = 5;  // first phase that writes traces
   // packed table sizes
   static constexpr int kOpsFloats = 4 * Np * Np + Nfq * Nfn + Nfq;
   static constexpr int kOpsInts = 4 * Nfn + 6 * Nfn + 4 * Np;
@@ -48,7 +49,7 @@ struct TetStage {
 
   HD static bool active(int ph, int mode) {
     if (mode == kModeTrace) return ph == 0 || ph == 5;
-    if (mode == kModeRhs) return ph <= 4;
+    if (mode == kModeRhs || mode == kModeRhsHist) return ph <= 4;
     return true;
   }
 
@@ -74,14 +75,14 @@ struct TetStage {
       for (int it = tid; it < 4 * EPB * Np; it += NT) {
         const int f = it / (EPB * Np), r = it % (EPB * Np);
         const int el = r / Np, i = r % Np;
-        (&sm.u[0][0][0])[it] = (e0 + el < K) ? a.U[(int64_t)f * K * Np + e0 * Np + r] : 0.0f;
-        (void)i;
+        const int64_t e = item(a, e0 + el);
+        (&sm.u[0][0][0])[it] = (e >= 0) ? a.U[(int64_t)f * K * Np + e * Np + i] : 0.0f;
       }
       for (int it = tid; it < EPB * 12; it += NT) {
         const int el = it / 12, c = it % 12;
-        const int64_t e = e0 + el;
+        const int64_t e = item(a, e0 + el);
         float v = 0.0f;
-        if (e < K) v = (c < 10) ? a.geo[e * 12 + c] : (c == 10 ? a.mat[e].x : a.mat[e].y);
+        if (e >= 0) v = (c < 10) ? a.geo[e * 12 + c] : (c == 10 ? a.mat[e].x : a.mat[e].y);
         sm.geo[el][c] = v;
       }
     } else if (ph == 1) {
@@ -94,9 +95,9 @@ struct TetStage {
       for (int it = tid; it < EPB * 4 * Nfq; it += NT) {
         const int el = it / (4 * Nfq), rr = it % (4 * Nfq);
         const int f = rr / Nfq, q = rr % Nfq;
-        const int64_t e = e0 + el;
+        const int64_t e = item(a, e0 + el);
         float out[4] = {0.f, 0.f, 0.f, 0.f};
-        if (e < K) {
+        if (e >= 0) {
           const int64_t slot = a.slot0 + e * 4 + f;
           float4 g = a.fgeo[e * 4 + f];
           g.w *= sm.w[q];
@@ -110,8 +111,8 @@ struct TetStage {
       for (int it = tid; it < EPB * 4 * Nfn; it += NT) {
         const int el = it / (4 * Nfn), rr = it % (4 * Nfn);
         const int f = rr / Nfn, m = rr % Nfn;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         const int o = a.ori[a.slot0 + e * 4 + f];
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int q = 0; q < Nfq; ++q) {
@@ -135,8 +136,8 @@ struct TetStage {
     } else if (ph == 4) {
       for (int it = tid; it < EPB * Np; it += NT) {
         const int el = it / Np, i = it % Np;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         float dp[3] = {0.f, 0.f, 0.f}, div = 0.f, lift[4] = {0.f, 0.f, 0.f, 0.f};
         for (int j = 0; j < Np; ++j) {
           const float pj = sm.u[0][el][j];
@@ -157,8 +158,8 @@ struct TetStage {
         const int64_t base = e * Np + i;
         for (int c = 0; c < 4; ++c) {
           const int64_t gi = (int64_t)c * K * Np + base;
-          if (a.mode == kModeRhs) {
-            a.R[gi] = rhs[c];
+          if (a.mode == kModeRhs || a.mode == kModeRhsHist) {
+            rhs_dst(a, e, Np)[gi] = rhs[c];
           } else {
             const float res = a.a * a.R[gi] + a.dt * rhs[c];
             const float un = sm.u[c][el][i] + a.b * res;
@@ -173,8 +174,8 @@ struct TetStage {
       for (int it = tid; it < EPB * 4 * Nfq; it += NT) {
         const int el = it / (4 * Nfq), rr = it % (4 * Nfq);
         const int f = rr / Nfq, q = rr % Nfq;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         const int64_t slot = a.slot0 + e * 4 + f;
         const int o = a.ori[slot];
         float acc[4] = {0.f, 0.f, 0.f, 0.f};

@@ -30,6 +30,7 @@ struct WedgeStage {
   static constexpr int NT = 256;
   static constexpr int kEPB = EPB;
   static constexpr int nphase = 7;
+  static constexpr int kTraceBegin = 5;  // first phase that writes traces
   // ops: Pt, Ptr, Ptt [Nct][Ntri]; tri_w [Nct]; P1, dP1 [n1][n1]; w1 [n1];
   //      P1f [2][n1]; Ftri [Nfn][Ntri]; Fedge [3][n1][Ntri]; Ican [Nfq][Nfn]
   static constexpr int oPt = 0, oPtr = oPt + Nct * Ntri, oPtt = oPtr + Nct * Ntri, oTw = oPtt + Nct * Ntri;
@@ -55,7 +56,7 @@ struct WedgeStage {
 
   HD static bool active(int ph, int mode) {
     if (mode == kModeTrace) return ph == 0 || ph >= 5;
-    if (mode == kModeRhs) return ph <= 4;
+    if (mode == kModeRhs || mode == kModeRhsHist) return ph <= 4;
     return true;
   }
 
@@ -82,13 +83,14 @@ struct WedgeStage {
     if (ph == 0) {
       for (int it = tid; it < 4 * EPB * Np; it += NT) {
         const int f = it / (EPB * Np), r = it % (EPB * Np);
-        const int el = r / Np;
-        (&sm.u[0][0][0])[it] = (e0 + el < K) ? a.U[(int64_t)f * K * Np + e0 * Np + r] : 0.0f;
+        const int el = r / Np, i = r % Np;
+        const int64_t e = item(a, e0 + el);
+        (&sm.u[0][0][0])[it] = (e >= 0) ? a.U[(int64_t)f * K * Np + e * Np + i] : 0.0f;
       }
       for (int it = tid; it < EPB; it += NT) {
-        const int64_t e = e0 + it;
-        sm.mat[it][0] = e < K ? a.mat[e].x : 0.f;
-        sm.mat[it][1] = e < K ? a.mat[e].y : 0.f;
+        const int64_t e = item(a, e0 + it);
+        sm.mat[it][0] = e >= 0 ? a.mat[e].x : 0.f;
+        sm.mat[it][1] = e >= 0 ? a.mat[e].y : 0.f;
       }
     } else if (ph == 1) {
       for (int it = tid; it < EPB * 5 * n1 * Ntri; it += NT) {
@@ -104,8 +106,8 @@ struct WedgeStage {
       for (int it = tid; it < EPB * 5 * Nfq; it += NT) {
         const int el = it / (5 * Nfq), rr = it % (5 * Nfq);
         const int f = rr / Nfq, q = rr % Nfq;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         const int64_t slot = a.slot0 + e * 5 + f;
         const float4 g = a.fgeo[(e * 5 + f) * Nfq + q];
         float4 m, p;
@@ -120,8 +122,8 @@ struct WedgeStage {
       for (int it = tid; it < EPB * Nq; it += NT) {
         const int el = it / Nq, q = it % Nq;
         const int qs = q / Nct, qt = q % Nct;
-        const int64_t e = e0 + el;
-        if (e >= K) {
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) {
           for (int k = 0; k < 7; ++k) sm.B[k][el][q] = 0.f;
           continue;
         }
@@ -150,8 +152,8 @@ struct WedgeStage {
       for (int it = tid; it < EPB * 2 * Nfn; it += NT) {
         const int el = it / (2 * Nfn), rr = it % (2 * Nfn);
         const int tf = rr / Nfn, m = rr % Nfn;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         const int o = a.ori[a.slot0 + e * 5 + tf];
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int q = 0; q < Nfq; ++q) {
@@ -206,8 +208,8 @@ struct WedgeStage {
       for (int it = tid; it < EPB * Np; it += NT) {
         const int el = it / Np, m = it % Np;
         const int js = m / Ntri, jt = m % Ntri;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         float vp = 0.f, vu[3] = {0.f, 0.f, 0.f};
         for (int qs = 0; qs < n1; ++qs) {
           const float p1 = P1[qs * n1 + js];
@@ -221,8 +223,8 @@ struct WedgeStage {
         const int64_t base = e * Np + m;
         for (int c = 0; c < 4; ++c) {
           const int64_t gi = (int64_t)c * K * Np + base;
-          if (a.mode == kModeRhs) {
-            a.R[gi] = rhs[c];
+          if (a.mode == kModeRhs || a.mode == kModeRhsHist) {
+            rhs_dst(a, e, Np)[gi] = rhs[c];
           } else {
             const float res = a.a * a.R[gi] + a.dt * rhs[c];
             const float un = sm.u[c][el][m] + a.b * res;
@@ -250,8 +252,8 @@ struct WedgeStage {
       for (int it = tid; it < EPB * 3 * Nfq; it += NT) {
         const int el = it / (3 * Nfq), rr = it % (3 * Nfq);
         const int ef = rr / Nfq, q = rr % Nfq;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         const int f = 2 + ef;
         const int64_t slot = a.slot0 + e * 5 + f;
         const int l = sm.qperm[a.ori[slot]][q];
@@ -271,8 +273,8 @@ struct WedgeStage {
       for (int it = tid; it < EPB * 2 * Nfq; it += NT) {
         const int el = it / (2 * Nfq), rr = it % (2 * Nfq);
         const int tf = rr / Nfq, q = rr % Nfq;
-        const int64_t e = e0 + el;
-        if (e >= K) continue;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
         const int64_t slot = a.slot0 + e * 5 + tf;
         const int o = a.ori[slot];
         float acc[4] = {0.f, 0.f, 0.f, 0.f};

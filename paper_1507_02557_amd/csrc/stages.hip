@@ -17,7 +17,7 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   S::load_ops(threadIdx.x, sm, a);
   __syncthreads();
   constexpr int EPB = S::kEPB;
-  const int64_t nb = (a.K + EPB - 1) / EPB;
+  const int64_t nb = (a.n_items + EPB - 1) / EPB;
   for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
     for (int ph = 0; ph < S::nphase; ++ph) {
       if (!S::active(ph, a.mode)) continue;
@@ -28,12 +28,28 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
 }
 
 template <class S>
-static int go(const StageArgs& a, hipStream_t s) {
+__global__ __launch_bounds__(256) void mrab_update_kernel(StageArgs a) {
+  __shared__ typename S::Smem sm;
+  S::load_ops(threadIdx.x, sm, a);
+  __syncthreads();
+  constexpr int EPB = S::kEPB;
+  const int64_t nb = (a.n_items + EPB - 1) / EPB;
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    for (int st = 0; st < MrabUpdate<S>::nstep; ++st) {
+      MrabUpdate<S>::step(st, threadIdx.x, sm, a, b * EPB);
+      __syncthreads();
+    }
+  }
+}
+
+template <class S>
+static int go(const StageArgs& a, hipStream_t s, bool mrab) {
   static_assert(sizeof(typename S::Smem) <= 160 * 1024, "LDS budget exceeded");
-  if (a.K == 0) return 0;
-  const int64_t nb = (a.K + S::kEPB - 1) / S::kEPB;
+  if (a.n_items == 0) return 0;
+  const int64_t nb = (a.n_items + S::kEPB - 1) / S::kEPB;
   const unsigned grid = (unsigned)(nb < 2048 ? nb : 2048);
-  hipLaunchKernelGGL(stage_kernel<S>, dim3(grid), dim3(S::NT), 0, s, a);
+  if (mrab) hipLaunchKernelGGL(mrab_update_kernel<S>, dim3(grid), dim3(S::NT), 0, s, a);
+  else hipLaunchKernelGGL(stage_kernel<S>, dim3(grid), dim3(S::NT), 0, s, a);
   return 0;
 }
 
@@ -44,12 +60,12 @@ static void sizes(int* nf, int* ni) {
 }
 
 template <int N>
-static int launch_n(int type, const StageArgs& a, hipStream_t s) {
+static int launch_n(int type, const StageArgs& a, hipStream_t s, bool mrab) {
   switch (type) {
-    case 0: return go<HexStage<N, epb(0, N)>>(a, s);
-    case 1: return go<WedgeStage<N, epb(1, N)>>(a, s);
-    case 2: return go<PyrStage<N, epb(2, N)>>(a, s);
-    case 3: return go<TetStage<N, epb(3, N)>>(a, s);
+    case 0: return go<HexStage<N, epb(0, N)>>(a, s, mrab);
+    case 1: return go<WedgeStage<N, epb(1, N)>>(a, s, mrab);
+    case 2: return go<PyrStage<N, epb(2, N)>>(a, s, mrab);
+    case 3: return go<TetStage<N, epb(3, N)>>(a, s, mrab);
   }
   return -1;
 }
@@ -64,16 +80,20 @@ static void sizes_n(int type, int* nf, int* ni) {
   }
 }
 
-int launch_stage(int type, int N, const StageArgs& a, hipStream_t s) {
+static int launch_any(int type, int N, const StageArgs& a, hipStream_t s, bool mrab) {
   switch (N) {
-    case 1: return launch_n<1>(type, a, s);
-    case 2: return launch_n<2>(type, a, s);
-    case 3: return launch_n<3>(type, a, s);
-    case 4: return launch_n<4>(type, a, s);
-    case 5: return launch_n<5>(type, a, s);
+    case 1: return launch_n<1>(type, a, s, mrab);
+    case 2: return launch_n<2>(type, a, s, mrab);
+    case 3: return launch_n<3>(type, a, s, mrab);
+    case 4: return launch_n<4>(type, a, s, mrab);
+    case 5: return launch_n<5>(type, a, s, mrab);
   }
   return -1;
 }
+
+int launch_stage(int type, int N, const StageArgs& a, hipStream_t s) { return launch_any(type, N, a, s, false); }
+
+int launch_mrab_update(int type, int N, const StageArgs& a, hipStream_t s) { return launch_any(type, N, a, s, true); }
 
 void stage_table_sizes(int type, int N, int* nf, int* ni) {
   switch (N) {

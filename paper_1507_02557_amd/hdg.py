@@ -36,6 +36,8 @@ _SIGS = [
     ("hdg_rhs", ctypes.c_int, [_P]),
     ("hdg_step", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int64]),
     ("hdg_energy", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    ("hdg_mrab_setup", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _P, _P]),
+    ("hdg_mrab_advance", ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     ("hdg_profile", ctypes.c_int, [_P, ctypes.c_int]),
     ("hdg_profile_read", ctypes.c_int, [_P, _P, _P]),
 ]
@@ -174,6 +176,20 @@ class Solver:
         E = ctypes.c_double()
         self._check(self._lib.hdg_energy(self._h, ctypes.byref(E)))
         return E.value
+
+    def mrab_setup(self, n_levels: int, cfl: float = 0.5):
+        """Multi-rate levels; returns (dt_min, elements per level, level per element)."""
+        mn = ctypes.c_double()
+        cnt = np.zeros(n_levels, dtype=np.int64)
+        lev = np.zeros(self.n_elem, dtype=np.int8)
+        self._check(self._lib.hdg_mrab_setup(self._h, n_levels, cfl, ctypes.byref(mn), cnt.ctypes.data,
+                                             lev.ctypes.data))
+        return mn.value, cnt, lev
+
+    def mrab_advance(self, n_coarse: int) -> float:
+        t = ctypes.c_double()
+        self._check(self._lib.hdg_mrab_advance(self._h, int(n_coarse), ctypes.byref(t)))
+        return t.value
 
     def profile(self, on: bool):
         self._check(self._lib.hdg_profile(self._h, 1 if on else 0))

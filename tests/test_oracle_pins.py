@@ -320,3 +320,56 @@ def test_convergence_rate_unjittered(N):
         errs.append(d.l2_error(U, standing_mode_free, T))
     rate = np.log2(errs[0] / errs[1])
     assert rate > N + 0.5, (N, errs, rate)
+
+
+# --- multi-rate AB3 (Section 2.4) --------------------------------------------
+def test_ab3_dense_output_weights():
+    """beta(1) are the AB3 weights (23, -16, 5)/12; the dense output integrates a
+    quadratic-in-time right-hand side exactly for every theta."""
+    from oracle.mrab import ab3_beta
+    assert np.allclose(ab3_beta(1.0), np.array([23.0, -16.0, 5.0]) / 12.0, rtol=0, atol=1e-15)
+    assert np.allclose(ab3_beta(0.5), np.array([17.0, -7.0, 2.0]) / 24.0, rtol=0, atol=1e-15)
+    a, b, c = 0.3, -1.1, 2.5
+    f = lambda t: a + b * t + c * t * t
+    for theta in (0.25, 0.5, 0.8, 1.0):
+        exact = a * theta + b * theta ** 2 / 2 + c * theta ** 3 / 3
+        beta = ab3_beta(theta)
+        assert abs(beta @ np.array([f(0.0), f(-1.0), f(-2.0)]) - exact) < 1e-14
+
+
+def test_mrab_levels_are_stable_and_smooth():
+    from oracle.mrab import bin_levels
+    d = Disc(four_slab_mesh(4, seed=0, jitter=0.1), 2)
+    L = 3
+    lev, dtmin = bin_levels(d, L)
+    dte = d.dt_elements(0.5)
+    ne = sum(d.els[t].size for t in d.types)
+    g = np.zeros(ne, dtype=np.int64)
+    for t in d.types:
+        g[d.els[t]] = lev[t]
+        assert np.all((2.0 ** (L - lev[t])) * dtmin <= dte[t] * (1 + 1e-12))
+    inner = d.nbr >= 0
+    assert np.all(np.abs(g[d.slot_elem[inner]] - g[d.slot_elem[d.nbr[inner]]]) <= 1)
+    assert len(set(g.tolist())) > 1  # the mesh really is multi-rate
+
+
+def test_mrab_third_order_in_time():
+    """Multi-rate AB3 against a fine-step LSERK4 solution of the same semi-discrete
+    system: halving the step cuts the error by about 2^3."""
+    from oracle.mrab import MRAB3
+    d = Disc(four_slab_mesh(4, seed=0, jitter=0.1), 1)
+    errs = []
+    T = None
+    for cfl in (0.2, 0.1):
+        mr = MRAB3(d, 3, cfl)
+        U = mr.startup(d.project(standing_mode_rigid))
+        ncoarse = int(round(6 * 0.2 / cfl))
+        for _ in range(ncoarse):
+            U = mr.coarse_step(U)
+        Ur = d.project(standing_mode_rigid)
+        ns = int(np.ceil(mr.t / d.dt_min(0.02)))
+        for _ in range(ns):
+            Ur = lserk4_step(d, Ur, mr.t / ns)
+        D = {t: U[t] - Ur[t] for t in d.types}
+        errs.append(np.sqrt(d.inner(D, D)))
+    assert errs[0] / errs[1] > 6.0, errs
