@@ -29,8 +29,23 @@ struct GeoTables {
   int quad_P[8][4];
 };
 
+// Vertices of element e (nv of them, Vall = [K][nv][3]) into registers.  Every
+// index is a compile-time constant so the array never lives in scratch
+// memory; entries past nv are zero.
+HD __forceinline__ void load_verts(const double* Vall, int64_t e, int nv, double V[8][3]) {
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int vv = v < nv ? v : 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double x = Vall[(e * nv + vv) * 3 + d];
+      V[v][d] = v < nv ? x : 0.0;
+    }
+  }
+}
+
 // Vertex map of a type at reference point X: physical x and F[d][r] = dx_d/dxi_r.
-HD inline void vmap(int type, const double (*V)[3], const double* X, double* x, double F[3][3]) {
+HD __forceinline__ void vmap(int type, const double (*V)[3], const double* X, double* x, double F[3][3]) {
   const double r = X[0], s = X[1], t = X[2];
   for (int d = 0; d < 3; ++d) {
     x[d] = 0.0;
@@ -95,13 +110,13 @@ HD inline void vmap(int type, const double (*V)[3], const double* X, double* x, 
   }
 }
 
-HD inline double det3(const double F[3][3]) {
+HD __forceinline__ double det3(const double F[3][3]) {
   return F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
          F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
 }
 
 // G = F^{-1}: G[r][d] = dxi_r / dx_d
-HD inline double inv3(const double F[3][3], double G[3][3]) {
+HD __forceinline__ double inv3(const double F[3][3], double G[3][3]) {
   const double J = det3(F);
   const double iJ = 1.0 / J;
   G[0][0] = (F[1][1] * F[2][2] - F[1][2] * F[2][1]) * iJ;
@@ -118,7 +133,7 @@ HD inline double inv3(const double F[3][3], double G[3][3]) {
 
 // Physical gradient of J for a wedge at X: grad_rst J = J tr(G dF/dxi_m),
 // dF/dxi_m from the (constant) second derivatives of the wedge shape functions.
-HD inline void wedge_gradJ(const double (*V)[3], const double* X, double gJ[3]) {
+HD __forceinline__ void wedge_gradJ(const double (*V)[3], const double* X, double gJ[3]) {
   double x[3], F[3][3], G[3][3];
   vmap(1, V, X, x, F);
   const double J = inv3(F, G);
@@ -151,20 +166,24 @@ HD inline void wedge_gradJ(const double (*V)[3], const double* X, double gJ[3]) 
 
 // Canonical face point q of face f (orientation code o) of an element of the
 // given type: reference coordinates Xr, physical point xq, tangent cross
-// product cr (not normalised, canonical frame orientation).
-HD inline void face_point(const GeoTables& T, int type, const double (*V)[3], int f, int o, int q, double* Xr,
+// product cr (not normalised, canonical frame orientation).  Ve points to the
+// element's vertices in global memory ([nv][3]); the face's vertices are read
+// from there by runtime index.
+HD __forceinline__ void face_point(const GeoTables& T, int type, const double* Ve, int f, int o, int q, double* Xr,
                           double* xq, double* cr) {
   const int nv = T.fnv[type][f];
   const int* P = nv == 3 ? T.tri_P[o] : T.quad_P[o];
   const double e1 = nv == 3 ? T.tri_eta[q][0] : T.quad_eta[q][0];
   const double e2 = nv == 3 ? T.tri_eta[q][1] : T.quad_eta[q][1];
+  // shape functions of the canonical frame (triangle: barycentric, 4th = 0)
   double S[4], d1[4], d2[4];
   if (nv == 3) {
-    S[0] = -0.5 * (e1 + e2); S[1] = 0.5 * (1 + e1); S[2] = 0.5 * (1 + e2);
-    d1[0] = -0.5; d1[1] = 0.5; d1[2] = 0.0;
-    d2[0] = -0.5; d2[1] = 0.0; d2[2] = 0.5;
+    S[0] = -0.5 * (e1 + e2); S[1] = 0.5 * (1 + e1); S[2] = 0.5 * (1 + e2); S[3] = 0.0;
+    d1[0] = -0.5; d1[1] = 0.5; d1[2] = 0.0; d1[3] = 0.0;
+    d2[0] = -0.5; d2[1] = 0.0; d2[2] = 0.5; d2[3] = 0.0;
   } else {
     const double cs[4][2] = {{-1, -1}, {1, -1}, {1, 1}, {-1, 1}};
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
       S[k] = 0.25 * (1 + e1 * cs[k][0]) * (1 + e2 * cs[k][1]);
       d1[k] = 0.25 * cs[k][0] * (1 + e2 * cs[k][1]);
@@ -172,17 +191,22 @@ HD inline void face_point(const GeoTables& T, int type, const double (*V)[3], in
     }
   }
   double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0};
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
     Xr[d] = 0.0;
     xq[d] = 0.0;
   }
-  for (int k = 0; k < nv; ++k) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k >= nv) continue;
     const int lv = T.fv[type][f][P[k]];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
+      const double xv = Ve[lv * 3 + d];
       Xr[d] += S[k] * T.vref[type][lv][d];
-      xq[d] += S[k] * V[lv][d];
-      t1[d] += d1[k] * V[lv][d];
-      t2[d] += d2[k] * V[lv][d];
+      xq[d] += S[k] * xv;
+      t1[d] += d1[k] * xv;
+      t2[d] += d2[k] * xv;
     }
   }
   cr[0] = t1[1] * t2[2] - t1[2] * t2[1];

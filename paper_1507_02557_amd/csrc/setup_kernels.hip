@@ -9,15 +9,14 @@ namespace hdg {
 
 // One thread per element: volume factors at the type's points, face factors at
 // the canonical face points, and the inputs of the stable time step.
-__global__ void geometry_kernel(GeoArgs g) {
+__global__ __launch_bounds__(64) void geometry_kernel(GeoArgs g) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= g.K) return;
   const GeoTables& T = *g.T;
   const int type = g.type;
   const int nv = T.nv[type], nf = T.nf[type];
   double V[8][3];
-  for (int v = 0; v < nv; ++v)
-    for (int d = 0; d < 3; ++d) V[v][d] = g.V[(e * nv + v) * 3 + d];
+  load_verts(g.V, e, nv, V);
   double minJ = 1e300;   // over volume points: enters C_J^K (Section 3.4)
   double minJall;        // over volume and face points: validity check
   // ---- volume points
@@ -56,7 +55,7 @@ __global__ void geometry_kernel(GeoArgs g) {
     const double sref = (fnv == 3 ? 2.0 : 4.0) / T.farea[type][f];
     for (int q = 0; q < Nfq; ++q) {
       double Xr[3], xq[3], cr[3], x[3], F[3][3], G[3][3];
-      face_point(T, type, V, f, o, q, Xr, xq, cr);
+      face_point(T, type, g.V + e * nv * 3, f, o, q, Xr, xq, cr);
       vmap(type, V, Xr, x, F);
       const double J = inv3(F, G);
       minJall = J < minJall ? J : minJall;
@@ -95,8 +94,7 @@ __global__ void points_kernel(int type, int64_t K, int nv, const double* Vall, c
   const int64_t e = it / npts;
   const int i = (int)(it % npts);
   double V[8][3];
-  for (int v = 0; v < nv; ++v)
-    for (int d = 0; d < 3; ++d) V[v][d] = Vall[(e * nv + v) * 3 + d];
+  load_verts(Vall, e, nv, V);
   double x[3], F[3][3];
   vmap(type, V, pts + 3 * i, x, F);
   for (int d = 0; d < 3; ++d) out[it * 3 + d] = x[d];
@@ -112,8 +110,7 @@ __global__ void project_weight_kernel(int type, int64_t K, int nv, const double*
   const int64_t e = it / npts;
   const int q = (int)(it % npts);
   double V[8][3];
-  for (int v = 0; v < nv; ++v)
-    for (int d = 0; d < 3; ++d) V[v][d] = Vall[(e * nv + v) * 3 + d];
+  load_verts(Vall, e, nv, V);
   double x[3], F[3][3];
   vmap(type, V, pts + 3 * q, x, F);
   const double J = det3(F);
@@ -136,8 +133,7 @@ __global__ void project_apply_kernel(int type, int64_t K, int nv, const double* 
   double m = 1.0;
   if (type == 2) {
     double V[8][3];
-    for (int v = 0; v < nv; ++v)
-      for (int d = 0; d < 3; ++d) V[v][d] = Vall[(e * nv + v) * 3 + d];
+    load_verts(Vall, e, nv, V);
     double x[3], F[3][3];
     vmap(type, V, geo_pts + 3 * i, x, F);
     m = det3(F);
