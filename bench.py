@@ -68,6 +68,20 @@ def cpu_baseline(n: int, N: int, stages: int):
                       f"{os.cpu_count()} visible host cores"}
 
 
+def copy_calibration(mib: int):
+    """One plain device-to-device copy of known size: under rocprofv3 --pmc its
+    FETCH_SIZE / WRITE_SIZE give the counter scale for HBM traffic."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,10 +92,15 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=12)
     ap.add_argument("--cpu-stages", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_mib > 0:
+        copy_calibration(args.copy_mib)
+        return
 
     import numpy as np
     import torch
