@@ -40,6 +40,37 @@ def tet_alg_bytes(N: int) -> int:
     return 64 * Np + 32 * 4 * Nfq + 48 + 8 + 4 * (16 + 4 + 1 + 8)
 
 
+def csrc_hash() -> str:
+    """sha256 (first 16 hex) over the library's native sources, in name order."""
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1507_02557_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_name: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings),
+    or None when the sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    if data.get("source_hash") != csrc_hash():
+        return None
+    for name, b in data.get("bytes_per_launch", {}).items():
+        if kernel_name in name:
+            return float(b)
+    return None
+
+
 def cpu_baseline(n: int, N: int, stages: int):
     import numpy as np
     from threadpoolctl import threadpool_info
@@ -140,6 +171,7 @@ def main():
     per_type = {name: round(float(kms[t] / max(kcnt[t], 1)), 4)
                 for t, name in ((0, "hex"), (1, "wedge"), (2, "pyr"), (3, "tet")) if kcnt[t]}
     Ktet = s.info[hdg.TET][0]
+    tet_kernel = f"TetStage<{N}, "
     alg_bytes = tet_alg_bytes(N) * Ktet
     achieved = alg_bytes / (avg_ms[hdg.TET] * 1e-3) / 1e9
     E = s.energy()
@@ -174,7 +206,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(tet_kernel),
             "alg_bytes_per_launch": int(alg_bytes),
         },
     }
