@@ -26,18 +26,21 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def tet_alg_bytes(N: int) -> int:
+def tet_alg_bytes(N: int, lattice: bool) -> int:
     """Algorithmic HBM bytes per tetrahedron per stage of the fused kernel.
 
     State: read U and res, write U and res (4 fields, FP32): 64 B per node.
-    Traces: write the element's own traces and read the neighbour's at the
-    4 (N+1)^2 face points (4 fields, FP32): 32 B per face point.
-    Element data: 12 geometry floats, (kappa, 1/rho), 4 face records
-    (normal + J^s, neighbour slot, orientation, penalties): 48+8+4*(16+4+1+8).
+    Traces: write the element's own traces and read the neighbour's (4 fields,
+    FP32): 32 B per trace point, on 4 faces; a trace point is a face-lattice
+    node ((N+1)(N+2)/2 per face) with lattice traces, else a cubature point
+    ((N+1)^2 per face).
+    Element data: 10 geometry floats read as 12, (kappa, 1/rho), 4 face
+    records (normal + J^s, neighbour slot, orientation, penalties):
+    48 + 8 + 4 * (16 + 4 + 1 + 8).
     """
     Np = (N + 1) * (N + 2) * (N + 3) // 6
-    Nfq = (N + 1) ** 2
-    return 64 * Np + 32 * 4 * Nfq + 48 + 8 + 4 * (16 + 4 + 1 + 8)
+    npt = (N + 1) * (N + 2) // 2 if lattice else (N + 1) ** 2
+    return 64 * Np + 32 * 4 * npt + 48 + 8 + 4 * (16 + 4 + 1 + 8)
 
 
 def csrc_hash() -> str:
@@ -171,8 +174,9 @@ def main():
     per_type = {name: round(float(kms[t] / max(kcnt[t], 1)), 4)
                 for t, name in ((0, "hex"), (1, "wedge"), (2, "pyr"), (3, "tet")) if kcnt[t]}
     Ktet = s.info[hdg.TET][0]
-    tet_kernel = f"TetStage<{N}, "
-    alg_bytes = tet_alg_bytes(N) * Ktet
+    lattice = s.get_path()[1] == 1
+    tet_kernel = f"TetMfma<{N}, " if lattice else f"TetStage<{N}, "
+    alg_bytes = tet_alg_bytes(N, lattice) * Ktet
     achieved = alg_bytes / (avg_ms[hdg.TET] * 1e-3) / 1e9
     E = s.energy()
 
@@ -201,7 +205,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": f"stage_kernel<TetStage<{N}>>",
+            "kernel": ("tet_mfma_kernel" if lattice else "stage_kernel") + f"<{tet_kernel}...>",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

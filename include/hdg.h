@@ -61,6 +61,9 @@ extern "C" {
 
 #define HDG_PREC_FP32 0      /* operator arithmetic in FP32 */
 
+#define HDG_PATH_AUTO 0      /* lattice traces + matrix-core tetrahedra where the mesh allows */
+#define HDG_PATH_GENERIC 1   /* cubature-point traces on every face, vector kernels */
+
 typedef struct hdg_ctx hdg_ctx;
 
 /* Mesh description (all host pointers, copied by hdg_create).
@@ -177,6 +180,20 @@ int hdg_energy(hdg_ctx* ctx, double* E);
  * Enabling or disabling resets the counters. */
 int hdg_profile(hdg_ctx* ctx, int on);
 int hdg_profile_read(hdg_ctx* ctx, double* ms_out, int64_t* count_out);
+
+/* Kernel path (both compute the same discrete operator, Section 2.3).
+ * HDG_PATH_AUTO (default): where no triangular face joins a wedge to a
+ * tetrahedron or pyramid, faces between tetrahedra and pyramids exchange
+ * face-lattice traces (the traces there are degree-N polynomials, so the
+ * lattice values determine them and the flux on a planar face), and
+ * tetrahedra run on the matrix cores.  Otherwise, or with HDG_PATH_GENERIC,
+ * every face exchanges traces at the canonical cubature points.
+ * hdg_set_path: path is HDG_PATH_AUTO or HDG_PATH_GENERIC (else
+ * HDG_EINVAL); HDG_ESTATE after hdg_mrab_setup.  Traces are rebuilt from the
+ * state on the next step.  hdg_get_path: requested path and whether lattice
+ * traces are in use (1) or not (0); either pointer may be NULL. */
+int hdg_set_path(hdg_ctx* ctx, int path);
+int hdg_get_path(const hdg_ctx* ctx, int* path_out, int* lattice_out);
 
 #ifdef __cplusplus
 }

@@ -47,6 +47,8 @@ struct TypeData {
   double* V = nullptr;         // [K][nv][3]
   float* ops = nullptr;
   int* iops = nullptr;
+  float* mops = nullptr;       // tetrahedra: matrix-core kernel tables
+  int* miops = nullptr;
   double* spts = nullptr;      // sample reference points [nsample][3]
   double* sw = nullptr;        // sample weights (wedge, pyramid)
   double* Phi = nullptr;       // basis at sample points (wedge, pyramid)
@@ -80,6 +82,9 @@ struct hdg_ctx {
   float4* trace[2] = {nullptr, nullptr};
   int cur = 0;
   bool traces_valid = false;
+  bool lattice_ok = false;     // no triangular face joins a wedge to a tet or pyramid
+  int path = HDG_PATH_AUTO;
+  int max_blocks = 1024;       // cap of persistent grids (4 per compute unit)
   GeoTables* gtab = nullptr;
   double* partial = nullptr;
   int* flag = nullptr;
@@ -204,6 +209,81 @@ int build_tables(hdg_ctx* c, int t, std::vector<float>& ops, std::vector<int>& i
   return HDG_OK;
 }
 
+// Tables of the matrix-core tetrahedron kernel: D^{r,s,t} and the lattice
+// lift matrices L_f = M^-1 E_f M_f in MFMA fragment order, where
+// M_f = Ican^T W Ican is the mass matrix of the face lattice (exact: the
+// canonical rule integrates degree 2N on the triangle).
+int build_tet_mfma_tables(hdg_ctx* c, std::vector<float>& ops, std::vector<int>& iops) {
+  const TetRef& T = c->tet;
+  const FaceTables& ft = c->ft;
+  const int Np = T.Np, Nfn = ft.Nfn, Nfq = ft.Nfq;
+  const int Mt = (Np + 15) / 16, Ks = (Np + 3) / 4, Kf = (Nfn + 3) / 4;
+  std::vector<double> Mf((size_t)Nfn * Nfn, 0.0);
+  for (int q = 0; q < Nfq; ++q)
+    for (int x = 0; x < Nfn; ++x)
+      for (int y = 0; y < Nfn; ++y) Mf[x * Nfn + y] += ft.Ican[q * Nfn + x] * ft.tri_w[q] * ft.Ican[q * Nfn + y];
+  double mx = 0.0;
+  for (double v : Mf) mx = std::max(mx, std::fabs(v));
+  // the lattice is symmetric: M_f must not depend on the face frame
+  for (int o = 0; o < 6; ++o) {
+    const int* P = &ft.tri_perm[o * Nfn];
+    for (int x = 0; x < Nfn; ++x)
+      for (int y = 0; y < Nfn; ++y)
+        if (std::fabs(Mf[P[x] * Nfn + P[y]] - Mf[x * Nfn + y]) > 1e-10 * mx)
+          return fail(c, HDG_EINVAL, "internal: face lattice mass matrix is not permutation invariant");
+  }
+  std::vector<double> L((size_t)4 * Np * Nfn, 0.0);
+  for (int f = 0; f < 4; ++f)
+    for (int i = 0; i < Np; ++i)
+      for (int l = 0; l < Nfn; ++l) {
+        double acc = 0.0;
+        for (int j = 0; j < Nfn; ++j) acc += T.Minv[(size_t)i * Np + T.fnode[f * Nfn + j]] * Mf[j * Nfn + l];
+        L[((size_t)f * Np + i) * Nfn + l] = acc;
+      }
+  ops.clear();
+  iops.clear();
+  const Vec* D[3] = {&T.Dr, &T.Ds, &T.Dt};
+  for (int r = 0; r < 3; ++r)
+    for (int t = 0; t < Mt; ++t)
+      for (int s = 0; s < Ks; ++s)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int row = 16 * t + lane % 16, col = 4 * s + lane / 16;
+          ops.push_back(row < Np && col < Np ? (float)(*D[r])[(size_t)row * Np + col] : 0.0f);
+        }
+  for (int f = 0; f < 4; ++f)
+    for (int t = 0; t < Mt; ++t)
+      for (int s = 0; s < Kf; ++s)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int row = 16 * t + lane % 16, col = 4 * s + lane / 16;
+          ops.push_back(row < Np && col < Nfn ? (float)L[((size_t)f * Np + row) * Nfn + col] : 0.0f);
+        }
+  iops.insert(iops.end(), T.fnode.begin(), T.fnode.end());
+  iops.insert(iops.end(), ft.tri_perm.begin(), ft.tri_perm.end());
+  int nf = 0, ni = 0;
+  tet_mfma_table_sizes(c->N, &nf, &ni);
+  if ((int)ops.size() != nf || (int)iops.size() != ni)
+    return fail(c, HDG_EINVAL, "internal: matrix-core table size mismatch");
+  return HDG_OK;
+}
+
+bool use_lattice(const hdg_ctx* c) { return c->path == HDG_PATH_AUTO && c->lattice_ok; }
+
+// One launch of the kernel serving type t: tetrahedra go to the matrix-core
+// kernel when lattice traces are in use; mrab selects the multi-rate update.
+int launch_type(hdg_ctx* c, int t, StageArgs a, bool mrab) {
+  a.lat = use_lattice(c) ? 1 : 0;
+  if (t == kTet && a.lat) {
+    a.ops = c->td[t].mops;
+    a.iops = c->td[t].miops;
+    if (mrab) a.mode = kModeMrab;
+    if (launch_tet_mfma(c->N, a, c->stream, c->max_blocks)) return fail(c, HDG_EINVAL, "no kernel for this order");
+    return HDG_OK;
+  }
+  const int r = mrab ? launch_mrab_update(t, c->N, a, c->stream) : launch_stage(t, c->N, a, c->stream);
+  if (r) return fail(c, HDG_EINVAL, "no stage kernel for this order");
+  return HDG_OK;
+}
+
 int check_type(const hdg_ctx* c, int t) {
   if (t < 0 || t > 3) return HDG_EINVAL;
   return c->td[t].present ? HDG_OK : HDG_EINVAL;
@@ -232,7 +312,8 @@ int ensure_traces(hdg_ctx* c) {
     a.ops = d.ops;
     a.iops = d.iops;
     a.mode = kModeTrace;
-    if (launch_stage(t, c->N, a, c->stream)) return fail(c, HDG_EINVAL, "no stage kernel for this order");
+    int rc = launch_type(c, t, a, false);
+    if (rc) return rc;
   }
   HIPCHK(c, hipGetLastError());
   c->traces_valid = true;
@@ -284,7 +365,7 @@ int run_stage(hdg_ctx* c, int mode, float ra, float rb, float dt) {
     hipEvent_t stop;
     int rc = prof_begin(c, t, &stop);
     if (rc) return rc;
-    if (launch_stage(t, c->N, a, c->stream)) return fail(c, HDG_EINVAL, "no stage kernel for this order");
+    if ((rc = launch_type(c, t, a, false))) return rc;
     if (stop) HIPCHK(c, hipEventRecord(stop, c->stream));
   }
   HIPCHK(c, hipGetLastError());
@@ -373,6 +454,26 @@ int create_impl(hdg_ctx* c, const hdg_mesh* m, int N) {
     }
     i = j;
   }
+  // lattice traces need every triangular face touching a tetrahedron or a
+  // pyramid to have no wedge on either side (wedge traces are not polynomial)
+  {
+    std::vector<int8_t> slot_type(ns), slot_nv(ns);
+    for (int t = 0; t < 4; ++t) {
+      const TypeData& d = c->td[t];
+      const ElemDesc& E = elem_desc(t);
+      for (int64_t k = 0; k < d.K; ++k)
+        for (int f = 0; f < E.nf; ++f) {
+          slot_type[d.slot0 + k * E.nf + f] = (int8_t)t;
+          slot_nv[d.slot0 + k * E.nf + f] = (int8_t)E.fnv[f];
+        }
+    }
+    c->lattice_ok = true;
+    for (int64_t s = 0; s < ns && c->lattice_ok; ++s) {
+      if (nbr[s] < 0 || slot_nv[s] != 3) continue;
+      const int ta = slot_type[s], tb = slot_type[nbr[s]];
+      if ((ta == kWedge) != (tb == kWedge)) c->lattice_ok = false;
+    }
+  }
   // penalties: tau_p = 1 / {rho c}, tau_u = {rho c}; boundary uses own rho c
   std::vector<float2> tau(ns);
   std::vector<double> taup_max(ne, 0.0), tauu_max(ne, 0.0);
@@ -389,6 +490,12 @@ int create_impl(hdg_ctx* c, const hdg_mesh* m, int N) {
   c->nbr_h = nbr;
   c->etype_h = etype_local;
   c->eidx_h = eidx;
+  {
+    int dev = 0, ncu = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (ncu > 0) c->max_blocks = 4 * ncu;
+  }
   int rc;
   if ((rc = upload(c, &c->nbr, nbr))) return rc;
   if ((rc = upload(c, &c->ori, ori))) return rc;
@@ -515,6 +622,11 @@ int create_impl(hdg_ctx* c, const hdg_mesh* m, int N) {
     if ((rc = build_tables(c, t, ops, iops))) return rc;
     if ((rc = upload(c, &d.ops, ops))) return rc;
     if ((rc = upload(c, &d.iops, iops))) return rc;
+    if (t == kTet) {
+      if ((rc = build_tet_mfma_tables(c, ops, iops))) return rc;
+      if ((rc = upload(c, &d.mops, ops))) return rc;
+      if ((rc = upload(c, &d.miops, iops))) return rc;
+    }
     const size_t nstate = (size_t)4 * K * d.Np;
     if ((rc = dalloc(c, &d.U, nstate))) return rc;
     if ((rc = dalloc(c, &d.R, nstate))) return rc;
@@ -755,7 +867,7 @@ int mr_rhs(hdg_ctx* c, int k, int dense) {
     hipEvent_t stop;
     int rc = prof_begin(c, t, &stop);
     if (rc) return rc;
-    if (launch_stage(t, c->N, a, c->stream)) return fail(c, HDG_EINVAL, "no stage kernel for this order");
+    if ((rc = launch_type(c, t, a, false))) return rc;
     if (stop) HIPCHK(c, hipEventRecord(stop, c->stream));
   }
   for (int l = lmin; l <= c->L; ++l) c->hcount[l]++;
@@ -775,7 +887,7 @@ int mr_update(hdg_ctx* c, int k) {
     hipEvent_t stop;
     int rc = prof_begin(c, t, &stop);
     if (rc) return rc;
-    if (launch_mrab_update(t, c->N, a, c->stream)) return fail(c, HDG_EINVAL, "no stage kernel for this order");
+    if ((rc = launch_type(c, t, a, true))) return rc;
     if (stop) HIPCHK(c, hipEventRecord(stop, c->stream));
   }
   HIPCHK(c, hipGetLastError());
@@ -906,6 +1018,24 @@ int hdg_energy(hdg_ctx* c, double* E) {
   }
   *E = total;
   return std::isfinite(total) ? HDG_OK : fail(c, HDG_ENONFINITE, "energy is not finite");
+}
+
+int hdg_set_path(hdg_ctx* c, int path) {
+  if (!c) return HDG_EINVAL;
+  if (path != HDG_PATH_AUTO && path != HDG_PATH_GENERIC) return fail(c, HDG_EINVAL, "unknown path");
+  if (c->mr_ready) return fail(c, HDG_ESTATE, "the path cannot change after hdg_mrab_setup");
+  if (path != c->path) {
+    c->path = path;
+    c->traces_valid = false;
+  }
+  return HDG_OK;
+}
+
+int hdg_get_path(const hdg_ctx* c, int* path_out, int* lattice_out) {
+  if (!c) return HDG_EINVAL;
+  if (path_out) *path_out = c->path;
+  if (lattice_out) *lattice_out = use_lattice(c) ? 1 : 0;
+  return HDG_OK;
 }
 
 int hdg_profile(hdg_ctx* c, int on) {

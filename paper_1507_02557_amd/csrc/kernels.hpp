@@ -54,5 +54,11 @@ int launch_mrab_update(int type, int N, const StageArgs& a, hipStream_t s);
 // Packed operator table sizes of the stage kernel for (type, N).
 void stage_table_sizes(int type, int N, int* n_floats, int* n_ints);
 int stage_batch(int type, int N);
+// Tetrahedra on the matrix cores with lattice traces (all modes, including
+// kModeMrab); max_blocks caps the persistent grid.
+int launch_tet_mfma(int N, const StageArgs& a, hipStream_t s, int max_blocks);
+// Packed table sizes: D fragments [3][Mt][Ks][64], lift fragments
+// [4][Mt][Kf][64]; fnode [4][Nfn], tperm [6][Nfn].
+void tet_mfma_table_sizes(int N, int* n_floats, int* n_ints);
 
 }  // namespace hdg

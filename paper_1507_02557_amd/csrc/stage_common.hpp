@@ -58,10 +58,13 @@ struct StageArgs {
   const float* ops;      // packed FP32 operator tables
   const int* iops;       // packed integer tables
   float a, b, dt;        // res = a res + dt rhs; U = U + b res
-  int mode;              // kModeStage, kModeTrace, kModeRhs or kModeRhsHist
+  int mode;              // kModeStage, kModeTrace, kModeRhs, kModeRhsHist or kModeMrab
+  int lat;               // 1: triangular faces between tetrahedra and pyramids carry
+                         // lattice traces (face-lattice values, canonical order)
 };
 
-enum { kModeStage = 0, kModeTrace = 1, kModeRhs = 2, kModeRhsHist = 3 };
+// kModeMrab: multi-rate update (state, traces, mid-step traces) of the items.
+enum { kModeStage = 0, kModeTrace = 1, kModeRhs = 2, kModeRhsHist = 3, kModeMrab = 4 };
 
 // Element processed by item i, or -1 past the end of the launch.
 HD inline int64_t item(const StageArgs& a, int64_t i) {
@@ -107,21 +110,43 @@ HD inline void upwind_flux(float4 m, float4 p, float4 g, float2 tau, bool skew, 
   out[3] = fu * nz;
 }
 
+// Trace buffer holding the neighbour slot nb's current trace: a coarser
+// neighbour that is mid-step supplies its dense-output (mid-step) trace.
+HD inline const float4* neighbour_src(const StageArgs& a, int64_t slot, int nb) {
+  if (a.mr.dense) {
+    const int ln = a.slevel[nb];
+    if (ln < a.slevel[slot] && (a.mr.ksub & ((1 << (a.mr.L - ln)) - 1)) != 0) return a.tr_half;
+  }
+  return a.tr_in;
+}
+
 // Own and neighbour traces at canonical point q of a slot.
 HD inline void face_states(const StageArgs& a, int64_t slot, int nfq, int q, float4 g, float4& m, float4& p) {
   m = a.tr_in[slot * nfq + q];
   const int nb = a.nbr[slot];
   if (nb >= 0) {
-    const float4* src = a.tr_in;
-    if (a.mr.dense) {
-      // a coarser neighbour that is mid-step supplies its dense-output trace
-      const int ln = a.slevel[nb];
-      if (ln < a.slevel[slot] && (a.mr.ksub & ((1 << (a.mr.L - ln)) - 1)) != 0) src = a.tr_half;
-    }
-    p = src[(int64_t)nb * nfq + q];
+    p = neighbour_src(a, slot, nb)[(int64_t)nb * nfq + q];
   } else {
     p = mirror_state(m, -nb - 1, g.x, g.y, g.z);
   }
+}
+
+// Same from lattice traces: values at canonical cubature point q are
+// interpolated from the canonical lattice values (Ican [nfq][nfn]).
+HD inline void face_states_lattice(const StageArgs& a, int64_t slot, int nfq, int nfn, int q, const float* Ican,
+                                   float4 g, float4& m, float4& p) {
+  const float4* own = a.tr_in + slot * nfq;
+  const int nb = a.nbr[slot];
+  const float4* nbv = nb >= 0 ? neighbour_src(a, slot, nb) + (int64_t)nb * nfq : own;
+  float4 sm = make_float4(0.f, 0.f, 0.f, 0.f), sp = sm;
+  for (int j = 0; j < nfn; ++j) {
+    const float w = Ican[q * nfn + j];
+    const float4 x = own[j], y = nbv[j];
+    sm.x += w * x.x; sm.y += w * x.y; sm.z += w * x.z; sm.w += w * x.w;
+    sp.x += w * y.x; sp.y += w * y.y; sp.z += w * y.z; sp.w += w * y.w;
+  }
+  m = sm;
+  p = nb >= 0 ? sp : mirror_state(sm, -nb - 1, g.x, g.y, g.z);
 }
 
 // Multi-rate update of one batch, as a sequence of barrier-separated steps:

@@ -8,7 +8,9 @@
 // Surface: base (quadrilateral) face through the basis values at its local GL
 //          points; triangular faces through the face's equispaced lattice
 //          (the pyramid's trace on a triangle is a degree-N polynomial), as
-//          for tetrahedra.
+//          for tetrahedra.  With lattice traces (a.lat) the triangular faces
+//          exchange lattice values and interpolate both sides to the
+//          cubature points.
 #pragma once
 
 #include "stage_common.hpp"
@@ -108,7 +110,8 @@ struct PyrStage {
         const int64_t slot = a.slot0 + e * 5 + f;
         const float4 g = a.fgeo[(e * 5 + f) * Nfq + q];
         float4 m, p;
-        face_states(a, slot, Nfq, q, g, m, p);
+        if (a.lat && f > 0) face_states_lattice(a, slot, Nfq, Nfn, q, &sm.Ican[0][0], g, m, p);
+        else face_states(a, slot, Nfq, q, g, m, p);
         float out[4];
         upwind_flux(m, p, g, a.tau[slot], true, out);
         const int l = (f == 0) ? sm.qperm[a.ori[slot]][q] : q;
@@ -207,6 +210,17 @@ struct PyrStage {
           for (int c = 0; c < 4; ++c) acc[c] += w * src[c][el][j];
         }
         for (int c = 0; c < 4; ++c) sm.c[el][tf][l][c] = acc[c];
+      }
+    } else if (ph == 6 && a.lat) {
+      // lattice traces: the face-lattice values in the canonical order
+      for (int it = tid; it < EPB * 4 * Nfn; it += NT) {
+        const int el = it / (4 * Nfn), rr = it % (4 * Nfn);
+        const int tf = rr / Nfn, m = rr % Nfn;
+        const int64_t e = item(a, e0 + el);
+        if (e < 0) continue;
+        const int64_t slot = a.slot0 + e * 5 + 1 + tf;
+        const int l = sm.tperm[a.ori[slot]][m];
+        a.tr_out[slot * Nfq + m] = make_float4(sm.c[el][tf][l][0], sm.c[el][tf][l][1], sm.c[el][tf][l][2], sm.c[el][tf][l][3]);
       }
     } else if (ph == 6) {
       for (int it = tid; it < EPB * 4 * Nfq; it += NT) {

@@ -1,0 +1,446 @@
+// Tetrahedra on the matrix cores (Section 2.3.2, Algorithm 4: strong form,
+// dense reference derivative matrices, constant geometric factors).
+//
+// Each wavefront owns a tile of 16 consecutive elements; the element index is
+// the column index of every matrix product, so one 16x16x4 FP32 MFMA applies
+// a 16-row slice of an operator to 16 elements at once:
+//
+//   grad:   G_r = D^r p                  (3 products per k-step)
+//   div:    P   = sum_r D^r (-u^r)       u^r = sum_d dxi_r/dx_d u_d
+//   lift:   P  += sum_f L_f (J^s F_p / J),  U_d = sum_f L_f (J^s F_d / J)
+//
+// with L_f = M^-1 E_f M_f, M_f the face mass matrix of the equispaced face
+// lattice (E_f scatters face lattice nodes onto element nodes).  On a planar
+// face between elements whose traces are degree-N polynomials (tetrahedra,
+// pyramids) the upwind flux is a degree-N polynomial with constant
+// coefficients, so evaluating it at the lattice nodes and weighting by M_f
+// gives the same face integral as the canonical cubature rule.  The lattice
+// is invariant under the face's vertex permutations, so M_f is the same in
+// every local frame, and the trace of an element on such a face is just its
+// face-node values: the kernel writes them (permuted to the canonical frame)
+// to the trace buffer and reads the neighbour's in the same form.
+//
+// Operators live in LDS in MFMA fragment order (entry [lane] of a fragment
+// is the value lane 'lane' passes to the instruction), so every fragment
+// load is one conflict-free 32-bit LDS read.  The element tile lives in LDS
+// row-major per element with an odd row stride, which makes the B-fragment
+// reads (16 elements x 4 consecutive nodes) conflict-free as well.
+#pragma once
+
+#include "stage_common.hpp"
+
+namespace hdg {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// D = A B + C for 16x16 tiles, K = 4: lane l passes A[l%16][l/16] and
+// B[l/16][l%16] and holds D[4(l/16)+i][l%16] in component i.
+__device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// LDS writes of this wavefront become visible to its later LDS reads (LDS
+// operations of one wavefront complete in order; this stops the compiler
+// from moving memory operations across the point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Neighbour state on a lattice face at canonical lattice node m (boundary:
+// mirror of the own state).  A coarser neighbour that is mid-step supplies
+// its dense-output trace.
+__device__ __forceinline__ float4 lattice_neighbour(const StageArgs& a, int64_t slot, int nfq, int m, float4 g,
+                                                    float4 own) {
+  const int nb = a.nbr[slot];
+  if (nb < 0) return mirror_state(own, -nb - 1, g.x, g.y, g.z);
+  return neighbour_src(a, slot, nb)[(int64_t)nb * nfq + m];
+}
+
+template <int N, int NW>
+struct TetMfma {
+  static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
+  static constexpr int Nfn = (N + 1) * (N + 2) / 2;
+  static constexpr int Nfq = (N + 1) * (N + 1);
+  static constexpr int Mt = (Np + 15) / 16;  // 16-row tiles of the element operators
+  static constexpr int Ks = (Np + 3) / 4;    // k-steps over element nodes
+  static constexpr int Kf = (Nfn + 3) / 4;   // k-steps over one face's lattice
+  static constexpr int SX = (4 * Ks) | 1;    // odd row strides, padded rows stay zero
+  static constexpr int SF = (4 * Kf) | 1;
+  static constexpr int NT = 64 * NW;
+  static constexpr int kDFloats = 3 * Mt * Ks * 64;
+  static constexpr int kLFloats = 4 * Mt * Kf * 64;
+  static constexpr int kOpsFloats = kDFloats + kLFloats;
+  static constexpr int kOpsInts = 4 * Nfn + 6 * Nfn;
+
+  struct Wave {
+    float X[4][16][SX];  // state tile (p, ux, uy, uz)
+    float F[4][16][SF];  // one face's scaled flux; staging of one output field
+  };
+  static_assert(4 * 16 * SF >= 16 * SX, "output staging does not fit the flux buffer");
+
+  struct Smem {
+    float D[3][Mt][Ks][64];
+    float L[4][Mt][Kf][64];
+    int fnode[4][Nfn];  // element node of local face lattice node
+    int tperm[6][Nfn];  // canonical lattice node -> local lattice node
+    Wave w[NW];
+  };
+
+  static constexpr int Q4 = 4 * Np;          // float4 per field of a full tile (16 Np floats)
+  static constexpr int JQ = (Q4 + 63) / 64;  // of them per lane
+  static constexpr int JF = (Nfn + 3) / 4;   // lattice nodes m = g + 4 j per lane and face
+
+  // rows [0, Np) of 16 elements of one field, global [K][Np] <-> LDS [16][S]
+  template <int S>
+  __device__ static void load_rows(float (*dst)[S], const float* src, const StageArgs& a, int64_t e0, int lane) {
+    for (int it = lane; it < 16 * Np; it += 64) {
+      const int n = it / Np, k = it - n * Np;
+      const int64_t e = item(a, e0 + n);
+      dst[n][k] = e >= 0 ? src[e * Np + k] : 0.0f;
+    }
+  }
+  template <int S>
+  __device__ static void store_rows(float* dst, const float (*src)[S], const StageArgs& a, int64_t e0, int lane) {
+    for (int it = lane; it < 16 * Np; it += 64) {
+      const int n = it / Np, k = it - n * Np;
+      const int64_t e = item(a, e0 + n);
+      if (e >= 0) dst[e * Np + k] = src[n][k];
+    }
+  }
+  // four consecutive entries q0 .. q0+3 of a tile in flat [16][Np] order
+  template <int S>
+  __device__ static void put4(float (*dst)[S], int q0, float4 v) {
+    const float x[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = q0 + i, n = q / Np;
+      dst[n][q - n * Np] = x[i];
+    }
+  }
+  template <int S>
+  __device__ static float4 get4(const float (*src)[S], int q0) {
+    float x[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = q0 + i, n = q / Np;
+      x[i] = src[n][q - n * Np];
+    }
+    return make_float4(x[0], x[1], x[2], x[3]);
+  }
+  // A full tile of consecutive elements whose fields start 16-byte aligned
+  // moves as flat float4 vectors, all loads of a field group issued at once.
+  __device__ static bool contiguous(const StageArgs& a, int64_t e0) {
+    return a.elist == nullptr && e0 + 16 <= a.n_items && ((a.K * Np) & 3) == 0;
+  }
+  __device__ static void load_field(float4 (&v)[JQ], const float* base, int64_t e0, int lane) {
+    const float4* src = reinterpret_cast<const float4*>(base + e0 * Np);
+#pragma unroll
+    for (int j = 0; j < JQ; ++j)
+      if (lane + 64 * j < Q4) v[j] = src[lane + 64 * j];
+  }
+  template <int S>
+  __device__ static void put_field(float (*dst)[S], const float4 (&v)[JQ], int lane) {
+#pragma unroll
+    for (int j = 0; j < JQ; ++j)
+      if (lane + 64 * j < Q4) put4<S>(dst, 4 * (lane + 64 * j), v[j]);
+  }
+  template <int S>
+  __device__ static void store_tile(float* dst, const float (*src)[S], const StageArgs& a, int64_t e0, int lane,
+                                    bool contig) {
+    if (contig) {
+      float4* d4 = reinterpret_cast<float4*>(dst + e0 * Np);
+#pragma unroll
+      for (int j = 0; j < JQ; ++j)
+        if (lane + 64 * j < Q4) d4[lane + 64 * j] = get4<S>(src, 4 * (lane + 64 * j));
+    } else {
+      store_rows<S>(dst, src, a, e0, lane);
+    }
+  }
+
+  // Per-lane face record: element (lane & 15) of the tile, face (lane >> 4).
+  struct FaceRec {
+    int nb, ori, half;  // neighbour slot (or -(1 + bc)), orientation, read the mid-step trace
+    float4 g;           // normal, J^s
+    float2 tau;
+  };
+  __device__ static FaceRec load_rec(const StageArgs& a, int64_t e, int f) {
+    FaceRec r{-1, 0, 0, make_float4(0.f, 0.f, 0.f, 0.f), make_float2(0.f, 0.f)};
+    if (e < 0) return r;
+    const int64_t slot = a.slot0 + e * 4 + f;
+    r.nb = a.nbr[slot];
+    r.ori = a.ori[slot];
+    r.g = a.fgeo[e * 4 + f];
+    r.tau = a.tau[slot];
+    if (r.nb >= 0 && a.mr.dense) r.half = neighbour_src(a, slot, r.nb) == a.tr_half;
+    return r;
+  }
+  __device__ static FaceRec shfl_rec(const FaceRec& r, int src) {
+    FaceRec o;
+    o.nb = __shfl(r.nb, src);
+    o.ori = __shfl(r.ori, src);
+    o.half = __shfl(r.half, src);
+    o.g = make_float4(__shfl(r.g.x, src), __shfl(r.g.y, src), __shfl(r.g.z, src), __shfl(r.g.w, src));
+    o.tau = make_float2(__shfl(r.tau.x, src), __shfl(r.tau.y, src));
+    return o;
+  }
+
+  // face-node values of the tile's state, canonical lattice order
+  __device__ static void write_traces(const Smem& sm, const Wave& W, const StageArgs& a, int64_t e0, int lane,
+                                      const FaceRec& rec, float4* tr) {
+    const int n = lane & 15, g = lane >> 4;
+    const int64_t e = item(a, e0 + n);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int o = __shfl(rec.ori, n + 16 * f);
+      if (e < 0) continue;
+      const int64_t slot = a.slot0 + e * 4 + f;
+#pragma unroll
+      for (int j = 0; j < JF; ++j) {
+        const int m = g + 4 * j;
+        if (m >= Nfn) continue;
+        const int node = sm.fnode[f][sm.tperm[o][m]];
+        tr[slot * Nfq + m] = make_float4(W.X[0][n][node], W.X[1][n][node], W.X[2][n][node], W.X[3][n][node]);
+      }
+    }
+  }
+
+  // multi-rate AB3 update: u_half traces (dense output at mid-step), then
+  // u_new = u + dtau_l sum_j beta_j(1) r_{s-j} with its traces
+  __device__ static void mrab_update(const Smem& sm, Wave& W, const StageArgs& a, int64_t e0, int lane,
+                                     const FaceRec& rec) {
+    const int64_t K = a.K;
+    const int64_t hstr = 4 * K * Np;
+    const int n = lane & 15, g = lane >> 4;
+    const int64_t e = item(a, e0 + n);
+    const int lv = e >= 0 ? a.elevel[e] : 1;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int o = __shfl(rec.ori, n + 16 * f);
+      if (e < 0) continue;
+      const int64_t slot = a.slot0 + e * 4 + f;
+      for (int j = 0; j < JF; ++j) {
+        const int m = g + 4 * j;
+        if (m >= Nfn) continue;
+        const int node = sm.fnode[f][sm.tperm[o][m]];
+        float v[4];
+        for (int c = 0; c < 4; ++c) {
+          const int64_t gi = (int64_t)c * K * Np + e * Np + node;
+          const float acc = a.mr.bh[lv][0] * a.H[a.mr.hs[lv][0] * hstr + gi] +
+                            a.mr.bh[lv][1] * a.H[a.mr.hs[lv][1] * hstr + gi] +
+                            a.mr.bh[lv][2] * a.H[a.mr.hs[lv][2] * hstr + gi];
+          v[c] = W.X[c][n][node] + a.mr.dtl[lv] * acc;
+        }
+        a.tr_half[slot * Nfq + m] = make_float4(v[0], v[1], v[2], v[3]);
+      }
+    }
+    wave_sync();
+    for (int c = 0; c < 4; ++c)
+      for (int it = lane; it < 16 * Np; it += 64) {
+        const int nn = it / Np, k = it - nn * Np;
+        const int64_t ee = item(a, e0 + nn);
+        if (ee < 0) continue;
+        const int l2 = a.elevel[ee];
+        const int64_t gi = (int64_t)c * K * Np + ee * Np + k;
+        const float acc = a.mr.b1[l2][0] * a.H[a.mr.hs[l2][0] * hstr + gi] +
+                          a.mr.b1[l2][1] * a.H[a.mr.hs[l2][1] * hstr + gi] +
+                          a.mr.b1[l2][2] * a.H[a.mr.hs[l2][2] * hstr + gi];
+        const float un = W.X[c][nn][k] + a.mr.dtl[l2] * acc;
+        W.X[c][nn][k] = un;
+        a.U[gi] = un;
+      }
+    wave_sync();
+    write_traces(sm, W, a, e0, lane, rec, a.tr_out);
+  }
+
+  // Output of field C: rhs = sc * acc at rows 16 t + 4 g + i of column n,
+  // then the stage update (res = a res + dt rhs, u += b res) or the rhs store.
+  template <int C>
+  __device__ static void emit(Wave& W, const StageArgs& a, int64_t e0, int lane, bool contig, const float4 (&rv)[JQ],
+                              const f32x4 (&acc)[Mt], float sc) {
+    const int64_t K = a.K;
+    const int n = lane & 15, g = lane >> 4;
+    const bool stage = a.mode == kModeStage;
+    float(*RB)[SX] = reinterpret_cast<float(*)[SX]>(&W.F[0][0][0]);
+    if (stage) {
+      if (contig) {
+        put_field<SX>(RB, rv, lane);
+      } else {
+        load_rows<SX>(RB, a.R + (int64_t)C * K * Np, a, e0, lane);
+      }
+      wave_sync();
+    }
+#pragma unroll
+    for (int t = 0; t < Mt; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * t + 4 * g + i;
+        if (row >= Np) continue;
+        const float rhs = sc * acc[t][i];
+        if (stage) {
+          const float res = a.a * RB[n][row] + a.dt * rhs;
+          RB[n][row] = res;
+          W.X[C][n][row] += a.b * res;
+        } else {
+          RB[n][row] = rhs;
+        }
+      }
+    wave_sync();
+    if (a.mode == kModeRhsHist) {
+      for (int it = lane; it < 16 * Np; it += 64) {
+        const int nn = it / Np, k = it - nn * Np;
+        const int64_t ee = item(a, e0 + nn);
+        if (ee >= 0) rhs_dst(a, ee, Np)[(int64_t)C * K * Np + ee * Np + k] = RB[nn][k];
+      }
+    } else {
+      store_tile<SX>(a.R + (int64_t)C * K * Np, RB, a, e0, lane, contig);
+    }
+    if (stage) store_tile<SX>(a.U + (int64_t)C * K * Np, W.X[C], a, e0, lane, contig);
+    wave_sync();
+  }
+
+  __device__ static void tile(const Smem& sm, Wave& W, const StageArgs& a, int64_t e0, int lane) {
+    const int64_t K = a.K;
+    const int n = lane & 15, g = lane >> 4;
+    const int64_t e = item(a, e0 + n);  // element of this lane's column
+    const bool contig = contiguous(a, e0);
+    const FaceRec rec = load_rec(a, e, g);
+    if (contig) {
+      const int64_t fs = K * Np;
+      float4 v0[JQ], v1[JQ], v2[JQ], v3[JQ];
+      load_field(v0, a.U, e0, lane);
+      load_field(v1, a.U + fs, e0, lane);
+      load_field(v2, a.U + 2 * fs, e0, lane);
+      load_field(v3, a.U + 3 * fs, e0, lane);
+      put_field<SX>(W.X[0], v0, lane);
+      put_field<SX>(W.X[1], v1, lane);
+      put_field<SX>(W.X[2], v2, lane);
+      put_field<SX>(W.X[3], v3, lane);
+    } else {
+      for (int c = 0; c < 4; ++c) load_rows<SX>(W.X[c], a.U + (int64_t)c * K * Np, a, e0, lane);
+    }
+    wave_sync();
+    if (a.mode == kModeTrace) {
+      write_traces(sm, W, a, e0, lane, rec, a.tr_out);
+      return;
+    }
+    if (a.mode == kModeMrab) {
+      mrab_update(sm, W, a, e0, lane, rec);
+      return;
+    }
+    // geometric factors and material of this lane's element (column n)
+    float G[10], kap = 0.f, irho = 0.f;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) G[i] = e >= 0 ? a.geo[e * 12 + i] : 0.f;
+    if (e >= 0) {
+      kap = a.mat[e].x;
+      irho = a.mat[e].y;
+    }
+    const float iJ = G[9];
+    f32x4 accP[Mt], accG[3][Mt];
+#pragma unroll
+    for (int t = 0; t < Mt; ++t) {
+      accP[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int r = 0; r < 3; ++r) accG[r][t] = accP[t];
+    }
+    // volume
+#pragma unroll 2
+    for (int s = 0; s < Ks; ++s) {
+      const int k = 4 * s + g;
+      const float p = W.X[0][n][k], u1 = W.X[1][n][k], u2 = W.X[2][n][k], u3 = W.X[3][n][k];
+      float ut[3];
+      for (int r = 0; r < 3; ++r) ut[r] = -(G[3 * r] * u1 + G[3 * r + 1] * u2 + G[3 * r + 2] * u3);
+#pragma unroll
+      for (int t = 0; t < Mt; ++t)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const float d = sm.D[r][t][s][lane];
+          accG[r][t] = mma_f32(d, p, accG[r][t]);
+          accP[t] = mma_f32(d, ut[r], accP[t]);
+        }
+    }
+    // velocity rhs accumulators start from the physical pressure gradient
+    f32x4 accL[3][Mt];
+#pragma unroll
+    for (int t = 0; t < Mt; ++t)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) accL[d][t] = -(G[d] * accG[0][t] + G[3 + d] * accG[1][t] + G[6 + d] * accG[2][t]);
+    // the residual of the stage, fetched while the faces are processed
+    const bool stage = a.mode == kModeStage;
+    float4 rv0[JQ], rv1[JQ], rv2[JQ], rv3[JQ];
+    if (stage && contig) {
+      const int64_t fs = K * Np;
+      load_field(rv0, a.R, e0, lane);
+      load_field(rv1, a.R + fs, e0, lane);
+      load_field(rv2, a.R + 2 * fs, e0, lane);
+      load_field(rv3, a.R + 3 * fs, e0, lane);
+    }
+    // faces: flux at the lattice nodes, then the lift products
+#pragma unroll 1
+    for (int f = 0; f < 4; ++f) {
+      const FaceRec fr = shfl_rec(rec, n + 16 * f);
+      const float4* nsrc = fr.half ? a.tr_half : a.tr_in;
+      float4 pv[JF];
+#pragma unroll
+      for (int j = 0; j < JF; ++j) {
+        const int m = g + 4 * j;
+        if (e >= 0 && m < Nfn && fr.nb >= 0) pv[j] = nsrc[(int64_t)fr.nb * Nfq + m];
+      }
+#pragma unroll
+      for (int j = 0; j < JF; ++j) {
+        const int m = g + 4 * j;
+        if (m >= Nfn) continue;
+        float out[4] = {0.f, 0.f, 0.f, 0.f};
+        int l = m;
+        if (e >= 0) {
+          l = sm.tperm[fr.ori][m];
+          const int node = sm.fnode[f][l];
+          const float4 own = make_float4(W.X[0][n][node], W.X[1][n][node], W.X[2][n][node], W.X[3][n][node]);
+          const float4 nb = fr.nb >= 0 ? pv[j] : mirror_state(own, -fr.nb - 1, fr.g.x, fr.g.y, fr.g.z);
+          upwind_flux(own, nb, fr.g, fr.tau, false, out);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) W.F[c][n][l] = out[c] * iJ;
+      }
+      wave_sync();
+#pragma unroll
+      for (int s = 0; s < Kf; ++s) {
+        const int k = 4 * s + g;
+        const float b0 = W.F[0][n][k], b1 = W.F[1][n][k], b2 = W.F[2][n][k], b3 = W.F[3][n][k];
+#pragma unroll
+        for (int t = 0; t < Mt; ++t) {
+          const float lf = sm.L[f][t][s][lane];
+          accP[t] = mma_f32(lf, b0, accP[t]);
+          accL[0][t] = mma_f32(lf, b1, accL[0][t]);
+          accL[1][t] = mma_f32(lf, b2, accL[1][t]);
+          accL[2][t] = mma_f32(lf, b3, accL[2][t]);
+        }
+      }
+      wave_sync();
+    }
+    // rhs at rows 16 t + 4 g + i of column n; stage update or rhs output
+    emit<0>(W, a, e0, lane, contig, rv0, accP, kap);
+    emit<1>(W, a, e0, lane, contig, rv1, accL[0], irho);
+    emit<2>(W, a, e0, lane, contig, rv2, accL[1], irho);
+    emit<3>(W, a, e0, lane, contig, rv3, accL[2], irho);
+    if (stage) write_traces(sm, W, a, e0, lane, rec, a.tr_out);
+  }
+
+  __device__ static void run(Smem& sm, const StageArgs& a) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int i = tid; i < kDFloats; i += NT) (&sm.D[0][0][0][0])[i] = a.ops[i];
+    for (int i = tid; i < kLFloats; i += NT) (&sm.L[0][0][0][0])[i] = a.ops[kDFloats + i];
+    for (int i = tid; i < 4 * Nfn; i += NT) (&sm.fnode[0][0])[i] = a.iops[i];
+    for (int i = tid; i < 6 * Nfn; i += NT) (&sm.tperm[0][0])[i] = a.iops[4 * Nfn + i];
+    // padded rows and columns of the tiles must hold finite values
+    float* wz = &sm.w[0].X[0][0][0];
+    for (int i = tid; i < (int)(NW * sizeof(Wave) / sizeof(float)); i += NT) wz[i] = 0.f;
+    __syncthreads();
+    Wave& W = sm.w[wv];
+    const int64_t ntile = (a.n_items + 15) / 16;
+    for (int64_t t = (int64_t)blockIdx.x * NW + wv; t < ntile; t += (int64_t)gridDim.x * NW) tile(sm, W, a, t * 16, lane);
+  }
+};
+
+}  // namespace hdg

@@ -16,6 +16,7 @@ import torch
 HEX, WEDGE, PYR, TET = 0, 1, 2, 3
 BC_FREE_SURFACE, BC_RIGID_WALL = 0, 1
 PREC_FP32 = 0
+PATH_AUTO, PATH_GENERIC = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhdg.so")
@@ -40,6 +41,8 @@ _SIGS = [
     ("hdg_mrab_advance", ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     ("hdg_profile", ctypes.c_int, [_P, ctypes.c_int]),
     ("hdg_profile_read", ctypes.c_int, [_P, _P, _P]),
+    ("hdg_set_path", ctypes.c_int, [_P, ctypes.c_int]),
+    ("hdg_get_path", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
 ]
 EXPORTS = [s[0] for s in _SIGS]
 
@@ -85,7 +88,7 @@ class Solver:
     """
 
     def __init__(self, mesh, N: int, bc: int = BC_RIGID_WALL, precision: int = PREC_FP32,
-                 device: str | torch.device = "cuda", lib_path: str | None = None):
+                 device: str | torch.device = "cuda", lib_path: str | None = None, path: int = PATH_AUTO):
         self.device = torch.device(device)
         self._lib = load_library(lib_path)
         if lib_path is None and (self.device.type != "cuda" or not torch.cuda.is_available()):
@@ -110,6 +113,8 @@ class Solver:
             self._check(self._lib.hdg_type_info(h, t, ctypes.byref(K), ctypes.byref(Np), ctypes.byref(ns)))
             self.info[t] = (K.value, Np.value, ns.value)
         self.types = [t for t in (HEX, WEDGE, PYR, TET) if self.info[t][0] > 0]
+        if path != PATH_AUTO:
+            self.set_path(path)
 
     def _stream(self):
         if self.device.type == "cuda":
@@ -193,6 +198,15 @@ class Solver:
 
     def profile(self, on: bool):
         self._check(self._lib.hdg_profile(self._h, 1 if on else 0))
+
+    def set_path(self, path: int):
+        self._check(self._lib.hdg_set_path(self._h, path))
+
+    def get_path(self):
+        """(requested path, 1 if lattice traces are in use else 0)."""
+        p, lat = ctypes.c_int(), ctypes.c_int()
+        self._check(self._lib.hdg_get_path(self._h, ctypes.byref(p), ctypes.byref(lat)))
+        return p.value, lat.value
 
     def profile_read(self):
         ms = np.zeros(4, dtype=np.float64)

@@ -21,6 +21,7 @@ from .parity_util import lib_state_to_oracle, local_index, patch_mesh, random_st
 pytestmark = pytest.mark.gpu
 
 TOL_RHS = 1e-5
+PATHS = [hdg.PATH_AUTO, hdg.PATH_GENERIC]
 
 
 @pytest.fixture(scope="module")
@@ -44,10 +45,12 @@ def test_dt_matches_oracle(c1_mesh):
     assert abs(mn - d.dt_min(0.5)) < 1e-12 * mn
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 5])
-def test_rhs_matches_oracle(c1_mesh, N):
+def test_rhs_matches_oracle(c1_mesh, N, path):
     d = Disc(c1_mesh, N)
-    s = hdg.Solver(c1_mesh, N)
+    s = hdg.Solver(c1_mesh, N, path=path)
+    assert s.get_path() == (path, 1 if path == hdg.PATH_AUTO else 0)
     U = random_state(d, seed=N)
     set_lib_state(s, U)
     Rl = {t: v.double().cpu().numpy() for t, v in s.rhs().items()}
@@ -56,13 +59,14 @@ def test_rhs_matches_oracle(c1_mesh, N):
     assert max(err.values()) < TOL_RHS, err
 
 
-def test_rhs_free_surface_and_materials():
+@pytest.mark.parametrize("path", PATHS)
+def test_rhs_free_surface_and_materials(path):
     m = four_slab_mesh(4, seed=5, jitter=0.1)
     rng = np.random.default_rng(9)
     m.kappa = rng.uniform(0.5, 2.0, m.n_elem)
     m.rho = rng.uniform(0.5, 2.0, m.n_elem)
     d = Disc(m, 2, bc=BC_FREE_SURFACE)
-    s = hdg.Solver(m, 2, bc=hdg.BC_FREE_SURFACE)
+    s = hdg.Solver(m, 2, bc=hdg.BC_FREE_SURFACE, path=path)
     U = random_state(d, seed=3)
     set_lib_state(s, U)
     Rl = {t: v.double().cpu().numpy() for t, v in s.rhs().items()}
@@ -73,12 +77,13 @@ def test_rhs_free_surface_and_materials():
     assert np.max(np.abs(dte - ref) / ref) < 1e-12
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("slabs,n", [(("hex",), 1), (("tet",), 1), (("pyr6",), 2), (("wedge",), 2), (("pyrtet",), 2)])
-def test_single_type_meshes(slabs, n):
+def test_single_type_meshes(slabs, n, path):
     """Single-element and single-type meshes (all faces on the boundary for n=1)."""
     m = four_slab_mesh(n, seed=2, jitter=0.1, slabs=slabs)
     d = Disc(m, 3)
-    s = hdg.Solver(m, 3)
+    s = hdg.Solver(m, 3, path=path)
     U = random_state(d, seed=7)
     set_lib_state(s, U)
     Rl = {t: v.double().cpu().numpy() for t, v in s.rhs().items()}
@@ -94,11 +99,12 @@ def test_projection_matches_oracle(c1_mesh):
     assert max(err.values()) < 1e-6, err
 
 
-def test_c1_standing_mode_100_steps(c1_mesh):
+@pytest.mark.parametrize("path", PATHS)
+def test_c1_standing_mode_100_steps(c1_mesh, path):
     """Configuration 1: n=4 jittered four-slab mesh, N=3, rigid walls, standing
     mode, 100 LSERK4 steps at the derived stable step: rel L2 <= 1e-5."""
     d = Disc(c1_mesh, 3)
-    s = hdg.Solver(c1_mesh, 3)
+    s = hdg.Solver(c1_mesh, 3, path=path)
     dt = d.dt_min(0.5)
     Uo = d.project(standing_mode_rigid)
     s.project_function(standing_mode_rigid)
@@ -194,13 +200,14 @@ def test_full_size_sampled_rhs():
     assert np.isfinite(E1) and E1 <= E0 * (1 + 1e-6)
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("N,L", [(2, 3), (3, 2)])
-def test_mrab_matches_oracle(c1_mesh, N, L):
+def test_mrab_matches_oracle(c1_mesh, N, L, path):
     """Multi-rate AB3 (levels, start-up and coarse steps) against the oracle."""
     from oracle.mrab import MRAB3
     d = Disc(c1_mesh, N)
     mr = MRAB3(d, L)
-    s = hdg.Solver(c1_mesh, N)
+    s = hdg.Solver(c1_mesh, N, path=path)
     dtmin, cnt, lev = s.mrab_setup(L)
     g = np.zeros(c1_mesh.n_elem, dtype=np.int64)
     for t in d.types:
@@ -231,3 +238,47 @@ def test_mrab_full_size_runs_and_stays_bounded():
     s.mrab_advance(1)
     E1 = s.energy()
     assert np.isfinite(E1) and E1 <= E0 * (1 + 1e-3)
+
+
+def test_paths_agree_after_steps(c1_mesh):
+    """Lattice traces with matrix-core tetrahedra and cubature traces with the
+    vector kernels compute the same operator: 20 LSERK4 steps agree to FP32
+    rounding."""
+    out = []
+    for path in PATHS:
+        s = hdg.Solver(c1_mesh, 4, path=path)
+        s.project_function(standing_mode_rigid)
+        _, dt = s.dt(0.5)
+        s.step(dt, 20)
+        out.append({t: s.get_field(t).double().cpu().numpy() for t in s.types})
+    d = Disc(c1_mesh, 4)
+    assert d.rel_l2(out[0], out[1]) < 2e-6
+
+
+def _wedge_tet_mesh():
+    """A wedge and a tetrahedron sharing the wedge's triangular face s = -1,
+    plus a pyramid on one quadrilateral face: lattice traces must be off."""
+    from paper_1507_02557_amd.inputs import Mesh
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 0, 1],        # wedge s=-1 triangle (y = 0)
+                    [0, 1, 0], [1, 1, 0], [0, 1, 1],        # wedge s=+1 triangle (y = 1)
+                    [0.3, -0.8, 0.3],                       # tet apex below y = 0
+                    [0.4, 0.5, -0.9]], dtype=np.float64)    # pyramid apex below z = 0
+    ev = -np.ones((3, 8), dtype=np.int64)
+    ev[0, :6] = [0, 1, 2, 3, 4, 5]
+    ev[1, :4] = [0, 1, 2, 6]
+    ev[2, :5] = [0, 3, 4, 1, 7]
+    m = Mesh(xyz=xyz, etype=np.array([hdg.WEDGE, hdg.TET, hdg.PYR], dtype=np.int8), everts=ev,
+             kappa=np.array([1.0, 1.5, 0.8]), rho=np.array([1.0, 0.7, 1.2]))
+    return m
+
+
+def test_wedge_tet_face_falls_back_to_cubature_traces():
+    m = _wedge_tet_mesh()
+    d = Disc(m, 3)
+    s = hdg.Solver(m, 3)
+    assert s.get_path() == (hdg.PATH_AUTO, 0)
+    U = random_state(d, seed=11)
+    set_lib_state(s, U)
+    Rl = {t: v.double().cpu().numpy() for t, v in s.rhs().items()}
+    err = type_rel_err(Rl, d.rhs(U))
+    assert max(err.values()) < TOL_RHS, err
