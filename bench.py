@@ -57,7 +57,7 @@ def csrc_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_name: str):
+def measured_traffic(kernel_name: str, also: str = ""):
     """HBM bytes per launch of a kernel from the committed rocprofv3 --pmc
     summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings),
     or None when the sources have changed since the counters were taken."""
@@ -69,7 +69,7 @@ def measured_traffic(kernel_name: str):
     if data.get("source_hash") != csrc_hash():
         return None
     for name, b in data.get("bytes_per_launch", {}).items():
-        if kernel_name in name:
+        if kernel_name in name and also in name:
             return float(b)
     return None
 
@@ -144,32 +144,37 @@ def main():
 
     N = args.order
     mesh = four_slab_mesh(args.n, seed=0, jitter=0.1)
-    s = hdg.Solver(mesh, N, bc=hdg.BC_RIGID_WALL)
     c = pulse_centre(0)
-    s.project_function(lambda x, y, z, t: gaussian_pulse(x, y, z, c))
-    _, dtmin = s.dt(0.5)
     T = 0.5
-    nT = math.ceil(T / dtmin)
-    dt = T / nT
-    dofs = sum(s.info[t][0] * s.info[t][1] for t in s.types)
+    prof_steps = max(2, args.steps // 4)
 
-    s.step(dt, args.warmup)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    s.step(dt, args.steps)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    def run(precision: int, dt: float | None):
+        s = hdg.Solver(mesh, N, bc=hdg.BC_RIGID_WALL, precision=precision)
+        s.project_function(lambda x, y, z, t: gaussian_pulse(x, y, z, c))
+        if dt is None:
+            _, dtmin = s.dt(0.5)
+            dt = T / math.ceil(T / dtmin)
+        s.step(dt, args.warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(dt, args.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        # per-kernel durations (events on the launch stream around each launch)
+        s.profile(True)
+        s.step(dt, prof_steps)
+        kms, kcnt = s.profile_read()
+        s.profile(False)
+        state = {t: s.get_field(t).clone() for t in s.types}
+        return s, dt, ms, kms, kcnt, state
+
+    s, dt, ms, kms, kcnt, state32 = run(hdg.PREC_FP32, None)
+    dofs = sum(s.info[t][0] * s.info[t][1] for t in s.types)
     stages = 5 * args.steps
     gdofs = dofs * stages / (ms * 1e-3) / 1e9
-
-    # per-kernel durations (events on the launch stream around each launch)
-    s.profile(True)
-    s.step(dt, max(2, args.steps // 4))
-    kms, kcnt = s.profile_read()
-    s.profile(False)
     avg_ms = {hdg.TET: kms[3] / max(kcnt[3], 1)}
     per_type = {name: round(float(kms[t] / max(kcnt[t], 1)), 4)
                 for t, name in ((0, "hex"), (1, "wedge"), (2, "pyr"), (3, "tet")) if kcnt[t]}
@@ -179,6 +184,30 @@ def main():
     alg_bytes = tet_alg_bytes(N, lattice) * Ktet
     achieved = alg_bytes / (avg_ms[hdg.TET] * 1e-3) / 1e9
     E = s.energy()
+    info = dict(s.info)
+    types = list(s.types)
+    s.close()
+    del s
+
+    # the same workload with split-FP16 matrix-core products
+    s16, _, ms16, kms16, kcnt16, state16 = run(hdg.PREC_FP16X2, dt)
+    gdofs16 = dofs * stages / (ms16 * 1e-3) / 1e9
+    num = sum(float(((state16[t].double() - state32[t].double()) ** 2).sum()) for t in types)
+    den = sum(float((state32[t].double() ** 2).sum()) for t in types)
+    mixed = {
+        "precision": "split FP16 operands (hi + lo, power-of-two scales), FP32 accumulation, 16x16x32 MFMA, "
+                     "tetrahedra; other types FP32",
+        "value": round(gdofs16, 4),
+        "unit": "GDOF/s",
+        "speedup_vs_fp32_plain": round(gdofs16 / gdofs, 4),
+        "stage_ms": round(ms16 / stages, 4),
+        "kernel_ms_per_launch": {name: round(float(kms16[t] / max(kcnt16[t], 1)), 4)
+                                 for t, name in ((0, "hex"), (1, "wedge"), (2, "pyr"), (3, "tet")) if kcnt16[t]},
+        "rel_l2_vs_fp32_path": math.sqrt(num / den),
+        "steps_compared": args.warmup + args.steps + prof_steps,
+    }
+    s16.close()
+    del s16
 
     out = {
         "metric": "GDOF/s per RK stage: mixed-precision vs FP32 plain, at rel L2 <= 1e-5 vs FP64",
@@ -196,12 +225,13 @@ def main():
         "config": {
             "workload": f"four-slab hybrid mesh n={args.n} (jitter 0.1h, seed 0), N={N}, Gaussian pulse, "
                         f"rigid walls, single-rate LSERK4, FP32 plain",
-            "elements": {name: int(s.info[t][0]) for t, name in ((0, "hex"), (1, "wedge"), (2, "pyr"), (3, "tet"))},
+            "elements": {name: int(info[t][0]) for t, name in ((0, "hex"), (1, "wedge"), (2, "pyr"), (3, "tet"))},
             "dofs_per_field": int(dofs),
             "dt": dt,
             "stage_ms": round(ms / stages, 4),
             "kernel_ms_per_launch": per_type,
             "energy_after": E,
+            "mixed_precision": mixed,
         },
         "roofline": {
             "bound": "hbm",
@@ -210,7 +240,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(tet_kernel),
+            "traffic": measured_traffic(tet_kernel, ", 0>" if lattice else ""),
             "alg_bytes_per_launch": int(alg_bytes),
         },
     }

@@ -84,6 +84,7 @@ struct hdg_ctx {
   bool traces_valid = false;
   bool lattice_ok = false;     // no triangular face joins a wedge to a tet or pyramid
   int path = HDG_PATH_AUTO;
+  int prec = HDG_PREC_FP32;    // operand precision of the matrix-core products
   int max_blocks = 1024;       // cap of persistent grids (4 per compute unit)
   GeoTables* gtab = nullptr;
   double* partial = nullptr;
@@ -209,15 +210,66 @@ int build_tables(hdg_ctx* c, int t, std::vector<float>& ops, std::vector<int>& i
   return HDG_OK;
 }
 
+// MFMA A-fragments of a row-major R x C matrix, appended to out: for each
+// 16-row tile t and k-step s (K = kk per instruction), piece pc and lane l,
+// the ki entries A[16t + l%16][kk s + ki (l/16) + i] (0 outside the matrix).
+// Precision 0 stores FP32 values; otherwise x = sc A is stored as two FP16
+// pieces hi = fp16(x), lo = fp16(x - hi).
+void pack_frags(const double* A, int R, int C, int P, double sc, std::vector<float>& out) {
+  int kk, ki, npc;
+  tet_mfma_frag_shape(P, &kk, &ki, &npc);
+  const int Mt = (R + 15) / 16, Ks = (C + kk - 1) / kk;
+  auto at = [&](int t, int s, int l, int i) {
+    const int row = 16 * t + l % 16, col = kk * s + ki * (l / 16) + i;
+    return row < R && col < C ? A[(size_t)row * C + col] : 0.0;
+  };
+  if (P == 0) {
+    for (int t = 0; t < Mt; ++t)
+      for (int s = 0; s < Ks; ++s)
+        for (int l = 0; l < 64; ++l) out.push_back((float)at(t, s, l, 0));
+    return;
+  }
+  std::vector<uint16_t> h;
+  for (int t = 0; t < Mt; ++t)
+    for (int s = 0; s < Ks; ++s)
+      for (int pc = 0; pc < npc; ++pc)
+        for (int l = 0; l < 64; ++l)
+          for (int i = 0; i < ki; ++i) {
+            const double x = at(t, s, l, i) * sc;
+            const _Float16 hi = (_Float16)x;
+            const _Float16 v = pc == 0 ? hi : (_Float16)(x - (double)hi);
+            uint16_t bits;
+            std::memcpy(&bits, &v, 2);
+            h.push_back(bits);
+          }
+  const size_t o = out.size();
+  out.resize(o + h.size() / 2);
+  std::memcpy(out.data() + o, h.data(), h.size() * 2);
+}
+
+// Packs nmat consecutive R x C matrices with one scale for the group (a power
+// of two bringing the group maximum into [2^13, 2^14)); returns 1/scale.
+double pack_group(const std::vector<double>& all, int nmat, int R, int C, int P, std::vector<float>& out) {
+  double sc = 1.0;
+  if (P != 0) {
+    double m = 0.0;
+    for (double v : all) m = std::max(m, std::fabs(v));
+    int e = 0;
+    std::frexp(m > 0.0 ? m : 1.0, &e);
+    sc = std::ldexp(1.0, 14 - e);
+  }
+  for (int k = 0; k < nmat; ++k) pack_frags(all.data() + (size_t)k * R * C, R, C, P, sc, out);
+  return 1.0 / sc;
+}
+
 // Tables of the matrix-core tetrahedron kernel: D^{r,s,t} and the lattice
-// lift matrices L_f = M^-1 E_f M_f in MFMA fragment order, where
+// lift matrices L_f = M^-1 E_f M_f as MFMA fragments of precision P, where
 // M_f = Ican^T W Ican is the mass matrix of the face lattice (exact: the
 // canonical rule integrates degree 2N on the triangle).
-int build_tet_mfma_tables(hdg_ctx* c, std::vector<float>& ops, std::vector<int>& iops) {
+int build_tet_mfma_tables(hdg_ctx* c, int P, std::vector<float>& ops, std::vector<int>& iops) {
   const TetRef& T = c->tet;
   const FaceTables& ft = c->ft;
   const int Np = T.Np, Nfn = ft.Nfn, Nfq = ft.Nfq;
-  const int Mt = (Np + 15) / 16, Ks = (Np + 3) / 4, Kf = (Nfn + 3) / 4;
   std::vector<double> Mf((size_t)Nfn * Nfn, 0.0);
   for (int q = 0; q < Nfq; ++q)
     for (int x = 0; x < Nfn; ++x)
@@ -226,10 +278,10 @@ int build_tet_mfma_tables(hdg_ctx* c, std::vector<float>& ops, std::vector<int>&
   for (double v : Mf) mx = std::max(mx, std::fabs(v));
   // the lattice is symmetric: M_f must not depend on the face frame
   for (int o = 0; o < 6; ++o) {
-    const int* P = &ft.tri_perm[o * Nfn];
+    const int* Pm = &ft.tri_perm[o * Nfn];
     for (int x = 0; x < Nfn; ++x)
       for (int y = 0; y < Nfn; ++y)
-        if (std::fabs(Mf[P[x] * Nfn + P[y]] - Mf[x * Nfn + y]) > 1e-10 * mx)
+        if (std::fabs(Mf[Pm[x] * Nfn + Pm[y]] - Mf[x * Nfn + y]) > 1e-10 * mx)
           return fail(c, HDG_EINVAL, "internal: face lattice mass matrix is not permutation invariant");
   }
   std::vector<double> L((size_t)4 * Np * Nfn, 0.0);
@@ -240,27 +292,18 @@ int build_tet_mfma_tables(hdg_ctx* c, std::vector<float>& ops, std::vector<int>&
         for (int j = 0; j < Nfn; ++j) acc += T.Minv[(size_t)i * Np + T.fnode[f * Nfn + j]] * Mf[j * Nfn + l];
         L[((size_t)f * Np + i) * Nfn + l] = acc;
       }
+  std::vector<double> Dall;
+  for (const Vec* D : {&T.Dr, &T.Ds, &T.Dt}) Dall.insert(Dall.end(), D->begin(), D->end());
   ops.clear();
   iops.clear();
-  const Vec* D[3] = {&T.Dr, &T.Ds, &T.Dt};
-  for (int r = 0; r < 3; ++r)
-    for (int t = 0; t < Mt; ++t)
-      for (int s = 0; s < Ks; ++s)
-        for (int lane = 0; lane < 64; ++lane) {
-          const int row = 16 * t + lane % 16, col = 4 * s + lane / 16;
-          ops.push_back(row < Np && col < Np ? (float)(*D[r])[(size_t)row * Np + col] : 0.0f);
-        }
-  for (int f = 0; f < 4; ++f)
-    for (int t = 0; t < Mt; ++t)
-      for (int s = 0; s < Kf; ++s)
-        for (int lane = 0; lane < 64; ++lane) {
-          const int row = 16 * t + lane % 16, col = 4 * s + lane / 16;
-          ops.push_back(row < Np && col < Nfn ? (float)L[((size_t)f * Np + row) * Nfn + col] : 0.0f);
-        }
+  const double iD = pack_group(Dall, 3, Np, Np, P, ops);
+  const double iL = pack_group(L, 4, Np, Nfn, P, ops);
+  ops.push_back((float)iD);
+  ops.push_back((float)iL);
   iops.insert(iops.end(), T.fnode.begin(), T.fnode.end());
   iops.insert(iops.end(), ft.tri_perm.begin(), ft.tri_perm.end());
   int nf = 0, ni = 0;
-  tet_mfma_table_sizes(c->N, &nf, &ni);
+  tet_mfma_table_sizes(c->N, P, &nf, &ni);
   if ((int)ops.size() != nf || (int)iops.size() != ni)
     return fail(c, HDG_EINVAL, "internal: matrix-core table size mismatch");
   return HDG_OK;
@@ -276,7 +319,7 @@ int launch_type(hdg_ctx* c, int t, StageArgs a, bool mrab) {
     a.ops = c->td[t].mops;
     a.iops = c->td[t].miops;
     if (mrab) a.mode = kModeMrab;
-    if (launch_tet_mfma(c->N, a, c->stream, c->max_blocks)) return fail(c, HDG_EINVAL, "no kernel for this order");
+    if (launch_tet_mfma(c->N, c->prec, a, c->stream, c->max_blocks)) return fail(c, HDG_EINVAL, "no kernel for this order");
     return HDG_OK;
   }
   const int r = mrab ? launch_mrab_update(t, c->N, a, c->stream) : launch_stage(t, c->N, a, c->stream);
@@ -623,7 +666,7 @@ int create_impl(hdg_ctx* c, const hdg_mesh* m, int N) {
     if ((rc = upload(c, &d.ops, ops))) return rc;
     if ((rc = upload(c, &d.iops, iops))) return rc;
     if (t == kTet) {
-      if ((rc = build_tet_mfma_tables(c, ops, iops))) return rc;
+      if ((rc = build_tet_mfma_tables(c, c->prec, ops, iops))) return rc;
       if ((rc = upload(c, &d.mops, ops))) return rc;
       if ((rc = upload(c, &d.miops, iops))) return rc;
     }
@@ -657,12 +700,14 @@ int hdg_create(hdg_ctx** out, const hdg_mesh* m, int N, int precision, void* hip
   if (!m || !m->xyz || !m->type || !m->verts || !m->kappa || !m->rho)
     return fail(nullptr, HDG_EINVAL, "mesh or one of its arrays is NULL");
   if (N < 1 || N > kMaxN) return fail(nullptr, HDG_EINVAL, "order N must be in [1, 5]");
-  if (precision != HDG_PREC_FP32) return fail(nullptr, HDG_EINVAL, "unsupported precision mode");
+  if (precision != HDG_PREC_FP32 && precision != HDG_PREC_FP16X2 && precision != HDG_PREC_FP16X2_K16)
+    return fail(nullptr, HDG_EINVAL, "unsupported precision mode");
   if (m->n_elem < 1 || m->n_vert < 1) return fail(nullptr, HDG_EINVAL, "empty mesh");
   if (m->bc != HDG_BC_FREE_SURFACE && m->bc != HDG_BC_RIGID_WALL)
     return fail(nullptr, HDG_EINVAL, "unknown boundary condition");
   hdg_ctx* c = new hdg_ctx();
   c->stream = (hipStream_t)hip_stream;
+  c->prec = precision;
   int rc;
   try {
     rc = create_impl(c, m, N);

@@ -55,10 +55,14 @@ int launch_mrab_update(int type, int N, const StageArgs& a, hipStream_t s);
 void stage_table_sizes(int type, int N, int* n_floats, int* n_ints);
 int stage_batch(int type, int N);
 // Tetrahedra on the matrix cores with lattice traces (all modes, including
-// kModeMrab); max_blocks caps the persistent grid.
-int launch_tet_mfma(int N, const StageArgs& a, hipStream_t s, int max_blocks);
-// Packed table sizes: D fragments [3][Mt][Ks][64], lift fragments
-// [4][Mt][Kf][64]; fnode [4][Nfn], tperm [6][Nfn].
-void tet_mfma_table_sizes(int N, int* n_floats, int* n_ints);
+// kModeMrab); P is the operand precision (0 FP32, 1 split FP16 16x16x32,
+// 2 split FP16 16x16x16); max_blocks caps the persistent grid.
+int launch_tet_mfma(int N, int P, const StageArgs& a, hipStream_t s, int max_blocks);
+// Packed table sizes (in floats): D fragments [3][Mt][Ks][pieces][64][KI],
+// lift fragments [4][Mt][Kf][pieces][64][KI], then 1/s_D and 1/s_L;
+// integers fnode [4][Nfn], tperm [6][Nfn].
+void tet_mfma_table_sizes(int N, int P, int* n_floats, int* n_ints);
+// Fragment geometry of precision P: K per instruction, entries per lane, pieces.
+void tet_mfma_frag_shape(int P, int* kk, int* ki, int* npc);
 
 }  // namespace hdg

@@ -15,10 +15,20 @@ __global__ __launch_bounds__(S::NT) void tet_mfma_kernel(StageArgs a) {
   S::run(sm, a);
 }
 
-// wavefronts per block: LDS holds the operator fragments once per block
-constexpr int tet_waves(int N) { return N <= 4 ? 8 : 4; }
-template <int N>
-using TetM = TetMfma<N, tet_waves(N)>;
+// wavefronts per block: as many as fit the LDS (operator fragments are held
+// once per block)
+template <int N, int P, int NW>
+constexpr bool tet_fits() {
+  return sizeof(typename TetMfma<N, NW, P>::Smem) <= 160 * 1024;
+}
+// (split-precision kernels above N = 3 need more than the 256 registers a
+// lane gets at 8 wavefronts per block)
+template <int N, int P>
+constexpr int tet_waves() {
+  return (tet_fits<N, P, 8>() && (P == 0 || N <= 3)) ? 8 : (tet_fits<N, P, 4>() ? 4 : 2);
+}
+template <int N, int P>
+using TetM = TetMfma<N, tet_waves<N, P>(), P>;
 
 template <class S>
 static int go_mfma(const StageArgs& a, hipStream_t s, int max_blocks) {
@@ -31,26 +41,49 @@ static int go_mfma(const StageArgs& a, hipStream_t s, int max_blocks) {
   return 0;
 }
 
-int launch_tet_mfma(int N, const StageArgs& a, hipStream_t s, int max_blocks) {
-  if (max_blocks < 1) max_blocks = 1;
+template <int P>
+static int launch_p(int N, const StageArgs& a, hipStream_t s, int max_blocks) {
   switch (N) {
-    case 1: return go_mfma<TetM<1>>(a, s, max_blocks);
-    case 2: return go_mfma<TetM<2>>(a, s, max_blocks);
-    case 3: return go_mfma<TetM<3>>(a, s, max_blocks);
-    case 4: return go_mfma<TetM<4>>(a, s, max_blocks);
-    case 5: return go_mfma<TetM<5>>(a, s, max_blocks);
+    case 1: return go_mfma<TetM<1, P>>(a, s, max_blocks);
+    case 2: return go_mfma<TetM<2, P>>(a, s, max_blocks);
+    case 3: return go_mfma<TetM<3, P>>(a, s, max_blocks);
+    case 4: return go_mfma<TetM<4, P>>(a, s, max_blocks);
+    case 5: return go_mfma<TetM<5, P>>(a, s, max_blocks);
   }
   return -1;
 }
 
-void tet_mfma_table_sizes(int N, int* nf, int* ni) {
-  switch (N) {
-    case 1: *nf = TetM<1>::kOpsFloats; *ni = TetM<1>::kOpsInts; break;
-    case 2: *nf = TetM<2>::kOpsFloats; *ni = TetM<2>::kOpsInts; break;
-    case 3: *nf = TetM<3>::kOpsFloats; *ni = TetM<3>::kOpsInts; break;
-    case 4: *nf = TetM<4>::kOpsFloats; *ni = TetM<4>::kOpsInts; break;
-    default: *nf = TetM<5>::kOpsFloats; *ni = TetM<5>::kOpsInts; break;
+int launch_tet_mfma(int N, int P, const StageArgs& a, hipStream_t s, int max_blocks) {
+  if (max_blocks < 1) max_blocks = 1;
+  switch (P) {
+    case 0: return launch_p<0>(N, a, s, max_blocks);
+    case 1: return launch_p<1>(N, a, s, max_blocks);
+    case 2: return launch_p<2>(N, a, s, max_blocks);
   }
+  return -1;
+}
+
+template <int P>
+static void sizes_p(int N, int* nf, int* ni) {
+  switch (N) {
+    case 1: *nf = TetM<1, P>::kOpsFloats; *ni = TetM<1, P>::kOpsInts; break;
+    case 2: *nf = TetM<2, P>::kOpsFloats; *ni = TetM<2, P>::kOpsInts; break;
+    case 3: *nf = TetM<3, P>::kOpsFloats; *ni = TetM<3, P>::kOpsInts; break;
+    case 4: *nf = TetM<4, P>::kOpsFloats; *ni = TetM<4, P>::kOpsInts; break;
+    default: *nf = TetM<5, P>::kOpsFloats; *ni = TetM<5, P>::kOpsInts; break;
+  }
+}
+
+void tet_mfma_frag_shape(int P, int* kk, int* ki, int* npc) {
+  if (P == 1) { *kk = Prec<1>::KK; *ki = Prec<1>::KI; *npc = Prec<1>::NPC; }
+  else if (P == 2) { *kk = Prec<2>::KK; *ki = Prec<2>::KI; *npc = Prec<2>::NPC; }
+  else { *kk = Prec<0>::KK; *ki = Prec<0>::KI; *npc = Prec<0>::NPC; }
+}
+
+void tet_mfma_table_sizes(int N, int P, int* nf, int* ni) {
+  if (P == 1) sizes_p<1>(N, nf, ni);
+  else if (P == 2) sizes_p<2>(N, nf, ni);
+  else sizes_p<0>(N, nf, ni);
 }
 
 }  // namespace hdg

@@ -32,11 +32,73 @@
 namespace hdg {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // D = A B + C for 16x16 tiles, K = 4: lane l passes A[l%16][l/16] and
 // B[l/16][l%16] and holds D[4(l/16)+i][l%16] in component i.
 __device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// FP16 operands, FP32 accumulation: 16x16x16 (lane l passes A[l%16][4(l/16)+i]
+// and B[4(l/16)+i][l%16], i < 4) and 16x16x32 (A[l%16][8(l/16)+i],
+// B[8(l/16)+i][l%16], i < 8); the result layout is that of mma_f32.
+__device__ __forceinline__ f32x4 mma_f16(f16x4 a, f16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mma_f16(f16x8 a, f16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// Operand precision of the element-batched operator products.
+//   0: FP32 operands (16x16x4).
+//   1: split FP16, 16x16x32: x = hi + lo with hi = fp16(s x), lo = fp16(s x - hi)
+//      for a power-of-two scale s per operator and per element column, so
+//      each operand carries about 22 significant bits; A B is formed as
+//      hi hi + hi lo + lo hi with FP32 accumulation.
+//   2: the same split with 16x16x16 instructions (less padding of K).
+template <int P>
+struct Prec;
+template <>
+struct Prec<0> {
+  static constexpr int KI = 1, KK = 4, NPC = 1;
+  typedef float V;
+};
+template <>
+struct Prec<1> {
+  static constexpr int KI = 8, KK = 32, NPC = 2;
+  typedef f16x8 V;
+};
+template <>
+struct Prec<2> {
+  static constexpr int KI = 4, KK = 16, NPC = 2;
+  typedef f16x4 V;
+};
+
+// Power of two that brings a column maximum m into [2^14, 2^15) (1 for m = 0).
+__device__ __forceinline__ float col_scale(float m) {
+  if (!(m > 0.f)) return 1.f;
+  int e;
+  frexpf(m, &e);
+  e = 15 - e;
+  e = e < -120 ? -120 : (e > 120 ? 120 : e);
+  return ldexpf(1.f, e);
+}
+// Maximum over the four lanes of a column (lanes n, n+16, n+32, n+48).
+__device__ __forceinline__ float col_max(float m) {
+  m = fmaxf(m, __shfl_xor(m, 16));
+  return fmaxf(m, __shfl_xor(m, 32));
+}
+template <class V, int KI>
+__device__ __forceinline__ void split_f16(const float (&v)[KI], float sc, V& hi, V& lo) {
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const float x = v[i] * sc;
+    const _Float16 h = (_Float16)x;
+    hi[i] = h;
+    lo[i] = (_Float16)(x - (float)h);
+  }
 }
 
 // LDS writes of this wavefront become visible to its later LDS reads (LDS
@@ -58,8 +120,12 @@ __device__ __forceinline__ float4 lattice_neighbour(const StageArgs& a, int64_t 
   return neighbour_src(a, slot, nb)[(int64_t)nb * nfq + m];
 }
 
-template <int N, int NW>
+template <int N, int NW, int P>
 struct TetMfma {
+  typedef Prec<P> PR;
+  typedef typename PR::V V;
+  static constexpr int KI = PR::KI, KK = PR::KK, NPC = PR::NPC;
+  static constexpr int VF = (int)(sizeof(V) / sizeof(float));  // floats per fragment entry
   static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
   static constexpr int Nfn = (N + 1) * (N + 2) / 2;
   static constexpr int Nfq = (N + 1) * (N + 1);
@@ -69,9 +135,11 @@ struct TetMfma {
   static constexpr int SX = (4 * Ks) | 1;    // odd row strides, padded rows stay zero
   static constexpr int SF = (4 * Kf) | 1;
   static constexpr int NT = 64 * NW;
-  static constexpr int kDFloats = 3 * Mt * Ks * 64;
-  static constexpr int kLFloats = 4 * Mt * Kf * 64;
-  static constexpr int kOpsFloats = kDFloats + kLFloats;
+  static constexpr int KsP = (Np + KK - 1) / KK;   // k-steps over nodes at this precision
+  static constexpr int KfP = (Nfn + KK - 1) / KK;  // k-steps over a face lattice
+  static constexpr int kDFloats = 3 * Mt * KsP * NPC * 64 * VF;
+  static constexpr int kLFloats = 4 * Mt * KfP * NPC * 64 * VF;
+  static constexpr int kOpsFloats = kDFloats + kLFloats + 2;  // + inverse operator scales
   static constexpr int kOpsInts = 4 * Nfn + 6 * Nfn;
 
   struct Wave {
@@ -81,8 +149,9 @@ struct TetMfma {
   static_assert(4 * 16 * SF >= 16 * SX, "output staging does not fit the flux buffer");
 
   struct Smem {
-    float D[3][Mt][Ks][64];
-    float L[4][Mt][Kf][64];
+    V D[3][Mt][KsP][NPC][64];
+    V L[4][Mt][KfP][NPC][64];
+    float inv_sD, inv_sL;
     int fnode[4][Nfn];  // element node of local face lattice node
     int tperm[6][Nfn];  // canonical lattice node -> local lattice node
     Wave w[NW];
@@ -254,6 +323,42 @@ struct TetMfma {
     write_traces(sm, W, a, e0, lane, rec, a.tr_out);
   }
 
+  // acc += L_f F (one field) with split FP16 operands and a column scale.
+  __device__ static void lift_f16(const Smem& sm, const Wave& W, int f, int n, int g, int lane,
+                                  const float (*Fc)[SF], f32x4 (&acc)[Mt]) {
+    float mf = 0.f;
+#pragma unroll
+    for (int j = 0; j < JF; ++j) {
+      const int l = g + 4 * j;
+      if (l < Nfn) mf = fmaxf(mf, fabsf(Fc[n][l]));
+    }
+    const float sf = col_scale(col_max(mf));
+    f32x4 tmp[Mt];
+#pragma unroll
+    for (int t = 0; t < Mt; ++t) tmp[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KfP; ++s) {
+      float v[KI];
+#pragma unroll
+      for (int i = 0; i < KI; ++i) {
+        const int k = KK * s + KI * g + i;
+        v[i] = k < Nfn ? Fc[n][k < Nfn ? k : 0] : 0.f;
+      }
+      V bh, bl;
+      split_f16<V, KI>(v, sf, bh, bl);
+#pragma unroll
+      for (int t = 0; t < Mt; ++t) {
+        const V ah = sm.L[f][t][s][0][lane], al = sm.L[f][t][s][1][lane];
+        tmp[t] = mma_f16(ah, bh, tmp[t]);
+        tmp[t] = mma_f16(ah, bl, tmp[t]);
+        tmp[t] = mma_f16(al, bh, tmp[t]);
+      }
+    }
+    const float gs = sm.inv_sL / sf;
+#pragma unroll
+    for (int t = 0; t < Mt; ++t) acc[t] += tmp[t] * gs;
+  }
+
   // Output of field C: rhs = sc * acc at rows 16 t + 4 g + i of column n,
   // then the stage update (res = a res + dt rhs, u += b res) or the rhs store.
   template <int C>
@@ -345,20 +450,69 @@ struct TetMfma {
       for (int r = 0; r < 3; ++r) accG[r][t] = accP[t];
     }
     // volume
+    if constexpr (P == 0) {
 #pragma unroll 2
-    for (int s = 0; s < Ks; ++s) {
-      const int k = 4 * s + g;
-      const float p = W.X[0][n][k], u1 = W.X[1][n][k], u2 = W.X[2][n][k], u3 = W.X[3][n][k];
-      float ut[3];
-      for (int r = 0; r < 3; ++r) ut[r] = -(G[3 * r] * u1 + G[3 * r + 1] * u2 + G[3 * r + 2] * u3);
+      for (int s = 0; s < Ks; ++s) {
+        const int k = 4 * s + g;
+        const float p = W.X[0][n][k], u1 = W.X[1][n][k], u2 = W.X[2][n][k], u3 = W.X[3][n][k];
+        float ut[3];
+        for (int r = 0; r < 3; ++r) ut[r] = -(G[3 * r] * u1 + G[3 * r + 1] * u2 + G[3 * r + 2] * u3);
 #pragma unroll
-      for (int t = 0; t < Mt; ++t)
+        for (int t = 0; t < Mt; ++t)
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          const float d = sm.D[r][t][s][lane];
-          accG[r][t] = mma_f32(d, p, accG[r][t]);
-          accP[t] = mma_f32(d, ut[r], accP[t]);
+          for (int r = 0; r < 3; ++r) {
+            const float d = sm.D[r][t][s][0][lane];
+            accG[r][t] = mma_f32(d, p, accG[r][t]);
+            accP[t] = mma_f32(d, ut[r], accP[t]);
+          }
+      }
+    } else {
+      // column scales of p and of the contravariant velocities
+      float mp = 0.f, mu = 0.f;
+      for (int k = g; k < Np; k += 4) {
+        const float u1 = W.X[1][n][k], u2 = W.X[2][n][k], u3 = W.X[3][n][k];
+        mp = fmaxf(mp, fabsf(W.X[0][n][k]));
+#pragma unroll
+        for (int r = 0; r < 3; ++r) mu = fmaxf(mu, fabsf(G[3 * r] * u1 + G[3 * r + 1] * u2 + G[3 * r + 2] * u3));
+      }
+      const float sp = col_scale(col_max(mp)), su = col_scale(col_max(mu));
+#pragma unroll 1
+      for (int s = 0; s < KsP; ++s) {
+        float pv[KI], uv[3][KI];
+#pragma unroll
+        for (int i = 0; i < KI; ++i) {
+          const int k = KK * s + KI * g + i;
+          const bool in = k < Np;
+          const int kk = in ? k : 0;
+          const float u1 = W.X[1][n][kk], u2 = W.X[2][n][kk], u3 = W.X[3][n][kk];
+          pv[i] = in ? W.X[0][n][kk] : 0.f;
+#pragma unroll
+          for (int r = 0; r < 3; ++r) uv[r][i] = in ? -(G[3 * r] * u1 + G[3 * r + 1] * u2 + G[3 * r + 2] * u3) : 0.f;
         }
+        V ph, pl, uh[3], ul[3];
+        split_f16<V, KI>(pv, sp, ph, pl);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) split_f16<V, KI>(uv[r], su, uh[r], ul[r]);
+#pragma unroll
+        for (int t = 0; t < Mt; ++t)
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            const V ah = sm.D[r][t][s][0][lane], al = sm.D[r][t][s][1][lane];
+            accG[r][t] = mma_f16(ah, ph, accG[r][t]);
+            accG[r][t] = mma_f16(ah, pl, accG[r][t]);
+            accG[r][t] = mma_f16(al, ph, accG[r][t]);
+            accP[t] = mma_f16(ah, uh[r], accP[t]);
+            accP[t] = mma_f16(ah, ul[r], accP[t]);
+            accP[t] = mma_f16(al, uh[r], accP[t]);
+          }
+      }
+      const float gp = sm.inv_sD / sp, gu = sm.inv_sD / su;
+#pragma unroll
+      for (int t = 0; t < Mt; ++t) {
+        accP[t] *= gu;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) accG[r][t] *= gp;
+      }
     }
     // velocity rhs accumulators start from the physical pressure gradient
     f32x4 accL[3][Mt];
@@ -404,18 +558,25 @@ struct TetMfma {
         for (int c = 0; c < 4; ++c) W.F[c][n][l] = out[c] * iJ;
       }
       wave_sync();
+      if constexpr (P == 0) {
 #pragma unroll
-      for (int s = 0; s < Kf; ++s) {
-        const int k = 4 * s + g;
-        const float b0 = W.F[0][n][k], b1 = W.F[1][n][k], b2 = W.F[2][n][k], b3 = W.F[3][n][k];
+        for (int s = 0; s < Kf; ++s) {
+          const int k = 4 * s + g;
+          const float b0 = W.F[0][n][k], b1 = W.F[1][n][k], b2 = W.F[2][n][k], b3 = W.F[3][n][k];
 #pragma unroll
-        for (int t = 0; t < Mt; ++t) {
-          const float lf = sm.L[f][t][s][lane];
-          accP[t] = mma_f32(lf, b0, accP[t]);
-          accL[0][t] = mma_f32(lf, b1, accL[0][t]);
-          accL[1][t] = mma_f32(lf, b2, accL[1][t]);
-          accL[2][t] = mma_f32(lf, b3, accL[2][t]);
+          for (int t = 0; t < Mt; ++t) {
+            const float lf = sm.L[f][t][s][0][lane];
+            accP[t] = mma_f32(lf, b0, accP[t]);
+            accL[0][t] = mma_f32(lf, b1, accL[0][t]);
+            accL[1][t] = mma_f32(lf, b2, accL[1][t]);
+            accL[2][t] = mma_f32(lf, b3, accL[2][t]);
+          }
         }
+      } else {
+        lift_f16(sm, W, f, n, g, lane, W.F[0], accP);
+        lift_f16(sm, W, f, n, g, lane, W.F[1], accL[0]);
+        lift_f16(sm, W, f, n, g, lane, W.F[2], accL[1]);
+        lift_f16(sm, W, f, n, g, lane, W.F[3], accL[2]);
       }
       wave_sync();
     }
@@ -429,8 +590,14 @@ struct TetMfma {
 
   __device__ static void run(Smem& sm, const StageArgs& a) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int i = tid; i < kDFloats; i += NT) (&sm.D[0][0][0][0])[i] = a.ops[i];
-    for (int i = tid; i < kLFloats; i += NT) (&sm.L[0][0][0][0])[i] = a.ops[kDFloats + i];
+    float* dD = reinterpret_cast<float*>(&sm.D[0][0][0][0][0]);
+    float* dL = reinterpret_cast<float*>(&sm.L[0][0][0][0][0]);
+    for (int i = tid; i < kDFloats; i += NT) dD[i] = a.ops[i];
+    for (int i = tid; i < kLFloats; i += NT) dL[i] = a.ops[kDFloats + i];
+    if (tid == 0) {
+      sm.inv_sD = a.ops[kDFloats + kLFloats];
+      sm.inv_sL = a.ops[kDFloats + kLFloats + 1];
+    }
     for (int i = tid; i < 4 * Nfn; i += NT) (&sm.fnode[0][0])[i] = a.iops[i];
     for (int i = tid; i < 6 * Nfn; i += NT) (&sm.tperm[0][0])[i] = a.iops[4 * Nfn + i];
     // padded rows and columns of the tiles must hold finite values

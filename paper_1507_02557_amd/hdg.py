@@ -15,7 +15,7 @@ import torch
 
 HEX, WEDGE, PYR, TET = 0, 1, 2, 3
 BC_FREE_SURFACE, BC_RIGID_WALL = 0, 1
-PREC_FP32 = 0
+PREC_FP32, PREC_FP16X2, PREC_FP16X2_K16 = 0, 1, 2
 PATH_AUTO, PATH_GENERIC = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))

@@ -282,3 +282,53 @@ def test_wedge_tet_face_falls_back_to_cubature_traces():
     Rl = {t: v.double().cpu().numpy() for t, v in s.rhs().items()}
     err = type_rel_err(Rl, d.rhs(U))
     assert max(err.values()) < TOL_RHS, err
+
+
+PRECS = [hdg.PREC_FP16X2, hdg.PREC_FP16X2_K16]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5])
+def test_split_precision_rhs_matches_oracle(c1_mesh, N, prec):
+    """Split-FP16 matrix-core products: the right-hand side stays within the
+    FP32 tolerance of the FP64 oracle."""
+    d = Disc(c1_mesh, N)
+    s = hdg.Solver(c1_mesh, N, precision=prec)
+    U = random_state(d, seed=20 + N)
+    set_lib_state(s, U)
+    Rl = {t: v.double().cpu().numpy() for t, v in s.rhs().items()}
+    err = type_rel_err(Rl, d.rhs(U))
+    print("prec", prec, "N", N, "rel err per type", err)
+    assert max(err.values()) < TOL_RHS, err
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_split_precision_c1_100_steps(c1_mesh, prec):
+    """Configuration 1 with split-FP16 products: rel L2 <= 1e-5 after 100 steps."""
+    d = Disc(c1_mesh, 3)
+    s = hdg.Solver(c1_mesh, 3, precision=prec)
+    dt = d.dt_min(0.5)
+    Uo = d.project(standing_mode_rigid)
+    s.project_function(standing_mode_rigid)
+    for _ in range(100):
+        Uo = lserk4_step(d, Uo, dt)
+    s.step(dt, 100)
+    rel = d.rel_l2(lib_state_to_oracle(s), Uo)
+    print("prec", prec, "C1 rel L2 after 100 steps:", rel)
+    assert rel < 1e-5
+
+
+def test_split_precision_mrab(c1_mesh):
+    from oracle.mrab import MRAB3
+    d = Disc(c1_mesh, 3)
+    mr = MRAB3(d, 3)
+    s = hdg.Solver(c1_mesh, 3, precision=hdg.PREC_FP16X2)
+    s.mrab_setup(3)
+    U = mr.startup(d.project(standing_mode_rigid))
+    s.project_function(standing_mode_rigid)
+    s.mrab_advance(0)
+    for _ in range(2):
+        U = mr.coarse_step(U)
+    s.mrab_advance(2)
+    assert d.rel_l2(lib_state_to_oracle(s), U) < 1e-5
+

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_function():
     assert sorted(hdg.EXPORTS) == declared
 
 
-def _create(mesh, N=2, bc=1):
+def _create(mesh, N=2, bc=1, precision=0):
     lib = hdg.load_library()
     xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float64)
     et = np.ascontiguousarray(mesh.etype, dtype=np.int8)
@@ -41,7 +41,7 @@ def _create(mesh, N=2, bc=1):
     m = hdg.HdgMesh(xyz.shape[0], xyz.ctypes.data, et.shape[0], et.ctypes.data, ev.ctypes.data,
                     ka.ctypes.data, rh.ctypes.data, bc)
     h = ctypes.c_void_p()
-    rc = lib.hdg_create(ctypes.byref(h), ctypes.byref(m), N, 0, None)
+    rc = lib.hdg_create(ctypes.byref(h), ctypes.byref(m), N, precision, None)
     return rc, h, lib.hdg_last_error(None).decode()
 
 
@@ -61,6 +61,12 @@ XYZ = [[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [0, 0, -1], [1, 1, 1]]
 def test_create_rejects_unsupported_order(N):
     rc, h, msg = _create(_tets([[0, 1, 2, 3]], XYZ), N=N)
     assert rc == -1 and not h.value and "order" in msg
+
+
+@pytest.mark.parametrize("precision", [-1, 3, 7])
+def test_create_rejects_unknown_precision(precision):
+    rc, h, msg = _create(_tets([[0, 1, 2, 3]], XYZ), precision=precision)
+    assert rc == -1 and not h.value and "precision" in msg
 
 
 def test_create_rejects_non_manifold_face():
