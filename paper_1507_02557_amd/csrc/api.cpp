@@ -47,7 +47,7 @@ struct TypeData {
   double* V = nullptr;         // [K][nv][3]
   float* ops = nullptr;
   int* iops = nullptr;
-  float* mops = nullptr;       // tetrahedra: matrix-core kernel tables
+  float* mops = nullptr;       // matrix-core kernel tables (tetrahedra, pyramids)
   int* miops = nullptr;
   double* spts = nullptr;      // sample reference points [nsample][3]
   double* sw = nullptr;        // sample weights (wedge, pyramid)
@@ -309,12 +309,81 @@ int build_tet_mfma_tables(hdg_ctx* c, int P, std::vector<float>& ops, std::vecto
   return HDG_OK;
 }
 
+// Tables of the matrix-core pyramid kernel: D^{r,s,t}, the base-face basis
+// Fq and the triangle-face bases Ft_f as rows with an odd stride (zero
+// padded), the lattice lift fragments Ft_f^T M_f, the canonical triangle
+// weight of point 0, the geometry points (a, b) as doubles; the base and
+// lattice orientation permutations and their inverses.
+int build_pyr_mfma_tables(hdg_ctx* c, std::vector<float>& ops, std::vector<int>& iops) {
+  const PyrRef& P = c->pyr;
+  const FaceTables& ft = c->ft;
+  const int Np = P.Np, Nfn = ft.Nfn, Nfq = ft.Nfq;
+  const int SD = Np | 1, Mt = (Np + 15) / 16, Kf = (Nfn + 3) / 4;
+  int nf = 0, ni = 0;
+  if (pyr_mfma_table_sizes(c->N, &nf, &ni)) return fail(c, HDG_EINVAL, "internal: no pyramid matrix-core kernel");
+  ops.clear();
+  iops.clear();
+  auto rows = [&](const Vec& A, int R) {
+    for (int i = 0; i < R; ++i)
+      for (int j = 0; j < SD; ++j) ops.push_back(j < Np ? (float)A[(size_t)i * Np + j] : 0.0f);
+  };
+  rows(P.Dr, Np);
+  rows(P.Ds, Np);
+  rows(P.Dt, Np);
+  rows(P.Fquad, Nfq);
+  rows(P.Ftri, 4 * Nfn);
+  std::vector<double> Mf((size_t)Nfn * Nfn, 0.0);
+  for (int q = 0; q < Nfq; ++q)
+    for (int x = 0; x < Nfn; ++x)
+      for (int y = 0; y < Nfn; ++y) Mf[x * Nfn + y] += ft.Ican[q * Nfn + x] * ft.tri_w[q] * ft.Ican[q * Nfn + y];
+  for (int tf = 0; tf < 4; ++tf)
+    for (int t = 0; t < Mt; ++t)
+      for (int s = 0; s < Kf; ++s)
+        for (int l = 0; l < 64; ++l) {
+          const int i = 16 * t + l % 16, col = 4 * s + l / 16;
+          double v = 0.0;
+          if (i < Np && col < Nfn)
+            for (int m = 0; m < Nfn; ++m) v += P.Ftri[((size_t)tf * Nfn + m) * Np + i] * Mf[m * Nfn + col];
+          ops.push_back((float)v);
+        }
+  ops.push_back((float)ft.tri_w[0]);
+  while (ops.size() % 2) ops.push_back(0.0f);
+  std::vector<double> gab;
+  for (int i = 0; i < Np; ++i) {
+    gab.push_back(P.geo_pts[3 * i]);
+    gab.push_back(P.geo_pts[3 * i + 1]);
+  }
+  const size_t o = ops.size();
+  ops.resize(o + 2 * gab.size());
+  std::memcpy(ops.data() + o, gab.data(), gab.size() * sizeof(double));
+  std::vector<int> iq(8 * Nfq), it(6 * Nfn);
+  for (int k = 0; k < 8; ++k)
+    for (int q = 0; q < Nfq; ++q) iq[k * Nfq + ft.quad_perm[k * Nfq + q]] = q;
+  for (int k = 0; k < 6; ++k)
+    for (int m = 0; m < Nfn; ++m) it[k * Nfn + ft.tri_perm[k * Nfn + m]] = m;
+  iops.insert(iops.end(), ft.quad_perm.begin(), ft.quad_perm.end());
+  iops.insert(iops.end(), iq.begin(), iq.end());
+  iops.insert(iops.end(), ft.tri_perm.begin(), ft.tri_perm.end());
+  iops.insert(iops.end(), it.begin(), it.end());
+  if ((int)ops.size() != nf || (int)iops.size() != ni)
+    return fail(c, HDG_EINVAL, "internal: pyramid matrix-core table size mismatch");
+  return HDG_OK;
+}
+
 bool use_lattice(const hdg_ctx* c) { return c->path == HDG_PATH_AUTO && c->lattice_ok; }
 
 // One launch of the kernel serving type t: tetrahedra go to the matrix-core
 // kernel when lattice traces are in use; mrab selects the multi-rate update.
 int launch_type(hdg_ctx* c, int t, StageArgs a, bool mrab) {
   a.lat = use_lattice(c) ? 1 : 0;
+  a.V = c->td[t].V;
+  if (t == kPyr && a.lat && c->td[t].mops) {
+    a.ops = c->td[t].mops;
+    a.iops = c->td[t].miops;
+    if (mrab) a.mode = kModeMrab;
+    if (launch_pyr_mfma(c->N, a, c->stream, c->max_blocks)) return fail(c, HDG_EINVAL, "no kernel for this order");
+    return HDG_OK;
+  }
   if (t == kTet && a.lat) {
     a.ops = c->td[t].mops;
     a.iops = c->td[t].miops;
@@ -667,6 +736,12 @@ int create_impl(hdg_ctx* c, const hdg_mesh* m, int N) {
     if ((rc = upload(c, &d.iops, iops))) return rc;
     if (t == kTet) {
       if ((rc = build_tet_mfma_tables(c, c->prec, ops, iops))) return rc;
+      if ((rc = upload(c, &d.mops, ops))) return rc;
+      if ((rc = upload(c, &d.miops, iops))) return rc;
+    }
+    int pnf = 0, pni = 0;
+    if (t == kPyr && pyr_mfma_table_sizes(N, &pnf, &pni) == 0) {
+      if ((rc = build_pyr_mfma_tables(c, ops, iops))) return rc;
       if ((rc = upload(c, &d.mops, ops))) return rc;
       if ((rc = upload(c, &d.miops, iops))) return rc;
     }

@@ -62,6 +62,13 @@ int launch_tet_mfma(int N, int P, const StageArgs& a, hipStream_t s, int max_blo
 // lift fragments [4][Mt][Kf][pieces][64][KI], then 1/s_D and 1/s_L;
 // integers fnode [4][Nfn], tperm [6][Nfn].
 void tet_mfma_table_sizes(int N, int P, int* n_floats, int* n_ints);
+// Pyramids on the matrix cores with lattice traces on their triangular faces
+// (orders 1..4, all modes); returns -1 for other orders.
+int launch_pyr_mfma(int N, const StageArgs& a, hipStream_t s, int max_blocks);
+// Table sizes in floats / ints (D, Fq, Ft rows with odd stride, lattice lift
+// fragments, w0, geometry points; base and lattice permutations and their
+// inverses); -1 for orders without the kernel.
+int pyr_mfma_table_sizes(int N, int* n_floats, int* n_ints);
 // Fragment geometry of precision P: K per instruction, entries per lane, pieces.
 void tet_mfma_frag_shape(int P, int* kk, int* ki, int* npc);
 

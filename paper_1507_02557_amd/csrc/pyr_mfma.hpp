@@ -1,0 +1,573 @@
+// Pyramids on the matrix cores (Section 2.3.4, Algorithm 7: semi-nodal
+// basis, skew-symmetric form, quadrature-free operators), with lattice
+// traces on the four triangular faces.
+//
+// Each wavefront owns a tile of 16 consecutive pyramids (the column index of
+// every product).  With D^r_ij the quadrature-free derivative matrices, the
+// right-hand side at node i of an element is
+//
+//   rhs_p   = kappa / J_i (sum_r [(D^r)^T U^r]_i + S_p,i),
+//   rhs_u_d = (1/rho) (-sum_r G_rd,i [D^r p]_i + S_d,i / J_i),
+//   U^r_j   = sum_d adj(F)_rd,j u_d,j          (adj(F) = J G),
+//
+// with G = dxi/dx and J evaluated at the node's (a, b) (they do not depend on
+// the collapsed coordinate c) and S the surface term
+//
+//   S = Fq^T (w J^s flux at the base face's local points)
+//     + sum_f Ft_f^T M_f (J^s flux at face f's local lattice nodes),
+//
+// Fq, Ft_f the basis at the base face's GL points and at the triangle's
+// lattice nodes, M_f the lattice mass matrix.  The flux on a triangle is
+// linear in planar-face traces that are degree-N polynomials, so its
+// lattice values and M_f give the cubature rule's integral exactly.
+//
+// The geometric factors are recomputed per node in FP64 from the five
+// vertices (no stored per-node geometry).  The element's own traces at the
+// stage start are those it wrote at the end of the previous stage, so they
+// are read from the trace buffer rather than recomputed; the traces of the
+// updated state are the products Fq u and Ft_f u.
+#pragma once
+
+#include "mfma_common.hpp"
+
+namespace hdg {
+
+// Jacobian matrix F[d][r] = dx_d/dxi_r of the pyramid map on the plane
+// c = -1 at collapsed coordinates (a, b); V = 5 vertices (base 0..3, apex 4).
+__device__ __forceinline__ void pyr_jacobian(const double (&V)[5][3], double a, double b, double F[3][3]) {
+  const double sa[4] = {-1.0, 1.0, 1.0, -1.0}, sb[4] = {-1.0, -1.0, 1.0, 1.0};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double X = 0.0, Xa = 0.0, Xb = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double fa = 0.5 * (1.0 + sa[v] * a), fb = 0.5 * (1.0 + sb[v] * b);
+      X += fa * fb * V[v][d];
+      Xa += 0.5 * sa[v] * fb * V[v][d];
+      Xb += fa * 0.5 * sb[v] * V[v][d];
+    }
+    F[d][0] = Xa;
+    F[d][1] = Xb;
+    F[d][2] = 0.5 * (1.0 + a) * Xa + 0.5 * (1.0 + b) * Xb + 0.5 * (V[4][d] - X);
+  }
+}
+
+// adj(F)[r][d] = J dxi_r/dx_d; returns J = det F.
+__device__ __forceinline__ double adjugate(const double F[3][3], double A[3][3]) {
+  A[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+  A[0][1] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
+  A[0][2] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
+  A[1][0] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+  A[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
+  A[1][2] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
+  A[2][0] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+  A[2][1] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
+  A[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  return F[0][0] * A[0][0] + F[0][1] * A[1][0] + F[0][2] * A[2][0];
+}
+
+template <int N, int NW>
+struct PyrMfma {
+  static constexpr int Np = (N + 1) * (N + 2) * (2 * N + 3) / 6;
+  static constexpr int Nfn = (N + 1) * (N + 2) / 2;
+  static constexpr int Nfq = (N + 1) * (N + 1);
+  static constexpr int Mt = (Np + 15) / 16;   // row tiles over element nodes
+  static constexpr int Ks = (Np + 3) / 4;     // k-steps over element nodes
+  static constexpr int Mq = (Nfq + 15) / 16;  // row tiles over base-face points
+  static constexpr int Kq = (Nfq + 3) / 4;    // k-steps over base-face points
+  static constexpr int Kf = (Nfn + 3) / 4;    // k-steps over a triangle's lattice
+  static_assert(Nfn <= 16, "one row tile per triangle lattice");
+  static constexpr int SD = Np | 1;           // odd strides: conflict-free fragment reads
+  static constexpr int SX = Np | 1;
+  static constexpr int SF = Nfq | 1;
+  static constexpr int NT = 64 * NW;
+  static constexpr int kLFloats = 4 * Mt * Kf * 64;
+  // D [3][Np][SD], Fq [Nfq][SD], Ft [4][Nfn][SD], Lt fragments, w0, then the
+  // geometry points (a, b) as doubles at an even float offset
+  static constexpr int kOpsOpf = (3 * Np + Nfq + 4 * Nfn) * SD;
+  static constexpr int kGabOff = (kOpsOpf + kLFloats + 2) & ~1;
+  static constexpr int kOpsFloats = kGabOff + 4 * Np;
+  static constexpr int kOpsInts = 2 * 8 * Nfq + 2 * 6 * Nfn;
+  static constexpr int Q4 = 4 * Np;
+  static constexpr int JQ = (Q4 + 63) / 64;
+  static constexpr int JB = (Nfq + 3) / 4;  // base points q = g + 4 j per lane
+  static constexpr int JF = (Nfn + 3) / 4;  // lattice nodes m = g + 4 j per lane
+
+  struct Wave {
+    float X[4][16][SX];  // state tile
+    float F[4][16][SF];  // one face's weighted flux; staging of one output field
+  };
+  static_assert(4 * 16 * SF >= 16 * SX, "output staging does not fit the flux buffer");
+
+  struct Smem {
+    float D[3][Np][SD];
+    float Fq[Nfq][SD];
+    float Ft[4][Nfn][SD];
+    float Lt[4][Mt][Kf][64];
+    double gab[Np][2];
+    int qperm[8][Nfq], iqperm[8][Nfq];  // canonical <-> local base point
+    int tperm[6][Nfn], itperm[6][Nfn];  // canonical <-> local lattice node
+    float w0;                           // canonical triangle weight of point 0
+    Wave w[NW];
+  };
+
+  // operator entry with zero outside [0, R) x [0, C)
+  template <int R, int C, int S>
+  __device__ static float at(const float (*A)[S], int i, int j) {
+    const bool in = i < R && j < C;
+    return in ? A[in ? i : 0][in ? j : 0] : 0.f;
+  }
+
+  // ---- tile I/O (global [K][Np] per field <-> LDS [16][SX])
+  __device__ static bool contiguous(const StageArgs& a, int64_t e0) {
+    return a.elist == nullptr && e0 + 16 <= a.n_items && ((a.K * Np) & 3) == 0;
+  }
+  __device__ static void load_rows(float (*dst)[SX], const float* src, const StageArgs& a, int64_t e0, int lane) {
+    for (int it = lane; it < 16 * Np; it += 64) {
+      const int n = it / Np, k = it - n * Np;
+      const int64_t e = item(a, e0 + n);
+      dst[n][k] = e >= 0 ? src[e * Np + k] : 0.0f;
+    }
+  }
+  __device__ static void store_rows(float* dst, const float (*src)[SX], const StageArgs& a, int64_t e0, int lane) {
+    for (int it = lane; it < 16 * Np; it += 64) {
+      const int n = it / Np, k = it - n * Np;
+      const int64_t e = item(a, e0 + n);
+      if (e >= 0) dst[e * Np + k] = src[n][k];
+    }
+  }
+  __device__ static void put4(float (*dst)[SX], int q0, float4 v) {
+    const float x[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = q0 + i, n = q / Np;
+      dst[n][q - n * Np] = x[i];
+    }
+  }
+  __device__ static float4 get4(const float (*src)[SX], int q0) {
+    float x[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = q0 + i, n = q / Np;
+      x[i] = src[n][q - n * Np];
+    }
+    return make_float4(x[0], x[1], x[2], x[3]);
+  }
+  __device__ static void load_field(float4 (&v)[JQ], const float* base, int64_t e0, int lane) {
+    const float4* src = reinterpret_cast<const float4*>(base + e0 * Np);
+#pragma unroll
+    for (int j = 0; j < JQ; ++j)
+      if (lane + 64 * j < Q4) v[j] = src[lane + 64 * j];
+  }
+  __device__ static void put_field(float (*dst)[SX], const float4 (&v)[JQ], int lane) {
+#pragma unroll
+    for (int j = 0; j < JQ; ++j)
+      if (lane + 64 * j < Q4) put4(dst, 4 * (lane + 64 * j), v[j]);
+  }
+  __device__ static void store_tile(float* dst, const float (*src)[SX], const StageArgs& a, int64_t e0, int lane,
+                                    bool contig) {
+    if (contig) {
+      float4* d4 = reinterpret_cast<float4*>(dst + e0 * Np);
+#pragma unroll
+      for (int j = 0; j < JQ; ++j)
+        if (lane + 64 * j < Q4) d4[lane + 64 * j] = get4(src, 4 * (lane + 64 * j));
+    } else {
+      store_rows(dst, src, a, e0, lane);
+    }
+  }
+  __device__ static void load_state(Wave& W, const StageArgs& a, int64_t e0, int lane, bool contig) {
+    const int64_t fs = a.K * Np;
+    if (contig) {
+      float4 v0[JQ], v1[JQ], v2[JQ], v3[JQ];
+      load_field(v0, a.U, e0, lane);
+      load_field(v1, a.U + fs, e0, lane);
+      load_field(v2, a.U + 2 * fs, e0, lane);
+      load_field(v3, a.U + 3 * fs, e0, lane);
+      put_field(W.X[0], v0, lane);
+      put_field(W.X[1], v1, lane);
+      put_field(W.X[2], v2, lane);
+      put_field(W.X[3], v3, lane);
+    } else {
+      for (int c = 0; c < 4; ++c) load_rows(W.X[c], a.U + (int64_t)c * fs, a, e0, lane);
+    }
+  }
+
+  // ---- traces of the tile's state: base face at canonical GL points,
+  // triangles at canonical lattice nodes
+  __device__ static void write_traces(const Smem& sm, const Wave& W, const StageArgs& a, int64_t e0, int lane,
+                                      float4* tr) {
+    const int n = lane & 15, g = lane >> 4;
+    const int64_t e = item(a, e0 + n);
+    const int64_t slot = a.slot0 + (e >= 0 ? e : 0) * 5;
+    // base face: T = Fq u (rows = local GL points)
+    {
+      f32x4 acc[4][Mq];
+#pragma unroll
+      for (int t = 0; t < Mq; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+      for (int s = 0; s < Ks; ++s) {
+        const int k = 4 * s + g;
+        const bool in = k < Np;
+        const int kk = in ? k : 0;
+        float b[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = in ? W.X[c][n][kk] : 0.f;
+#pragma unroll
+        for (int t = 0; t < Mq; ++t) {
+          const float af = at<Nfq, Np, SD>(sm.Fq, 16 * t + (lane & 15), 4 * s + (lane >> 4));
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[c][t] = mma_f32(af, b[c], acc[c][t]);
+        }
+      }
+      const int o = e >= 0 ? a.ori[slot] : 0;
+#pragma unroll
+      for (int t = 0; t < Mq; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int l = 16 * t + 4 * g + i;
+          if (e >= 0 && l < Nfq)
+            tr[slot * Nfq + sm.iqperm[o][l]] = make_float4(acc[0][t][i], acc[1][t][i], acc[2][t][i], acc[3][t][i]);
+        }
+    }
+    // triangular faces: lattice values Ft_f u (rows = local lattice nodes)
+#pragma unroll 1
+    for (int tf = 0; tf < 4; ++tf) {
+      f32x4 acc[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+      for (int s = 0; s < Ks; ++s) {
+        const int k = 4 * s + g;
+        const bool in = k < Np;
+        const int kk = in ? k : 0;
+        const float af = at<Nfn, Np, SD>(sm.Ft[tf], lane & 15, 4 * s + (lane >> 4));
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = mma_f32(af, in ? W.X[c][n][kk] : 0.f, acc[c]);
+      }
+      const int o = e >= 0 ? a.ori[slot + 1 + tf] : 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int l = 4 * g + i;
+        if (e >= 0 && l < Nfn)
+          tr[(slot + 1 + tf) * Nfq + sm.itperm[o][l]] = make_float4(acc[0][i], acc[1][i], acc[2][i], acc[3][i]);
+      }
+    }
+  }
+
+  // multi-rate AB3 update: u_new = u + dtau_l sum_j beta_j(1) r_{s-j} with its
+  // traces, then the mid-step state u_new + dtau_l sum_j (beta_j(1/2) -
+  // beta_j(1)) r_{s-j} with its traces (dense output)
+  __device__ static void mrab_update(const Smem& sm, Wave& W, const StageArgs& a, int64_t e0, int lane) {
+    const int64_t K = a.K;
+    const int64_t hstr = 4 * K * Np;
+    for (int half = 0; half < 2; ++half) {
+      for (int c = 0; c < 4; ++c)
+        for (int it = lane; it < 16 * Np; it += 64) {
+          const int nn = it / Np, k = it - nn * Np;
+          const int64_t ee = item(a, e0 + nn);
+          if (ee < 0) continue;
+          const int lv = a.elevel[ee];
+          const int64_t gi = (int64_t)c * K * Np + ee * Np + k;
+          float acc = 0.f;
+          for (int j = 0; j < 3; ++j) {
+            const float w = half ? a.mr.bh[lv][j] - a.mr.b1[lv][j] : a.mr.b1[lv][j];
+            acc += w * a.H[a.mr.hs[lv][j] * hstr + gi];
+          }
+          const float un = W.X[c][nn][k] + a.mr.dtl[lv] * acc;
+          W.X[c][nn][k] = un;
+          if (!half) a.U[gi] = un;
+        }
+      wave_sync();
+      write_traces(sm, W, a, e0, lane, half ? a.tr_half : a.tr_out);
+      wave_sync();
+    }
+  }
+
+  // vertices of element e (a reference pyramid for e < 0, keeping the
+  // geometry of unused columns finite)
+  __device__ static void load_verts5(const StageArgs& a, int64_t e, double (&V)[5][3]) {
+    const double ref[5][3] = {{-1, -1, 0}, {1, -1, 0}, {1, 1, 0}, {-1, 1, 0}, {0, 0, 1}};
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) V[v][d] = e >= 0 ? a.V[(e * 5 + v) * 3 + d] : ref[v][d];
+  }
+
+  template <int C>
+  __device__ static void emit(Wave& W, const StageArgs& a, int64_t e0, int lane, bool contig, const float4 (&rv)[JQ],
+                              const f32x4 (&rhs)[Mt]) {
+    const int64_t K = a.K;
+    const int n = lane & 15, g = lane >> 4;
+    const bool stage = a.mode == kModeStage;
+    float(*RB)[SX] = reinterpret_cast<float(*)[SX]>(&W.F[0][0][0]);
+    if (stage) {
+      if (contig) put_field(RB, rv, lane);
+      else load_rows(RB, a.R + (int64_t)C * K * Np, a, e0, lane);
+      wave_sync();
+    }
+#pragma unroll
+    for (int t = 0; t < Mt; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * t + 4 * g + i;
+        if (row >= Np) continue;
+        if (stage) {
+          const float res = a.a * RB[n][row] + a.dt * rhs[t][i];
+          RB[n][row] = res;
+          W.X[C][n][row] += a.b * res;
+        } else {
+          RB[n][row] = rhs[t][i];
+        }
+      }
+    wave_sync();
+    if (a.mode == kModeRhsHist) {
+      for (int it = lane; it < 16 * Np; it += 64) {
+        const int nn = it / Np, k = it - nn * Np;
+        const int64_t ee = item(a, e0 + nn);
+        if (ee >= 0) rhs_dst(a, ee, Np)[(int64_t)C * K * Np + ee * Np + k] = RB[nn][k];
+      }
+    } else {
+      store_tile(a.R + (int64_t)C * K * Np, RB, a, e0, lane, contig);
+    }
+    if (stage) store_tile(a.U + (int64_t)C * K * Np, W.X[C], a, e0, lane, contig);
+    wave_sync();
+  }
+
+  __device__ static void tile(const Smem& sm, Wave& W, const StageArgs& a, int64_t e0, int lane) {
+    const int64_t K = a.K;
+    const int n = lane & 15, g = lane >> 4;
+    const int64_t e = item(a, e0 + n);
+    const bool contig = contiguous(a, e0);
+    load_state(W, a, e0, lane, contig);
+    wave_sync();
+    if (a.mode == kModeTrace) {
+      write_traces(sm, W, a, e0, lane, a.tr_out);
+      return;
+    }
+    if (a.mode == kModeMrab) {
+      mrab_update(sm, W, a, e0, lane);
+      return;
+    }
+    double V[5][3];
+    load_verts5(a, e, V);
+    float kap = 0.f, irho = 0.f;
+    if (e >= 0) {
+      kap = a.mat[e].x;
+      irho = a.mat[e].y;
+    }
+    // volume: grad = D^r p, div = sum_r (D^r)^T U^r
+    f32x4 accG[3][Mt], accV[Mt];
+#pragma unroll
+    for (int t = 0; t < Mt; ++t) {
+      accV[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) accG[r][t] = accV[t];
+    }
+#pragma unroll 1
+    for (int s = 0; s < Ks; ++s) {
+      const int k = 4 * s + g;
+      const bool in = k < Np;
+      const int kk = in ? k : 0;
+      double F[3][3], A[3][3];
+      pyr_jacobian(V, sm.gab[kk][0], sm.gab[kk][1], F);
+      adjugate(F, A);
+      const float p = in ? W.X[0][n][kk] : 0.f;
+      const float u1 = W.X[1][n][kk], u2 = W.X[2][n][kk], u3 = W.X[3][n][kk];
+      float ur[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+        ur[r] = in ? (float)A[r][0] * u1 + (float)A[r][1] * u2 + (float)A[r][2] * u3 : 0.f;
+      const int ra = lane & 15, ca = lane >> 4;
+#pragma unroll
+      for (int t = 0; t < Mt; ++t)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const float d = at<Np, Np, SD>(sm.D[r], 16 * t + ra, 4 * s + ca);
+          const float dt = at<Np, Np, SD>(sm.D[r], 4 * s + ca, 16 * t + ra);
+          accG[r][t] = mma_f32(d, p, accG[r][t]);
+          accV[t] = mma_f32(dt, ur[r], accV[t]);
+        }
+    }
+    // surface-term accumulators start from the volume terms, scaled so that
+    // rhs_p = kappa/J (S_p) and rhs_u = (1/rho)/J (S_u):
+    //   S_p = sum_r (D^r)^T U^r,  S_u_d = -sum_r adj(F)_rd [D^r p]
+    f32x4 accS[4][Mt];
+#pragma unroll
+    for (int t = 0; t < Mt; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * t + 4 * g + i;
+        double F[3][3], A[3][3];
+        const int rr = row < Np ? row : 0;
+        pyr_jacobian(V, sm.gab[rr][0], sm.gab[rr][1], F);
+        adjugate(F, A);
+        accS[0][t][i] = accV[t][i];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          accS[1 + d][t][i] = -((float)A[0][d] * accG[0][t][i] + (float)A[1][d] * accG[1][t][i] +
+                                (float)A[2][d] * accG[2][t][i]);
+      }
+    // the residual of the stage, fetched while the faces are processed
+    const bool stage = a.mode == kModeStage;
+    float4 rv0[JQ], rv1[JQ], rv2[JQ], rv3[JQ];
+    if (stage && contig) {
+      const int64_t fs = K * Np;
+      load_field(rv0, a.R, e0, lane);
+      load_field(rv1, a.R + fs, e0, lane);
+      load_field(rv2, a.R + 2 * fs, e0, lane);
+      load_field(rv3, a.R + 3 * fs, e0, lane);
+    }
+    // surface term S
+    const int64_t slot0 = a.slot0 + (e >= 0 ? e : 0) * 5;
+    // base face: weighted flux at local GL points, then Fq^T
+    {
+      int nb = -1, o = 0;
+      float2 tau = make_float2(0.f, 0.f);
+      const float4* nsrc = a.tr_in;
+      if (e >= 0) {
+        nb = a.nbr[slot0];
+        o = a.ori[slot0];
+        tau = a.tau[slot0];
+        if (nb >= 0) nsrc = neighbour_src(a, slot0, nb);
+      }
+#pragma unroll
+      for (int j0 = 0; j0 < JB; j0 += 2) {
+        float4 own[2], pv[2], gq[2];
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const int q = g + 4 * (j0 + jj);
+          if (e >= 0 && j0 + jj < JB && q < Nfq) {
+            own[jj] = a.tr_in[slot0 * Nfq + q];
+            gq[jj] = a.fgeo[(slot0 - a.slot0) * Nfq + q];
+            if (nb >= 0) pv[jj] = nsrc[(int64_t)nb * Nfq + q];
+          }
+        }
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const int q = g + 4 * (j0 + jj);
+          if (j0 + jj >= JB || q >= Nfq) continue;
+          float out[4] = {0.f, 0.f, 0.f, 0.f};
+          int l = q;
+          if (e >= 0) {
+            l = sm.qperm[o][q];
+            const float4 p = nb >= 0 ? pv[jj] : mirror_state(own[jj], -nb - 1, gq[jj].x, gq[jj].y, gq[jj].z);
+            upwind_flux(own[jj], p, gq[jj], tau, true, out);
+          }
+#pragma unroll
+          for (int c = 0; c < 4; ++c) W.F[c][n][l] = out[c];
+        }
+      }
+      wave_sync();
+#pragma unroll 1
+      for (int s = 0; s < Kq; ++s) {
+        const int k = 4 * s + g;
+        const bool in = k < Nfq;
+        const int kk = in ? k : 0;
+        float b[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = in ? W.F[c][n][kk] : 0.f;
+#pragma unroll
+        for (int t = 0; t < Mt; ++t) {
+          const float af = at<Nfq, Np, SD>(sm.Fq, 4 * s + (lane >> 4), 16 * t + (lane & 15));
+#pragma unroll
+          for (int c = 0; c < 4; ++c) accS[c][t] = mma_f32(af, b[c], accS[c][t]);
+        }
+      }
+      wave_sync();
+    }
+    // triangular faces: J^s-weighted flux at local lattice nodes, then Ft^T M_f
+#pragma unroll 1
+    for (int tf = 0; tf < 4; ++tf) {
+      const int64_t slot = slot0 + 1 + tf;
+      int nb = -1, o = 0;
+      float2 tau = make_float2(0.f, 0.f);
+      float4 gf = make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4* nsrc = a.tr_in;
+      if (e >= 0) {
+        nb = a.nbr[slot];
+        o = a.ori[slot];
+        tau = a.tau[slot];
+        gf = a.fgeo[(slot - a.slot0) * Nfq];
+        gf.w /= sm.w0;  // J^s (the stored value carries the weight of point 0)
+        if (nb >= 0) nsrc = neighbour_src(a, slot, nb);
+      }
+#pragma unroll
+      for (int j = 0; j < JF; ++j) {
+        const int m = g + 4 * j;
+        if (m >= Nfn) continue;
+        float out[4] = {0.f, 0.f, 0.f, 0.f};
+        int l = m;
+        if (e >= 0) {
+          const float4 own = a.tr_in[slot * Nfq + m];
+          const float4 p = nb >= 0 ? nsrc[(int64_t)nb * Nfq + m] : mirror_state(own, -nb - 1, gf.x, gf.y, gf.z);
+          l = sm.tperm[o][m];
+          upwind_flux(own, p, gf, tau, true, out);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) W.F[c][n][l] = out[c];
+      }
+      wave_sync();
+#pragma unroll
+      for (int s = 0; s < Kf; ++s) {
+        const int k = 4 * s + g;
+        const bool in = k < Nfn;
+        const int kk = in ? k : 0;
+        float b[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = in ? W.F[c][n][kk] : 0.f;
+#pragma unroll
+        for (int t = 0; t < Mt; ++t) {
+          const float lf = sm.Lt[tf][t][s][lane];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) accS[c][t] = mma_f32(lf, b[c], accS[c][t]);
+        }
+      }
+      wave_sync();
+    }
+    // right-hand side at rows 16 t + 4 g + i (overwrites accS); 1/J from the
+    // vertices again (cheaper than keeping it live across the faces)
+    load_verts5(a, e, V);
+#pragma unroll
+    for (int t = 0; t < Mt; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * t + 4 * g + i;
+        const int rr = row < Np ? row : 0;
+        double F[3][3], A[3][3];
+        pyr_jacobian(V, sm.gab[rr][0], sm.gab[rr][1], F);
+        const float iJ = (float)(1.0 / adjugate(F, A));
+        const float sp = kap * iJ, su = irho * iJ;
+        accS[0][t][i] *= sp;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) accS[1 + d][t][i] *= su;
+      }
+    emit<0>(W, a, e0, lane, contig, rv0, accS[0]);
+    emit<1>(W, a, e0, lane, contig, rv1, accS[1]);
+    emit<2>(W, a, e0, lane, contig, rv2, accS[2]);
+    emit<3>(W, a, e0, lane, contig, rv3, accS[3]);
+    if (stage) write_traces(sm, W, a, e0, lane, a.tr_out);
+  }
+
+  __device__ static void run(Smem& sm, const StageArgs& a) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    float* dst = &sm.D[0][0][0];
+    for (int i = tid; i < kOpsOpf; i += NT) dst[i] = a.ops[i];  // D, Fq, Ft are contiguous in Smem
+    float* lt = &sm.Lt[0][0][0][0];
+    for (int i = tid; i < kLFloats; i += NT) lt[i] = a.ops[kOpsOpf + i];
+    if (tid == 0) sm.w0 = a.ops[kOpsOpf + kLFloats];
+    const double* gab = reinterpret_cast<const double*>(a.ops + kGabOff);
+    for (int i = tid; i < 2 * Np; i += NT) (&sm.gab[0][0])[i] = gab[i];
+    int* ip = &sm.qperm[0][0];
+    for (int i = tid; i < kOpsInts; i += NT) ip[i] = a.iops[i];  // qperm, iqperm, tperm, itperm contiguous
+    float* wz = &sm.w[0].X[0][0][0];
+    for (int i = tid; i < (int)(NW * sizeof(Wave) / sizeof(float)); i += NT) wz[i] = 0.f;
+    __syncthreads();
+    Wave& W = sm.w[wv];
+    const int64_t ntile = (a.n_items + 15) / 16;
+    for (int64_t t = (int64_t)blockIdx.x * NW + wv; t < ntile; t += (int64_t)gridDim.x * NW) tile(sm, W, a, t * 16, lane);
+  }
+};
+
+}  // namespace hdg

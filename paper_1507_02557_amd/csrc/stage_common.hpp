@@ -46,6 +46,7 @@ struct StageArgs {
   float* U;              // state [4][K][Np], fields p, ux, uy, uz
   float* R;              // LSERK residual (or rhs) [4][K][Np]
   const float* geo;      // per-type volume geometry
+  const double* V;       // element vertices [K][nv][3] (geometry recomputed in FP64)
   const float2* mat;     // [K] (kappa, 1/rho)
   const int* nbr;        // [nslot] neighbour slot, or -(1 + bc) on the boundary
   const int8_t* ori;     // [nslot] orientation code of the canonical face frame

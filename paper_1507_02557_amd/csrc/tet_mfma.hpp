@@ -27,98 +27,9 @@
 // reads (16 elements x 4 consecutive nodes) conflict-free as well.
 #pragma once
 
-#include "stage_common.hpp"
+#include "mfma_common.hpp"
 
 namespace hdg {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-
-// D = A B + C for 16x16 tiles, K = 4: lane l passes A[l%16][l/16] and
-// B[l/16][l%16] and holds D[4(l/16)+i][l%16] in component i.
-__device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-// FP16 operands, FP32 accumulation: 16x16x16 (lane l passes A[l%16][4(l/16)+i]
-// and B[4(l/16)+i][l%16], i < 4) and 16x16x32 (A[l%16][8(l/16)+i],
-// B[8(l/16)+i][l%16], i < 8); the result layout is that of mma_f32.
-__device__ __forceinline__ f32x4 mma_f16(f16x4 a, f16x4 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f32x4 mma_f16(f16x8 a, f16x8 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-}
-
-// Operand precision of the element-batched operator products.
-//   0: FP32 operands (16x16x4).
-//   1: split FP16, 16x16x32: x = hi + lo with hi = fp16(s x), lo = fp16(s x - hi)
-//      for a power-of-two scale s per operator and per element column, so
-//      each operand carries about 22 significant bits; A B is formed as
-//      hi hi + hi lo + lo hi with FP32 accumulation.
-//   2: the same split with 16x16x16 instructions (less padding of K).
-template <int P>
-struct Prec;
-template <>
-struct Prec<0> {
-  static constexpr int KI = 1, KK = 4, NPC = 1;
-  typedef float V;
-};
-template <>
-struct Prec<1> {
-  static constexpr int KI = 8, KK = 32, NPC = 2;
-  typedef f16x8 V;
-};
-template <>
-struct Prec<2> {
-  static constexpr int KI = 4, KK = 16, NPC = 2;
-  typedef f16x4 V;
-};
-
-// Power of two that brings a column maximum m into [2^14, 2^15) (1 for m = 0).
-__device__ __forceinline__ float col_scale(float m) {
-  if (!(m > 0.f)) return 1.f;
-  int e;
-  frexpf(m, &e);
-  e = 15 - e;
-  e = e < -120 ? -120 : (e > 120 ? 120 : e);
-  return ldexpf(1.f, e);
-}
-// Maximum over the four lanes of a column (lanes n, n+16, n+32, n+48).
-__device__ __forceinline__ float col_max(float m) {
-  m = fmaxf(m, __shfl_xor(m, 16));
-  return fmaxf(m, __shfl_xor(m, 32));
-}
-template <class V, int KI>
-__device__ __forceinline__ void split_f16(const float (&v)[KI], float sc, V& hi, V& lo) {
-#pragma unroll
-  for (int i = 0; i < KI; ++i) {
-    const float x = v[i] * sc;
-    const _Float16 h = (_Float16)x;
-    hi[i] = h;
-    lo[i] = (_Float16)(x - (float)h);
-  }
-}
-
-// LDS writes of this wavefront become visible to its later LDS reads (LDS
-// operations of one wavefront complete in order; this stops the compiler
-// from moving memory operations across the point).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Neighbour state on a lattice face at canonical lattice node m (boundary:
-// mirror of the own state).  A coarser neighbour that is mid-step supplies
-// its dense-output trace.
-__device__ __forceinline__ float4 lattice_neighbour(const StageArgs& a, int64_t slot, int nfq, int m, float4 g,
-                                                    float4 own) {
-  const int nb = a.nbr[slot];
-  if (nb < 0) return mirror_state(own, -nb - 1, g.x, g.y, g.z);
-  return neighbour_src(a, slot, nb)[(int64_t)nb * nfq + m];
-}
 
 template <int N, int NW, int P>
 struct TetMfma {
