@@ -434,7 +434,8 @@ struct PyrMfma {
       }
 #pragma unroll
       for (int j0 = 0; j0 < JB; j0 += 2) {
-        float4 own[2], pv[2], gq[2];
+        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 own[2] = {z4, z4}, pv[2] = {z4, z4}, gq[2] = {z4, z4};
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj) {
           const int q = g + 4 * (j0 + jj);

@@ -21,11 +21,11 @@ template <int N, int P, int NW>
 constexpr bool tet_fits() {
   return sizeof(typename TetMfma<N, NW, P>::Smem) <= 160 * 1024;
 }
-// (split-precision kernels above N = 3 need more than the 256 registers a
+// (split-precision kernels above N = 2 need more than the 256 registers a
 // lane gets at 8 wavefronts per block)
 template <int N, int P>
 constexpr int tet_waves() {
-  return (tet_fits<N, P, 8>() && (P == 0 || N <= 3)) ? 8 : (tet_fits<N, P, 4>() ? 4 : 2);
+  return (tet_fits<N, P, 8>() && (P == 0 || N <= 2)) ? 8 : (tet_fits<N, P, 4>() ? 4 : 2);
 }
 template <int N, int P>
 using TetM = TetMfma<N, tet_waves<N, P>(), P>;

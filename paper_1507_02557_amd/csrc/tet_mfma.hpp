@@ -166,6 +166,20 @@ struct TetMfma {
     return o;
   }
 
+  // the neighbour's lattice trace values of face f at the lane's nodes
+  // m = g + 4 j (element n of the tile)
+  __device__ static void fetch_nbr(const StageArgs& a, const FaceRec& rec, int64_t e, int n, int g, int f,
+                                   float4 (&pv)[JF]) {
+    const int src = n + 16 * f;
+    const int nb = __shfl(rec.nb, src);
+    const float4* nsrc = __shfl(rec.half, src) ? a.tr_half : a.tr_in;
+#pragma unroll
+    for (int j = 0; j < JF; ++j) {
+      const int m = g + 4 * j;
+      if (e >= 0 && m < Nfn && nb >= 0) pv[j] = nsrc[(int64_t)nb * Nfq + m];
+    }
+  }
+
   // face-node values of the tile's state, canonical lattice order
   __device__ static void write_traces(const Smem& sm, const Wave& W, const StageArgs& a, int64_t e0, int lane,
                                       const FaceRec& rec, float4* tr) {
@@ -270,6 +284,53 @@ struct TetMfma {
     for (int t = 0; t < Mt; ++t) acc[t] += tmp[t] * gs;
   }
 
+  // One face: the strong-form flux at the face's lattice nodes (own value
+  // from the tile, neighbour's from pv), scaled by J^s / J, then the lift
+  // products acc += L_f F.
+  __device__ static void face(const Smem& sm, Wave& W, const StageArgs& a, const FaceRec& rec, int64_t e, int f,
+                              int n, int g, int lane, float iJ, const float4 (&pv)[JF], f32x4 (&accP)[Mt],
+                              f32x4 (&accL)[3][Mt]) {
+    const FaceRec fr = shfl_rec(rec, n + 16 * f);
+#pragma unroll
+    for (int j = 0; j < JF; ++j) {
+      const int m = g + 4 * j;
+      if (m >= Nfn) continue;
+      float out[4] = {0.f, 0.f, 0.f, 0.f};
+      int l = m;
+      if (e >= 0) {
+        l = sm.tperm[fr.ori][m];
+        const int node = sm.fnode[f][l];
+        const float4 own = make_float4(W.X[0][n][node], W.X[1][n][node], W.X[2][n][node], W.X[3][n][node]);
+        const float4 nb = fr.nb >= 0 ? pv[j] : mirror_state(own, -fr.nb - 1, fr.g.x, fr.g.y, fr.g.z);
+        upwind_flux(own, nb, fr.g, fr.tau, false, out);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) W.F[c][n][l] = out[c] * iJ;
+    }
+    wave_sync();
+    if constexpr (P == 0) {
+#pragma unroll
+      for (int s = 0; s < Kf; ++s) {
+        const int k = 4 * s + g;
+        const float b0 = W.F[0][n][k], b1 = W.F[1][n][k], b2 = W.F[2][n][k], b3 = W.F[3][n][k];
+#pragma unroll
+        for (int t = 0; t < Mt; ++t) {
+          const float lf = sm.L[f][t][s][0][lane];
+          accP[t] = mma_f32(lf, b0, accP[t]);
+          accL[0][t] = mma_f32(lf, b1, accL[0][t]);
+          accL[1][t] = mma_f32(lf, b2, accL[1][t]);
+          accL[2][t] = mma_f32(lf, b3, accL[2][t]);
+        }
+      }
+    } else {
+      lift_f16(sm, W, f, n, g, lane, W.F[0], accP);
+      lift_f16(sm, W, f, n, g, lane, W.F[1], accL[0]);
+      lift_f16(sm, W, f, n, g, lane, W.F[2], accL[1]);
+      lift_f16(sm, W, f, n, g, lane, W.F[3], accL[2]);
+    }
+    wave_sync();
+  }
+
   // Output of field C: rhs = sc * acc at rows 16 t + 4 g + i of column n,
   // then the stage update (res = a res + dt rhs, u += b res) or the rhs store.
   template <int C>
@@ -322,6 +383,14 @@ struct TetMfma {
     const int64_t e = item(a, e0 + n);  // element of this lane's column
     const bool contig = contiguous(a, e0);
     const FaceRec rec = load_rec(a, e, g);
+    // geometric factors and material of this lane's element (column n)
+    float G[10], kap = 0.f, irho = 0.f;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) G[i] = e >= 0 ? a.geo[e * 12 + i] : 0.f;
+    if (e >= 0) {
+      kap = a.mat[e].x;
+      irho = a.mat[e].y;
+    }
     if (contig) {
       const int64_t fs = K * Np;
       float4 v0[JQ], v1[JQ], v2[JQ], v3[JQ];
@@ -345,15 +414,16 @@ struct TetMfma {
       mrab_update(sm, W, a, e0, lane, rec);
       return;
     }
-    // geometric factors and material of this lane's element (column n)
-    float G[10], kap = 0.f, irho = 0.f;
-#pragma unroll
-    for (int i = 0; i < 10; ++i) G[i] = e >= 0 ? a.geo[e * 12 + i] : 0.f;
-    if (e >= 0) {
-      kap = a.mat[e].x;
-      irho = a.mat[e].y;
-    }
     const float iJ = G[9];
+    // neighbour traces: with FP32 operands faces 0 and 1 are in flight
+    // during the volume products and faces 2 and 3 during the first two
+    // faces' lift products; the split-precision kernels (more registers in
+    // use) fetch each face's at its start
+    float4 pv[4][JF];
+    if constexpr (P == 0) {
+      fetch_nbr(a, rec, e, n, g, 0, pv[0]);
+      fetch_nbr(a, rec, e, n, g, 1, pv[1]);
+    }
     f32x4 accP[Mt], accG[3][Mt];
 #pragma unroll
     for (int t = 0; t < Mt; ++t) {
@@ -431,65 +501,40 @@ struct TetMfma {
     for (int t = 0; t < Mt; ++t)
 #pragma unroll
       for (int d = 0; d < 3; ++d) accL[d][t] = -(G[d] * accG[0][t] + G[3 + d] * accG[1][t] + G[6 + d] * accG[2][t]);
-    // the residual of the stage, fetched while the faces are processed
     const bool stage = a.mode == kModeStage;
     float4 rv0[JQ], rv1[JQ], rv2[JQ], rv3[JQ];
-    if (stage && contig) {
-      const int64_t fs = K * Np;
-      load_field(rv0, a.R, e0, lane);
-      load_field(rv1, a.R + fs, e0, lane);
-      load_field(rv2, a.R + 2 * fs, e0, lane);
-      load_field(rv3, a.R + 3 * fs, e0, lane);
-    }
     // faces: flux at the lattice nodes, then the lift products
+    if constexpr (P == 0) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        if (f == 0) {
+          fetch_nbr(a, rec, e, n, g, 2, pv[2]);
+          fetch_nbr(a, rec, e, n, g, 3, pv[3]);
+        }
+        if (f == 2 && stage && contig) {
+          // the residual of the stage, fetched while the last faces are processed
+          const int64_t fs = K * Np;
+          load_field(rv0, a.R, e0, lane);
+          load_field(rv1, a.R + fs, e0, lane);
+          load_field(rv2, a.R + 2 * fs, e0, lane);
+          load_field(rv3, a.R + 3 * fs, e0, lane);
+        }
+        face(sm, W, a, rec, e, f, n, g, lane, iJ, pv[f], accP, accL);
+      }
+    } else {
+      if (stage && contig) {
+        const int64_t fs = K * Np;
+        load_field(rv0, a.R, e0, lane);
+        load_field(rv1, a.R + fs, e0, lane);
+        load_field(rv2, a.R + 2 * fs, e0, lane);
+        load_field(rv3, a.R + 3 * fs, e0, lane);
+      }
 #pragma unroll 1
-    for (int f = 0; f < 4; ++f) {
-      const FaceRec fr = shfl_rec(rec, n + 16 * f);
-      const float4* nsrc = fr.half ? a.tr_half : a.tr_in;
-      float4 pv[JF];
-#pragma unroll
-      for (int j = 0; j < JF; ++j) {
-        const int m = g + 4 * j;
-        if (e >= 0 && m < Nfn && fr.nb >= 0) pv[j] = nsrc[(int64_t)fr.nb * Nfq + m];
+      for (int f = 0; f < 4; ++f) {
+        float4 pf[JF];
+        fetch_nbr(a, rec, e, n, g, f, pf);
+        face(sm, W, a, rec, e, f, n, g, lane, iJ, pf, accP, accL);
       }
-#pragma unroll
-      for (int j = 0; j < JF; ++j) {
-        const int m = g + 4 * j;
-        if (m >= Nfn) continue;
-        float out[4] = {0.f, 0.f, 0.f, 0.f};
-        int l = m;
-        if (e >= 0) {
-          l = sm.tperm[fr.ori][m];
-          const int node = sm.fnode[f][l];
-          const float4 own = make_float4(W.X[0][n][node], W.X[1][n][node], W.X[2][n][node], W.X[3][n][node]);
-          const float4 nb = fr.nb >= 0 ? pv[j] : mirror_state(own, -fr.nb - 1, fr.g.x, fr.g.y, fr.g.z);
-          upwind_flux(own, nb, fr.g, fr.tau, false, out);
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) W.F[c][n][l] = out[c] * iJ;
-      }
-      wave_sync();
-      if constexpr (P == 0) {
-#pragma unroll
-        for (int s = 0; s < Kf; ++s) {
-          const int k = 4 * s + g;
-          const float b0 = W.F[0][n][k], b1 = W.F[1][n][k], b2 = W.F[2][n][k], b3 = W.F[3][n][k];
-#pragma unroll
-          for (int t = 0; t < Mt; ++t) {
-            const float lf = sm.L[f][t][s][0][lane];
-            accP[t] = mma_f32(lf, b0, accP[t]);
-            accL[0][t] = mma_f32(lf, b1, accL[0][t]);
-            accL[1][t] = mma_f32(lf, b2, accL[1][t]);
-            accL[2][t] = mma_f32(lf, b3, accL[2][t]);
-          }
-        }
-      } else {
-        lift_f16(sm, W, f, n, g, lane, W.F[0], accP);
-        lift_f16(sm, W, f, n, g, lane, W.F[1], accL[0]);
-        lift_f16(sm, W, f, n, g, lane, W.F[2], accL[1]);
-        lift_f16(sm, W, f, n, g, lane, W.F[3], accL[2]);
-      }
-      wave_sync();
     }
     // rhs at rows 16 t + 4 g + i of column n; stage update or rhs output
     emit<0>(W, a, e0, lane, contig, rv0, accP, kap);
