@@ -29,7 +29,7 @@ struct WedgeStage {
   static constexpr int Nfn = Ntri;
   static constexpr int NT = 256;
   static constexpr int kEPB = EPB;
-  static constexpr int nphase = 7;
+  static constexpr int nphase = 8;
   static constexpr int kTraceBegin = 5;  // first phase that writes traces
   // ops: Pt, Ptr, Ptt [Nct][Ntri]; tri_w [Nct]; P1, dP1 [n1][n1]; w1 [n1];
   //      P1f [2][n1]; Ftri [Nfn][Ntri]; Fedge [3][n1][Ntri]; Ican [Nfq][Nfn]
@@ -50,7 +50,10 @@ struct WedgeStage {
     float T[5][EPB][n1][Ntri];
     float g[EPB][5][Nfq][4];
     float c[EPB][2][Nfn][4];
-    float s[EPB][Np][4];
+    // sum-factorised face operands: quad faces [ef][l2 or l1][jt or js],
+    // triangle faces [tf][jt]
+    float W[EPB][3][n1][Ntri][4];
+    float z[EPB][2][Ntri][4];
     float mat[EPB][2];
   };
 
@@ -183,26 +186,28 @@ struct WedgeStage {
         sm.T[3][el][qs][jt] = t3;
         sm.T[4][el][qs][jt] = t4;
       }
-      for (int it = tid; it < EPB * Np; it += NT) {
-        const int el = it / Np, m = it % Np;
-        const int js = m / Ntri, jt = m % Ntri;
+      // quad faces: W[ef][l2][jt] = sum_l1 Fe[ef][l1][jt] g[2+ef][l2 n1 + l1]
+      for (int it = tid; it < EPB * 3 * n1 * Ntri; it += NT) {
+        const int el = it / (3 * n1 * Ntri), rr = it % (3 * n1 * Ntri);
+        const int ef = rr / (n1 * Ntri), r2 = rr % (n1 * Ntri);
+        const int l2 = r2 / Ntri, jt = r2 % Ntri;
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int tf = 0; tf < 2; ++tf) {
-          const float s1 = P1f[tf * n1 + js];
-          for (int l = 0; l < Nfn; ++l) {
-            const float w = s1 * Ft[l * Ntri + jt];
-            for (int c = 0; c < 4; ++c) acc[c] += w * sm.c[el][tf][l][c];
-          }
+        for (int l1 = 0; l1 < n1; ++l1) {
+          const float w = Fe[(ef * n1 + l1) * Ntri + jt];
+          for (int c = 0; c < 4; ++c) acc[c] += w * sm.g[el][2 + ef][l2 * n1 + l1][c];
         }
-        for (int ef = 0; ef < 3; ++ef)
-          for (int l2 = 0; l2 < n1; ++l2) {
-            const float s1 = P1[l2 * n1 + js];
-            for (int l1 = 0; l1 < n1; ++l1) {
-              const float w = s1 * Fe[(ef * n1 + l1) * Ntri + jt];
-              for (int c = 0; c < 4; ++c) acc[c] += w * sm.g[el][2 + ef][l2 * n1 + l1][c];
-            }
-          }
-        for (int c = 0; c < 4; ++c) sm.s[el][m][c] = acc[c];
+        for (int c = 0; c < 4; ++c) sm.W[el][ef][l2][jt][c] = acc[c];
+      }
+      // triangle faces: z[tf][jt] = sum_l Ft[l][jt] c[tf][l]
+      for (int it = tid; it < EPB * 2 * Ntri; it += NT) {
+        const int el = it / (2 * Ntri), rr = it % (2 * Ntri);
+        const int tf = rr / Ntri, jt = rr % Ntri;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int l = 0; l < Nfn; ++l) {
+          const float w = Ft[l * Ntri + jt];
+          for (int c = 0; c < 4; ++c) acc[c] += w * sm.c[el][tf][l][c];
+        }
+        for (int c = 0; c < 4; ++c) sm.z[el][tf][jt][c] = acc[c];
       }
     } else if (ph == 4) {
       for (int it = tid; it < EPB * Np; it += NT) {
@@ -216,10 +221,21 @@ struct WedgeStage {
           vp += p1 * sm.T[0][el][qs][jt] + dP1[qs * n1 + js] * sm.T[1][el][qs][jt];
           for (int d = 0; d < 3; ++d) vu[d] -= p1 * sm.T[2 + d][el][qs][jt];
         }
+        // surface: sum_tf P1f[tf][js] z[tf][jt] + sum_ef sum_l2 P1[l2][js] W[ef][l2][jt]
+        float sf[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int tf = 0; tf < 2; ++tf) {
+          const float w = P1f[tf * n1 + js];
+          for (int c = 0; c < 4; ++c) sf[c] += w * sm.z[el][tf][jt][c];
+        }
+        for (int ef = 0; ef < 3; ++ef)
+          for (int l2 = 0; l2 < n1; ++l2) {
+            const float w = P1[l2 * n1 + js];
+            for (int c = 0; c < 4; ++c) sf[c] += w * sm.W[el][ef][l2][jt][c];
+          }
         const float kap = sm.mat[el][0], irho = sm.mat[el][1];
         float rhs[4];
-        rhs[0] = kap * (vp + sm.s[el][m][0]);
-        for (int d = 0; d < 3; ++d) rhs[1 + d] = irho * (vu[d] + sm.s[el][m][1 + d]);
+        rhs[0] = kap * (vp + sf[0]);
+        for (int d = 0; d < 3; ++d) rhs[1 + d] = irho * (vu[d] + sf[1 + d]);
         const int64_t base = e * Np + m;
         for (int c = 0; c < 4; ++c) {
           const int64_t gi = (int64_t)c * K * Np + base;
@@ -235,17 +251,39 @@ struct WedgeStage {
         }
       }
     } else if (ph == 5) {
+      // s-contractions of the traces: triangle faces z[tf][jt] = sum_js P1f[tf][js] u[js][jt],
+      // quad faces W[ef][l1][js] = sum_jt Fe[ef][l1][jt] u[js][jt]
       const float(*src)[EPB][Np] = (a.mode == kModeTrace) ? sm.u : sm.un;
+      for (int it = tid; it < EPB * 2 * Ntri; it += NT) {
+        const int el = it / (2 * Ntri), rr = it % (2 * Ntri);
+        const int tf = rr / Ntri, jt = rr % Ntri;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int js = 0; js < n1; ++js) {
+          const float w = P1f[tf * n1 + js];
+          for (int c = 0; c < 4; ++c) acc[c] += w * src[c][el][js * Ntri + jt];
+        }
+        for (int c = 0; c < 4; ++c) sm.z[el][tf][jt][c] = acc[c];
+      }
+      for (int it = tid; it < EPB * 3 * n1 * n1; it += NT) {
+        const int el = it / (3 * n1 * n1), rr = it % (3 * n1 * n1);
+        const int ef = rr / (n1 * n1), r2 = rr % (n1 * n1);
+        const int l1 = r2 / n1, js = r2 % n1;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int jt = 0; jt < Ntri; ++jt) {
+          const float w = Fe[(ef * n1 + l1) * Ntri + jt];
+          for (int c = 0; c < 4; ++c) acc[c] += w * src[c][el][js * Ntri + jt];
+        }
+        for (int c = 0; c < 4; ++c) sm.W[el][ef][l1][js][c] = acc[c];
+      }
+    } else if (ph == 6) {
+      // triangle lattice values c = Ft z; quad traces sum_js P1[l2][js] W[ef][l1][js] / sqrt(J)
       for (int it = tid; it < EPB * 2 * Nfn; it += NT) {
         const int el = it / (2 * Nfn), rr = it % (2 * Nfn);
         const int tf = rr / Nfn, l = rr % Nfn;
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int js = 0; js < n1; ++js) {
-          const float s1 = P1f[tf * n1 + js];
-          for (int jt = 0; jt < Ntri; ++jt) {
-            const float w = s1 * Ft[l * Ntri + jt];
-            for (int c = 0; c < 4; ++c) acc[c] += w * src[c][el][js * Ntri + jt];
-          }
+        for (int jt = 0; jt < Ntri; ++jt) {
+          const float w = Ft[l * Ntri + jt];
+          for (int c = 0; c < 4; ++c) acc[c] += w * sm.z[el][tf][jt][c];
         }
         for (int c = 0; c < 4; ++c) sm.c[el][tf][l][c] = acc[c];
       }
@@ -260,16 +298,13 @@ struct WedgeStage {
         const int l1 = l % n1, l2 = l / n1;
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int js = 0; js < n1; ++js) {
-          const float s1 = P1[l2 * n1 + js];
-          for (int jt = 0; jt < Ntri; ++jt) {
-            const float w = s1 * Fe[(ef * n1 + l1) * Ntri + jt];
-            for (int c = 0; c < 4; ++c) acc[c] += w * src[c][el][js * Ntri + jt];
-          }
+          const float w = P1[l2 * n1 + js];
+          for (int c = 0; c < 4; ++c) acc[c] += w * sm.W[el][ef][l1][js][c];
         }
         const float isj = a.isqJ[(e * 5 + f) * Nfq + q];
         a.tr_out[slot * Nfq + q] = make_float4(acc[0] * isj, acc[1] * isj, acc[2] * isj, acc[3] * isj);
       }
-    } else if (ph == 6) {
+    } else if (ph == 7) {
       for (int it = tid; it < EPB * 2 * Nfq; it += NT) {
         const int el = it / (2 * Nfq), rr = it % (2 * Nfq);
         const int tf = rr / Nfq, q = rr % Nfq;
