@@ -8,7 +8,9 @@
 //          inverse mass 1/(w_ijk J_ijk) is applied per node.
 // Traces:  u(+-1, s_j, t_k) = sum_m l_m(+-1) u_mjk (Algorithm 2) at the local
 //          face point that the canonical point maps to under the face's
-//          orientation (a permutation of the GL tensor grid).
+//          orientation (a permutation of the GL tensor grid).  The element's
+//          own trace is recomputed from the state rather than read back, so
+//          only the neighbour's trace is read.
 #pragma once
 
 #include "stage_common.hpp"
@@ -79,11 +81,21 @@ struct HexStage {
         if (e < 0) continue;
         const int64_t slot = a.slot0 + e * 6 + f;
         const float4 g = a.fgeo[(e * 6 + f) * Nfq + q];
-        float4 m, p;
-        face_states(a, slot, Nfq, q, g, m, p);
+        const int l = sm.qperm[a.ori[slot]][q];
+        // own trace recomputed from the state (Algorithm 2), not read back
+        const int l1 = l % n1, l2 = l / n1;
+        const float* L = sm.Lf[f & 1];
+        float mv[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int k = 0; k < n1; ++k) {
+          const int nd = line_node(f, k, l1, l2);
+          for (int c = 0; c < 4; ++c) mv[c] += L[k] * sm.u[c][el][nd];
+        }
+        const float4 m = make_float4(mv[0], mv[1], mv[2], mv[3]);
+        const int nb = a.nbr[slot];
+        const float4 p = nb >= 0 ? neighbour_src(a, slot, nb)[(int64_t)nb * Nfq + q]
+                                 : mirror_state(m, -nb - 1, g.x, g.y, g.z);
         float out[4];
         upwind_flux(m, p, g, a.tau[slot], false, out);
-        const int l = sm.qperm[a.ori[slot]][q];
         for (int c = 0; c < 4; ++c) sm.g[el][f][l][c] = out[c];
       }
     } else if (ph == 2) {
