@@ -26,21 +26,37 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def tet_alg_bytes(N: int, lattice: bool) -> int:
-    """Algorithmic HBM bytes per tetrahedron per stage of the fused kernel.
+def alg_bytes(t: int, N: int, lattice: bool) -> int:
+    """Algorithmic HBM bytes per element per stage of the fused kernel of type t.
 
     State: read U and res, write U and res (4 fields, FP32): 64 B per node.
-    Traces: write the element's own traces and read the neighbour's (4 fields,
-    FP32): 32 B per trace point, on 4 faces; a trace point is a face-lattice
-    node ((N+1)(N+2)/2 per face) with lattice traces, else a cubature point
-    ((N+1)^2 per face).
-    Element data: 10 geometry floats read as 12, (kappa, 1/rho), 4 face
-    records (normal + J^s, neighbour slot, orientation, penalties):
-    48 + 8 + 4 * (16 + 4 + 1 + 8).
+    Traces: write the element's own trace and read the neighbour's (4 fields,
+    FP32): 32 B per trace point; a triangle shared by tetrahedra/pyramids
+    carries (N+1)(N+2)/2 lattice points with lattice traces, every other face
+    (N+1)^2 cubature points.
+    Geometry: the smaller of what the element needs to rebuild it (its
+    vertices in FP64, 24 B each) and the stored per-element factors (tet: 12
+    floats + 4 face normals with J^s).  Material (kappa, 1/rho): 8 B.  Face
+    records (neighbour slot, orientation, penalties): 13 B per face.
     """
-    Np = (N + 1) * (N + 2) * (N + 3) // 6
-    npt = (N + 1) * (N + 2) // 2 if lattice else (N + 1) ** 2
-    return 64 * Np + 32 * 4 * npt + 48 + 8 + 4 * (16 + 4 + 1 + 8)
+    n1 = N + 1
+    nfn, nfq = (N + 1) * (N + 2) // 2, n1 * n1
+    tri = nfn if lattice else nfq
+    if t == 3:  # tetrahedron
+        np_ = (N + 1) * (N + 2) * (N + 3) // 6
+        return 64 * np_ + 32 * 4 * tri + min(4 * 24, 48 + 4 * 16) + 8 + 4 * 13
+    if t == 2:  # pyramid: base quad + 4 triangles
+        np_ = (N + 1) * (N + 2) * (2 * N + 3) // 6
+        return 64 * np_ + 32 * (nfq + 4 * tri) + 5 * 24 + 8 + 5 * 13
+    if t == 1:  # wedge: 2 triangles (wedge-wedge: cubature) + 3 quads
+        np_ = n1 * nfn
+        return 64 * np_ + 32 * 5 * nfq + 6 * 24 + 8 + 5 * 13
+    np_ = n1 ** 3  # hexahedron
+    return 64 * np_ + 32 * 6 * nfq + 8 * 24 + 8 + 6 * 13
+
+
+def tet_alg_bytes(N: int, lattice: bool) -> int:
+    return alg_bytes(3, N, lattice)
 
 
 def csrc_hash() -> str:
@@ -175,14 +191,29 @@ def main():
     dofs = sum(s.info[t][0] * s.info[t][1] for t in s.types)
     stages = 5 * args.steps
     gdofs = dofs * stages / (ms * 1e-3) / 1e9
-    avg_ms = {hdg.TET: kms[3] / max(kcnt[3], 1)}
-    per_type = {name: round(float(kms[t] / max(kcnt[t], 1)), 4)
-                for t, name in ((0, "hex"), (1, "wedge"), (2, "pyr"), (3, "tet")) if kcnt[t]}
     Ktet = s.info[hdg.TET][0]
     lattice = s.get_path()[1] == 1
-    tet_kernel = f"TetMfma<{N}, " if lattice else f"TetStage<{N}, "
-    alg_bytes = tet_alg_bytes(N, lattice) * Ktet
-    achieved = alg_bytes / (avg_ms[hdg.TET] * 1e-3) / 1e9
+    # kernel names as rocprofv3 reports them (for the committed traffic counters)
+    kname = {3: (f"TetMfma<{N}, ", ", 0>") if lattice else (f"TetStage<{N}, ", ""),
+             2: (f"PyrMfma<{N}, ", "") if (lattice and N in (3, 4)) else (f"PyrStage<{N}, ", ""),
+             1: (f"WedgeStage<{N}, ", ""), 0: (f"HexStage<{N}, ", "")}
+    kfull = {3: "tet_mfma_kernel" if lattice else "stage_kernel",
+             2: "pyr_mfma_kernel" if (lattice and N in (3, 4)) else "stage_kernel",
+             1: "stage_kernel", 0: "stage_kernel"}
+    roof = {}
+    for t, name in ((0, "hex"), (1, "wedge"), (2, "pyr"), (3, "tet")):
+        if not kcnt[t]:
+            continue
+        ms_t = kms[t] / kcnt[t]
+        b = alg_bytes(t, N, lattice) * s.info[t][0]
+        ach = b / (ms_t * 1e-3) / 1e9
+        roof[name] = {"bound": "hbm", "kernel": f"{kfull[t]}<{kname[t][0]}...>", "ms_per_launch": round(ms_t, 4),
+                      "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(ach / HBM_PEAK_GBS, 4),
+                      "traffic": measured_traffic(*kname[t]), "alg_bytes_per_launch": int(b),
+                      "alg_bytes_per_element": alg_bytes(t, N, lattice)}
+    dominant = max(roof, key=lambda k: roof[k]["ms_per_launch"])
+    per_type = {k: v["ms_per_launch"] for k, v in roof.items()}
     E = s.energy()
     info = dict(s.info)
     types = list(s.types)
@@ -233,17 +264,9 @@ def main():
             "energy_after": E,
             "mixed_precision": mixed,
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": ("tet_mfma_kernel" if lattice else "stage_kernel") + f"<{tet_kernel}...>",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(tet_kernel, ", 0>" if lattice else ""),
-            "alg_bytes_per_launch": int(alg_bytes),
-        },
+        "roofline": dict(roof[dominant], type=dominant),
     }
+    out["config"]["roofline_by_type"] = roof
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, N, args.cpu_stages)
     print(json.dumps(out))

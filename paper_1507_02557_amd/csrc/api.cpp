@@ -85,7 +85,7 @@ struct hdg_ctx {
   bool lattice_ok = false;     // no triangular face joins a wedge to a tet or pyramid
   int path = HDG_PATH_AUTO;
   int prec = HDG_PREC_FP32;    // operand precision of the matrix-core products
-  int max_blocks = 1024;       // cap of persistent grids (4 per compute unit)
+  int max_blocks = 256;        // cap of persistent matrix-core grids (one block per compute unit)
   GeoTables* gtab = nullptr;
   double* partial = nullptr;
   int* flag = nullptr;
@@ -610,7 +610,7 @@ int create_impl(hdg_ctx* c, const hdg_mesh* m, int N) {
     int dev = 0, ncu = 0;
     HIPCHK(c, hipGetDevice(&dev));
     HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    if (ncu > 0) c->max_blocks = 4 * ncu;
+    if (ncu > 0) c->max_blocks = ncu;
   }
   int rc;
   if ((rc = upload(c, &c->nbr, nbr))) return rc;

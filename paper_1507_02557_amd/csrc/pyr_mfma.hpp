@@ -340,6 +340,8 @@ struct PyrMfma {
     const int n = lane & 15, g = lane >> 4;
     const int64_t e = item(a, e0 + n);
     const bool contig = contiguous(a, e0);
+    // lanes of the previous tile may still read other columns of the tile
+    wave_sync();
     load_state(W, a, e0, lane, contig);
     wave_sync();
     if (a.mode == kModeTrace) {

@@ -29,8 +29,8 @@ struct WedgeStage {
   static constexpr int Nfn = Ntri;
   static constexpr int NT = 256;
   static constexpr int kEPB = EPB;
-  static constexpr int nphase = 8;
-  static constexpr int kTraceBegin = 5;  // first phase that writes traces
+  static constexpr int nphase = 9;
+  static constexpr int kTraceBegin = 6;  // first phase that writes traces
   // ops: Pt, Ptr, Ptt [Nct][Ntri]; tri_w [Nct]; P1, dP1 [n1][n1]; w1 [n1];
   //      P1f [2][n1]; Ftri [Nfn][Ntri]; Fedge [3][n1][Ntri]; Ican [Nfq][Nfn]
   static constexpr int oPt = 0, oPtr = oPt + Nct * Ntri, oPtt = oPtr + Nct * Ntri, oTw = oPtt + Nct * Ntri;
@@ -44,22 +44,28 @@ struct WedgeStage {
     int qperm[8][Nfq];
     int tperm[6][Nfn];
     float u[4][EPB][Np];
-    float un[4][EPB][Np];
-    float A[5][EPB][n1][Ntri];
-    float B[7][EPB][Nq];
-    float T[5][EPB][n1][Ntri];
-    float g[EPB][5][Nfq][4];
+    // buffers whose lifetimes do not overlap share storage (phases in
+    // brackets write / read them):
+    union {
+      float A[5][EPB][n1][Ntri];  // s-contracted state [1] / [2]
+      float T[5][EPB][n1][Ntri];  // test contractions [3] / [5]
+    };
+    union {
+      float B[7][EPB][Nq];               // values, then trial integrands at the volume points [2, 3] / [3, 4]
+      float W[EPB][3][n1][Ntri][4];      // quad-face operands [4, 6] / [5, 7]
+    };
+    union {
+      float g[EPB][5][Nfq][4];  // weighted face fluxes [1] / [2, 4]
+      float un[4][EPB][Np];     // updated state [5] / [6, 7, 8]
+    };
     float c[EPB][2][Nfn][4];
-    // sum-factorised face operands: quad faces [ef][l2 or l1][jt or js],
-    // triangle faces [tf][jt]
-    float W[EPB][3][n1][Ntri][4];
-    float z[EPB][2][Ntri][4];
+    float z[EPB][2][Ntri][4];   // triangle-face operands [3, 6] / [5, 7]
     float mat[EPB][2];
   };
 
   HD static bool active(int ph, int mode) {
-    if (mode == kModeTrace) return ph == 0 || ph >= 5;
-    if (mode == kModeRhs || mode == kModeRhsHist) return ph <= 4;
+    if (mode == kModeTrace) return ph == 0 || ph >= kTraceBegin;
+    if (mode == kModeRhs || mode == kModeRhsHist) return ph < kTraceBegin;
     return true;
   }
 
@@ -186,18 +192,6 @@ struct WedgeStage {
         sm.T[3][el][qs][jt] = t3;
         sm.T[4][el][qs][jt] = t4;
       }
-      // quad faces: W[ef][l2][jt] = sum_l1 Fe[ef][l1][jt] g[2+ef][l2 n1 + l1]
-      for (int it = tid; it < EPB * 3 * n1 * Ntri; it += NT) {
-        const int el = it / (3 * n1 * Ntri), rr = it % (3 * n1 * Ntri);
-        const int ef = rr / (n1 * Ntri), r2 = rr % (n1 * Ntri);
-        const int l2 = r2 / Ntri, jt = r2 % Ntri;
-        float acc[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int l1 = 0; l1 < n1; ++l1) {
-          const float w = Fe[(ef * n1 + l1) * Ntri + jt];
-          for (int c = 0; c < 4; ++c) acc[c] += w * sm.g[el][2 + ef][l2 * n1 + l1][c];
-        }
-        for (int c = 0; c < 4; ++c) sm.W[el][ef][l2][jt][c] = acc[c];
-      }
       // triangle faces: z[tf][jt] = sum_l Ft[l][jt] c[tf][l]
       for (int it = tid; it < EPB * 2 * Ntri; it += NT) {
         const int el = it / (2 * Ntri), rr = it % (2 * Ntri);
@@ -210,6 +204,19 @@ struct WedgeStage {
         for (int c = 0; c < 4; ++c) sm.z[el][tf][jt][c] = acc[c];
       }
     } else if (ph == 4) {
+      // quad faces: W[ef][l2][jt] = sum_l1 Fe[ef][l1][jt] g[2+ef][l2 n1 + l1]
+      for (int it = tid; it < EPB * 3 * n1 * Ntri; it += NT) {
+        const int el = it / (3 * n1 * Ntri), rr = it % (3 * n1 * Ntri);
+        const int ef = rr / (n1 * Ntri), r2 = rr % (n1 * Ntri);
+        const int l2 = r2 / Ntri, jt = r2 % Ntri;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int l1 = 0; l1 < n1; ++l1) {
+          const float w = Fe[(ef * n1 + l1) * Ntri + jt];
+          for (int c = 0; c < 4; ++c) acc[c] += w * sm.g[el][2 + ef][l2 * n1 + l1][c];
+        }
+        for (int c = 0; c < 4; ++c) sm.W[el][ef][l2][jt][c] = acc[c];
+      }
+    } else if (ph == 5) {
       for (int it = tid; it < EPB * Np; it += NT) {
         const int el = it / Np, m = it % Np;
         const int js = m / Ntri, jt = m % Ntri;
@@ -250,7 +257,7 @@ struct WedgeStage {
           }
         }
       }
-    } else if (ph == 5) {
+    } else if (ph == 6) {
       // s-contractions of the traces: triangle faces z[tf][jt] = sum_js P1f[tf][js] u[js][jt],
       // quad faces W[ef][l1][js] = sum_jt Fe[ef][l1][jt] u[js][jt]
       const float(*src)[EPB][Np] = (a.mode == kModeTrace) ? sm.u : sm.un;
@@ -275,7 +282,7 @@ struct WedgeStage {
         }
         for (int c = 0; c < 4; ++c) sm.W[el][ef][l1][js][c] = acc[c];
       }
-    } else if (ph == 6) {
+    } else if (ph == 7) {
       // triangle lattice values c = Ft z; quad traces sum_js P1[l2][js] W[ef][l1][js] / sqrt(J)
       for (int it = tid; it < EPB * 2 * Nfn; it += NT) {
         const int el = it / (2 * Nfn), rr = it % (2 * Nfn);
@@ -304,7 +311,7 @@ struct WedgeStage {
         const float isj = a.isqJ[(e * 5 + f) * Nfq + q];
         a.tr_out[slot * Nfq + q] = make_float4(acc[0] * isj, acc[1] * isj, acc[2] * isj, acc[3] * isj);
       }
-    } else if (ph == 7) {
+    } else if (ph == 8) {
       for (int it = tid; it < EPB * 2 * Nfq; it += NT) {
         const int el = it / (2 * Nfq), rr = it % (2 * Nfq);
         const int tf = rr / Nfq, q = rr % Nfq;

@@ -11,8 +11,18 @@
 
 namespace hdg {
 
+// Minimum wavefronts per SIMD the register allocation must allow.
 template <class S>
-__global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
+struct Occupancy {
+  static constexpr int value = 1;
+};
+template <int N, int E>
+struct Occupancy<WedgeStage<N, E>> {
+  static constexpr int value = N <= 4 ? 3 : 1;
+};
+
+template <class S>
+__global__ __launch_bounds__(256, Occupancy<S>::value) void stage_kernel(StageArgs a) {
   __shared__ typename S::Smem sm;
   S::load_ops(threadIdx.x, sm, a);
   __syncthreads();

@@ -382,6 +382,8 @@ struct TetMfma {
     const int n = lane & 15, g = lane >> 4;
     const int64_t e = item(a, e0 + n);  // element of this lane's column
     const bool contig = contiguous(a, e0);
+    // lanes of the previous tile may still read other columns of the tile
+    wave_sync();
     const FaceRec rec = load_rec(a, e, g);
     // geometric factors and material of this lane's element (column n)
     float G[10], kap = 0.f, irho = 0.f;
