@@ -82,6 +82,33 @@ HD inline float* rhs_dst(const StageArgs& a, int64_t e, int Np) {
 
 // Neighbour state on a boundary face (mirror principle):
 // rigid wall p+ = p-, u+ = u- - 2 (n.u-) n; free surface p+ = -p-, u+ = u-.
+// Residual of the four fields at one node, read at the start of the node's
+// work so the four loads overlap it and one another (stores to R and U that
+// come later could alias them as far as the compiler can tell).
+HD inline void load_residual(const StageArgs& a, int64_t base, int Np, float (&r)[4]) {
+  const bool upd = a.mode != kModeRhs && a.mode != kModeRhsHist;
+  for (int c = 0; c < 4; ++c) r[c] = upd ? a.R[(int64_t)c * a.K * Np + base] : 0.f;
+}
+
+// Output of the four fields at one node: the rhs itself, or the low-storage
+// Runge-Kutta update of residual and state (u and un point at field 0 of the
+// node in the block's state arrays, fields fstride apart).
+HD inline void node_update(const StageArgs& a, int64_t e, int Np, int64_t base, const float (&rhs)[4],
+                           const float (&r)[4], const float* u, float* un, int fstride) {
+  for (int c = 0; c < 4; ++c) {
+    const int64_t gi = (int64_t)c * a.K * Np + base;
+    if (a.mode == kModeRhs || a.mode == kModeRhsHist) {
+      rhs_dst(a, e, Np)[gi] = rhs[c];
+    } else {
+      const float res = a.a * r[c] + a.dt * rhs[c];
+      const float v = u[c * fstride] + a.b * res;
+      a.R[gi] = res;
+      a.U[gi] = v;
+      un[c * fstride] = v;
+    }
+  }
+}
+
 HD inline float4 mirror_state(float4 m, int bc, float nx, float ny, float nz) {
   if (bc == 1) {
     const float un = m.y * nx + m.z * ny + m.w * nz;

@@ -103,6 +103,9 @@ struct HexStage {
         const int el = it / Np, node = it % Np;
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
+        const int64_t base = e * Np + node;
+        float r0[4];
+        load_residual(a, base, Np, r0);
         const int i = node % n1, j = (node / n1) % n1, k = node / (n1 * n1);
         float du[4][3];
         for (int c = 0; c < 4; ++c) {
@@ -134,19 +137,7 @@ struct HexStage {
         rhs[0] = kap * (-div + iwJ * surf[0]);
         for (int d = 0; d < 3; ++d)
           rhs[1 + d] = irho * (-(G[0][d] * du[0][0] + G[1][d] * du[0][1] + G[2][d] * du[0][2]) + iwJ * surf[1 + d]);
-        const int64_t base = e * Np + node;
-        for (int c = 0; c < 4; ++c) {
-          const int64_t gi = (int64_t)c * K * Np + base;
-          if (a.mode == kModeRhs || a.mode == kModeRhsHist) {
-            rhs_dst(a, e, Np)[gi] = rhs[c];
-          } else {
-            const float res = a.a * a.R[gi] + a.dt * rhs[c];
-            const float un = sm.u[c][el][node] + a.b * res;
-            a.R[gi] = res;
-            a.U[gi] = un;
-            sm.un[c][el][node] = un;
-          }
-        }
+        node_update(a, e, Np, base, rhs, r0, &sm.u[0][el][node], &sm.un[0][el][node], EPB * Np);
       }
     } else if (ph == 3) {
       const float(*src)[EPB][Np] = (a.mode == kModeTrace) ? sm.u : sm.un;

@@ -153,6 +153,9 @@ struct PyrStage {
         const int el = it / Np, i = it % Np;
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
+        const int64_t base = e * Np + i;
+        float r0[4];
+        load_residual(a, base, Np, r0);
         float Dp[3] = {0.f, 0.f, 0.f}, volp = 0.f;
         for (int j = 0; j < Np; ++j) {
           const float pj = sm.u[0][el][j];
@@ -171,19 +174,7 @@ struct PyrStage {
         rhs[0] = kap * iJ * (volp + sm.s[el][i][0]);
         for (int d = 0; d < 3; ++d)
           rhs[1 + d] = irho * (-(G[0][d] * Dp[0] + G[1][d] * Dp[1] + G[2][d] * Dp[2]) + iJ * sm.s[el][i][1 + d]);
-        const int64_t base = e * Np + i;
-        for (int c = 0; c < 4; ++c) {
-          const int64_t gi = (int64_t)c * K * Np + base;
-          if (a.mode == kModeRhs || a.mode == kModeRhsHist) {
-            rhs_dst(a, e, Np)[gi] = rhs[c];
-          } else {
-            const float res = a.a * a.R[gi] + a.dt * rhs[c];
-            const float un = sm.u[c][el][i] + a.b * res;
-            a.R[gi] = res;
-            a.U[gi] = un;
-            sm.un[c][el][i] = un;
-          }
-        }
+        node_update(a, e, Np, base, rhs, r0, &sm.u[0][el][i], &sm.un[0][el][i], EPB * Np);
       }
     } else if (ph == 5) {
       // base-face traces at canonical points; triangle-face lattice values

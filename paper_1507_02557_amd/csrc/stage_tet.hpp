@@ -138,6 +138,9 @@ struct TetStage {
         const int el = it / Np, i = it % Np;
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
+        const int64_t base = e * Np + i;
+        float r0[4];
+        load_residual(a, base, Np, r0);
         float dp[3] = {0.f, 0.f, 0.f}, div = 0.f, lift[4] = {0.f, 0.f, 0.f, 0.f};
         for (int j = 0; j < Np; ++j) {
           const float pj = sm.u[0][el][j];
@@ -155,19 +158,7 @@ struct TetStage {
         rhs[0] = kap * (-div + iJ * lift[0]);
         for (int d = 0; d < 3; ++d)
           rhs[1 + d] = irho * (-(G[d] * dp[0] + G[3 + d] * dp[1] + G[6 + d] * dp[2]) + iJ * lift[1 + d]);
-        const int64_t base = e * Np + i;
-        for (int c = 0; c < 4; ++c) {
-          const int64_t gi = (int64_t)c * K * Np + base;
-          if (a.mode == kModeRhs || a.mode == kModeRhsHist) {
-            rhs_dst(a, e, Np)[gi] = rhs[c];
-          } else {
-            const float res = a.a * a.R[gi] + a.dt * rhs[c];
-            const float un = sm.u[c][el][i] + a.b * res;
-            a.R[gi] = res;
-            a.U[gi] = un;
-            sm.un[c][el][i] = un;
-          }
-        }
+        node_update(a, e, Np, base, rhs, r0, &sm.u[0][el][i], &sm.un[0][el][i], EPB * Np);
       }
     } else if (ph == 5) {
       const float(*src)[EPB][Np] = (a.mode == kModeTrace) ? sm.u : sm.un;

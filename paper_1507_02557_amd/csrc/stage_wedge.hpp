@@ -29,8 +29,8 @@ struct WedgeStage {
   static constexpr int Nfn = Ntri;
   static constexpr int NT = 256;
   static constexpr int kEPB = EPB;
-  static constexpr int nphase = 9;
-  static constexpr int kTraceBegin = 6;  // first phase that writes traces
+  static constexpr int nphase = 8;
+  static constexpr int kTraceBegin = 5;  // first phase that writes traces
   // ops: Pt, Ptr, Ptt [Nct][Ntri]; tri_w [Nct]; P1, dP1 [n1][n1]; w1 [n1];
   //      P1f [2][n1]; Ftri [Nfn][Ntri]; Fedge [3][n1][Ntri]; Ican [Nfq][Nfn]
   static constexpr int oPt = 0, oPtr = oPt + Nct * Ntri, oPtt = oPtr + Nct * Ntri, oTw = oPtt + Nct * Ntri;
@@ -48,18 +48,18 @@ struct WedgeStage {
     // brackets write / read them):
     union {
       float A[5][EPB][n1][Ntri];  // s-contracted state [1] / [2]
-      float T[5][EPB][n1][Ntri];  // test contractions [3] / [5]
+      float T[5][EPB][n1][Ntri];  // test contractions with the quad faces folded in [3] / [4]
     };
     union {
-      float B[7][EPB][Nq];               // values, then trial integrands at the volume points [2, 3] / [3, 4]
-      float W[EPB][3][n1][Ntri][4];      // quad-face operands [4, 6] / [5, 7]
+      float B[7][EPB][Nq];            // trial integrands at the volume points [2] / [3]
+      float W[EPB][3][n1][n1][4];     // quad-face trace operands [5] / [6]
     };
     union {
-      float g[EPB][5][Nfq][4];  // weighted face fluxes [1] / [2, 4]
-      float un[4][EPB][Np];     // updated state [5] / [6, 7, 8]
+      float g[EPB][5][Nfq][4];  // weighted face fluxes [1] / [2, 3]
+      float un[4][EPB][Np];     // updated state [4] / [5, 6, 7]
     };
     float c[EPB][2][Nfn][4];
-    float z[EPB][2][Ntri][4];   // triangle-face operands [3, 6] / [5, 7]
+    float z[EPB][2][Ntri][4];   // triangle-face operands [3, 5] / [4, 6]
     float mat[EPB][2];
   };
 
@@ -186,6 +186,17 @@ struct WedgeStage {
           t3 += pt * sm.B[5][el][q];
           t4 += pt * sm.B[6][el][q];
         }
+        // quad faces: their s points are the volume points qs, so their test
+        // integrals share the final s-contraction with the volume terms
+        for (int ef = 0; ef < 3; ++ef)
+          for (int l1 = 0; l1 < n1; ++l1) {
+            const float w = Fe[(ef * n1 + l1) * Ntri + jt];
+            const float* gq = sm.g[el][2 + ef][qs * n1 + l1];
+            t0 += w * gq[0];
+            t2 -= w * gq[1];
+            t3 -= w * gq[2];
+            t4 -= w * gq[3];
+          }
         sm.T[0][el][qs][jt] = t0;
         sm.T[1][el][qs][jt] = t1;
         sm.T[2][el][qs][jt] = t2;
@@ -204,60 +215,33 @@ struct WedgeStage {
         for (int c = 0; c < 4; ++c) sm.z[el][tf][jt][c] = acc[c];
       }
     } else if (ph == 4) {
-      // quad faces: W[ef][l2][jt] = sum_l1 Fe[ef][l1][jt] g[2+ef][l2 n1 + l1]
-      for (int it = tid; it < EPB * 3 * n1 * Ntri; it += NT) {
-        const int el = it / (3 * n1 * Ntri), rr = it % (3 * n1 * Ntri);
-        const int ef = rr / (n1 * Ntri), r2 = rr % (n1 * Ntri);
-        const int l2 = r2 / Ntri, jt = r2 % Ntri;
-        float acc[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int l1 = 0; l1 < n1; ++l1) {
-          const float w = Fe[(ef * n1 + l1) * Ntri + jt];
-          for (int c = 0; c < 4; ++c) acc[c] += w * sm.g[el][2 + ef][l2 * n1 + l1][c];
-        }
-        for (int c = 0; c < 4; ++c) sm.W[el][ef][l2][jt][c] = acc[c];
-      }
-    } else if (ph == 5) {
       for (int it = tid; it < EPB * Np; it += NT) {
         const int el = it / Np, m = it % Np;
         const int js = m / Ntri, jt = m % Ntri;
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
+        const int64_t base = e * Np + m;
+        float r0[4];
+        load_residual(a, base, Np, r0);
         float vp = 0.f, vu[3] = {0.f, 0.f, 0.f};
         for (int qs = 0; qs < n1; ++qs) {
           const float p1 = P1[qs * n1 + js];
           vp += p1 * sm.T[0][el][qs][jt] + dP1[qs * n1 + js] * sm.T[1][el][qs][jt];
           for (int d = 0; d < 3; ++d) vu[d] -= p1 * sm.T[2 + d][el][qs][jt];
         }
-        // surface: sum_tf P1f[tf][js] z[tf][jt] + sum_ef sum_l2 P1[l2][js] W[ef][l2][jt]
+        // triangle faces: sum_tf P1f[tf][js] z[tf][jt]
         float sf[4] = {0.f, 0.f, 0.f, 0.f};
         for (int tf = 0; tf < 2; ++tf) {
           const float w = P1f[tf * n1 + js];
           for (int c = 0; c < 4; ++c) sf[c] += w * sm.z[el][tf][jt][c];
         }
-        for (int ef = 0; ef < 3; ++ef)
-          for (int l2 = 0; l2 < n1; ++l2) {
-            const float w = P1[l2 * n1 + js];
-            for (int c = 0; c < 4; ++c) sf[c] += w * sm.W[el][ef][l2][jt][c];
-          }
         const float kap = sm.mat[el][0], irho = sm.mat[el][1];
         float rhs[4];
         rhs[0] = kap * (vp + sf[0]);
         for (int d = 0; d < 3; ++d) rhs[1 + d] = irho * (vu[d] + sf[1 + d]);
-        const int64_t base = e * Np + m;
-        for (int c = 0; c < 4; ++c) {
-          const int64_t gi = (int64_t)c * K * Np + base;
-          if (a.mode == kModeRhs || a.mode == kModeRhsHist) {
-            rhs_dst(a, e, Np)[gi] = rhs[c];
-          } else {
-            const float res = a.a * a.R[gi] + a.dt * rhs[c];
-            const float un = sm.u[c][el][m] + a.b * res;
-            a.R[gi] = res;
-            a.U[gi] = un;
-            sm.un[c][el][m] = un;
-          }
-        }
+        node_update(a, e, Np, base, rhs, r0, &sm.u[0][el][m], &sm.un[0][el][m], EPB * Np);
       }
-    } else if (ph == 6) {
+    } else if (ph == 5) {
       // s-contractions of the traces: triangle faces z[tf][jt] = sum_js P1f[tf][js] u[js][jt],
       // quad faces W[ef][l1][js] = sum_jt Fe[ef][l1][jt] u[js][jt]
       const float(*src)[EPB][Np] = (a.mode == kModeTrace) ? sm.u : sm.un;
@@ -282,7 +266,7 @@ struct WedgeStage {
         }
         for (int c = 0; c < 4; ++c) sm.W[el][ef][l1][js][c] = acc[c];
       }
-    } else if (ph == 7) {
+    } else if (ph == 6) {
       // triangle lattice values c = Ft z; quad traces sum_js P1[l2][js] W[ef][l1][js] / sqrt(J)
       for (int it = tid; it < EPB * 2 * Nfn; it += NT) {
         const int el = it / (2 * Nfn), rr = it % (2 * Nfn);
@@ -311,7 +295,7 @@ struct WedgeStage {
         const float isj = a.isqJ[(e * 5 + f) * Nfq + q];
         a.tr_out[slot * Nfq + q] = make_float4(acc[0] * isj, acc[1] * isj, acc[2] * isj, acc[3] * isj);
       }
-    } else if (ph == 8) {
+    } else if (ph == 7) {
       for (int it = tid; it < EPB * 2 * Nfq; it += NT) {
         const int el = it / (2 * Nfq), rr = it % (2 * Nfq);
         const int tf = rr / Nfq, q = rr % Nfq;

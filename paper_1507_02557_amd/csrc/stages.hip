@@ -22,7 +22,7 @@ struct Occupancy<WedgeStage<N, E>> {
 };
 
 template <class S>
-__global__ __launch_bounds__(256, Occupancy<S>::value) void stage_kernel(StageArgs a) {
+__global__ __launch_bounds__(S::NT, Occupancy<S>::value) void stage_kernel(StageArgs a) {
   __shared__ typename S::Smem sm;
   S::load_ops(threadIdx.x, sm, a);
   __syncthreads();
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256, Occupancy<S>::value) void stage_kernel(StageAr
 }
 
 template <class S>
-__global__ __launch_bounds__(256) void mrab_update_kernel(StageArgs a) {
+__global__ __launch_bounds__(S::NT) void mrab_update_kernel(StageArgs a) {
   __shared__ typename S::Smem sm;
   S::load_ops(threadIdx.x, sm, a);
   __syncthreads();
