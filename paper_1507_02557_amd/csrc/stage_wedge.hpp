@@ -89,12 +89,26 @@ struct WedgeStage {
     const float* Ft = O + oFt;
     const float* Fe = O + oFe;
     const float* Ic = O + oIc;
+    // Global loads of a phase are issued together, from indices clamped to
+    // an element of the batch (item e0 always exists), and used after.
+    const int64_t e_any = item(a, e0);
     if (ph == 0) {
-      for (int it = tid; it < 4 * EPB * Np; it += NT) {
-        const int f = it / (EPB * Np), r = it % (EPB * Np);
-        const int el = r / Np, i = r % Np;
+      constexpr int NL = 4 * EPB * Np, RL = (NL + NT - 1) / NT;
+      float v[RL];
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int it = tid + r * NT;
+        const int itc = it < NL ? it : 0;
+        const int f = itc / (EPB * Np), rr = itc % (EPB * Np);
+        const int el = rr / Np, i = rr % Np;
         const int64_t e = item(a, e0 + el);
-        (&sm.u[0][0][0])[it] = (e >= 0) ? a.U[(int64_t)f * K * Np + e * Np + i] : 0.0f;
+        v[r] = a.U[(int64_t)f * K * Np + (e >= 0 ? e : e_any) * Np + i];
+        if (e < 0) v[r] = 0.f;
+      }
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int it = tid + r * NT;
+        if (it < NL) (&sm.u[0][0][0])[it] = v[r];
       }
       for (int it = tid; it < EPB; it += NT) {
         const int64_t e = item(a, e0 + it);
@@ -102,6 +116,28 @@ struct WedgeStage {
         sm.mat[it][1] = e >= 0 ? a.mat[e].y : 0.f;
       }
     } else if (ph == 1) {
+      // face data first, in flight during the s-contraction
+      constexpr int NF = EPB * 5 * Nfq, RF = (NF + NT - 1) / NT;
+      float4 fg[RF], fm[RF], fp[RF];
+      float fisj[RF];
+      float2 ftau[RF];
+      int fl[RF], fdst[RF];
+#pragma unroll
+      for (int r = 0; r < RF; ++r) {
+        const int it = tid + r * NT;
+        const int itc = it < NF ? it : 0;
+        const int el = itc / (5 * Nfq), rr = itc % (5 * Nfq);
+        const int f = rr / Nfq, q = rr % Nfq;
+        const int64_t e0v = item(a, e0 + el);
+        const int64_t e = e0v >= 0 ? e0v : e_any;
+        const int64_t slot = a.slot0 + e * 5 + f;
+        fg[r] = a.fgeo[(e * 5 + f) * Nfq + q];
+        face_states(a, slot, Nfq, q, fg[r], fm[r], fp[r]);
+        ftau[r] = a.tau[slot];
+        fisj[r] = a.isqJ[(e * 5 + f) * Nfq + q];
+        fl[r] = (f < 2) ? q : sm.qperm[a.ori[slot]][q];
+        fdst[r] = (it < NF && e0v >= 0) ? el * 5 + f : -1;
+      }
       for (int it = tid; it < EPB * 5 * n1 * Ntri; it += NT) {
         const int el = it / (5 * n1 * Ntri), rr = it % (5 * n1 * Ntri);
         const int c = rr / (n1 * Ntri), r2 = rr % (n1 * Ntri);
@@ -112,23 +148,30 @@ struct WedgeStage {
         for (int js = 0; js < n1; ++js) acc += op[qs * n1 + js] * sm.u[src][el][js * Ntri + jt];
         sm.A[c][el][qs][jt] = acc;
       }
-      for (int it = tid; it < EPB * 5 * Nfq; it += NT) {
-        const int el = it / (5 * Nfq), rr = it % (5 * Nfq);
-        const int f = rr / Nfq, q = rr % Nfq;
-        const int64_t e = item(a, e0 + el);
-        if (e < 0) continue;
-        const int64_t slot = a.slot0 + e * 5 + f;
-        const float4 g = a.fgeo[(e * 5 + f) * Nfq + q];
-        float4 m, p;
-        face_states(a, slot, Nfq, q, g, m, p);
+#pragma unroll
+      for (int r = 0; r < RF; ++r) {
+        if (fdst[r] < 0) continue;
         float out[4];
-        upwind_flux(m, p, g, a.tau[slot], true, out);
-        const float isj = a.isqJ[(e * 5 + f) * Nfq + q];
-        const int l = (f < 2) ? q : sm.qperm[a.ori[slot]][q];
-        for (int c = 0; c < 4; ++c) sm.g[el][f][l][c] = out[c] * isj;
+        upwind_flux(fm[r], fp[r], fg[r], ftau[r], true, out);
+        float* gd = sm.g[fdst[r] / 5][fdst[r] % 5][fl[r]];
+        for (int c = 0; c < 4; ++c) gd[c] = out[c] * fisj[r];
       }
     } else if (ph == 2) {
-      for (int it = tid; it < EPB * Nq; it += NT) {
+      constexpr int NB = EPB * Nq, RB = (NB + NT - 1) / NT;
+      float gq[RB][12];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int it = tid + r * NT;
+        const int itc = it < NB ? it : 0;
+        const int64_t e = item(a, e0 + itc / Nq);
+        const float* gp = a.geo + (e >= 0 ? e : e_any) * 12 * Nq + itc % Nq;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) gq[r][k] = gp[k * Nq];
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int it = tid + r * NT;
+        if (it >= NB) continue;
         const int el = it / Nq, q = it % Nq;
         const int qs = q / Nct, qt = q % Nct;
         const int64_t e = item(a, e0 + el);
@@ -146,14 +189,13 @@ struct WedgeStage {
           dPs += pt * sm.A[4][el][qs][jt];
           for (int d = 0; d < 3; ++d) U[d] += pt * sm.A[1 + d][el][qs][jt];
         }
-        const float* gp = a.geo + e * 12 * Nq + q;
         float G[3][3], hJ[3];
-        for (int r = 0; r < 3; ++r)
-          for (int d = 0; d < 3; ++d) G[r][d] = gp[(3 * r + d) * Nq];
-        for (int d = 0; d < 3; ++d) hJ[d] = gp[(9 + d) * Nq];
+        for (int i = 0; i < 3; ++i)
+          for (int d = 0; d < 3; ++d) G[i][d] = gq[r][3 * i + d];
+        for (int d = 0; d < 3; ++d) hJ[d] = gq[r][9 + d];
         const float w = Tw[qt] * w1[qs];
         const float dP[3] = {dPr, dPs, dPt};
-        for (int r = 0; r < 3; ++r) sm.B[r][el][q] = w * (G[r][0] * U[0] + G[r][1] * U[1] + G[r][2] * U[2]);
+        for (int i = 0; i < 3; ++i) sm.B[i][el][q] = w * (G[i][0] * U[0] + G[i][1] * U[1] + G[i][2] * U[2]);
         sm.B[3][el][q] = w * (hJ[0] * U[0] + hJ[1] * U[1] + hJ[2] * U[2]);
         for (int d = 0; d < 3; ++d)
           sm.B[4 + d][el][q] = w * (G[0][d] * dP[0] + G[1][d] * dP[1] + G[2][d] * dP[2] - P * hJ[d]);
@@ -177,6 +219,7 @@ struct WedgeStage {
         const int el = it / (n1 * Ntri), rr = it % (n1 * Ntri);
         const int qs = rr / Ntri, jt = rr % Ntri;
         float t0 = 0.f, t1 = 0.f, t2 = 0.f, t3 = 0.f, t4 = 0.f;
+#pragma unroll 5
         for (int qt = 0; qt < Nct; ++qt) {
           const int q = qs * Nct + qt;
           const float pt = Pt[qt * Ntri + jt];
@@ -215,14 +258,24 @@ struct WedgeStage {
         for (int c = 0; c < 4; ++c) sm.z[el][tf][jt][c] = acc[c];
       }
     } else if (ph == 4) {
-      for (int it = tid; it < EPB * Np; it += NT) {
+      constexpr int NN = EPB * Np, RN = (NN + NT - 1) / NT;
+      float rq[RN][4];
+#pragma unroll
+      for (int r = 0; r < RN; ++r) {
+        const int it = tid + r * NT;
+        const int itc = it < NN ? it : 0;
+        const int64_t e = item(a, e0 + itc / Np);
+        load_residual(a, (e >= 0 ? e : e_any) * Np + itc % Np, Np, rq[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < RN; ++r) {
+        const int it = tid + r * NT;
+        if (it >= NN) continue;
         const int el = it / Np, m = it % Np;
         const int js = m / Ntri, jt = m % Ntri;
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
         const int64_t base = e * Np + m;
-        float r0[4];
-        load_residual(a, base, Np, r0);
         float vp = 0.f, vu[3] = {0.f, 0.f, 0.f};
         for (int qs = 0; qs < n1; ++qs) {
           const float p1 = P1[qs * n1 + js];
@@ -239,7 +292,7 @@ struct WedgeStage {
         float rhs[4];
         rhs[0] = kap * (vp + sf[0]);
         for (int d = 0; d < 3; ++d) rhs[1 + d] = irho * (vu[d] + sf[1 + d]);
-        node_update(a, e, Np, base, rhs, r0, &sm.u[0][el][m], &sm.un[0][el][m], EPB * Np);
+        node_update(a, e, Np, base, rhs, rq[r], &sm.u[0][el][m], &sm.un[0][el][m], EPB * Np);
       }
     } else if (ph == 5) {
       // s-contractions of the traces: triangle faces z[tf][jt] = sum_js P1f[tf][js] u[js][jt],
@@ -268,6 +321,20 @@ struct WedgeStage {
       }
     } else if (ph == 6) {
       // triangle lattice values c = Ft z; quad traces sum_js P1[l2][js] W[ef][l1][js] / sqrt(J)
+      constexpr int NQ = EPB * 3 * Nfq, RQ = (NQ + NT - 1) / NT;
+      int qo[RQ];
+      float qisj[RQ];
+#pragma unroll
+      for (int r = 0; r < RQ; ++r) {
+        const int it = tid + r * NT;
+        const int itc = it < NQ ? it : 0;
+        const int el = itc / (3 * Nfq), rr = itc % (3 * Nfq);
+        const int f = 2 + rr / Nfq, q = rr % Nfq;
+        const int64_t e = item(a, e0 + el);
+        const int64_t es = e >= 0 ? e : e_any;
+        qo[r] = a.ori[a.slot0 + es * 5 + f];
+        qisj[r] = a.isqJ[(es * 5 + f) * Nfq + q];
+      }
       for (int it = tid; it < EPB * 2 * Nfn; it += NT) {
         const int el = it / (2 * Nfn), rr = it % (2 * Nfn);
         const int tf = rr / Nfn, l = rr % Nfn;
@@ -278,21 +345,24 @@ struct WedgeStage {
         }
         for (int c = 0; c < 4; ++c) sm.c[el][tf][l][c] = acc[c];
       }
-      for (int it = tid; it < EPB * 3 * Nfq; it += NT) {
+#pragma unroll
+      for (int r = 0; r < RQ; ++r) {
+        const int it = tid + r * NT;
+        if (it >= NQ) continue;
         const int el = it / (3 * Nfq), rr = it % (3 * Nfq);
         const int ef = rr / Nfq, q = rr % Nfq;
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
         const int f = 2 + ef;
         const int64_t slot = a.slot0 + e * 5 + f;
-        const int l = sm.qperm[a.ori[slot]][q];
+        const int l = sm.qperm[qo[r]][q];
         const int l1 = l % n1, l2 = l / n1;
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int js = 0; js < n1; ++js) {
           const float w = P1[l2 * n1 + js];
           for (int c = 0; c < 4; ++c) acc[c] += w * sm.W[el][ef][l1][js][c];
         }
-        const float isj = a.isqJ[(e * 5 + f) * Nfq + q];
+        const float isj = qisj[r];
         a.tr_out[slot * Nfq + q] = make_float4(acc[0] * isj, acc[1] * isj, acc[2] * isj, acc[3] * isj);
       }
     } else if (ph == 7) {

@@ -31,7 +31,12 @@ __global__ __launch_bounds__(S::NT, Occupancy<S>::value) void stage_kernel(Stage
   for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
     for (int ph = 0; ph < S::nphase; ++ph) {
       if (!S::active(ph, a.mode)) continue;
-      S::phase(ph, threadIdx.x, sm, a, b * EPB);
+      // an opaque copy of the thread index keeps each phase's index
+      // arithmetic inside the loop (hoisted out of it, the values of all
+      // phases would stay live in registers across the whole batch loop)
+      int t = threadIdx.x;
+      __asm__ volatile("" : "+v"(t));
+      S::phase(ph, t, sm, a, b * EPB);
       __syncthreads();
     }
   }
@@ -46,7 +51,9 @@ __global__ __launch_bounds__(S::NT) void mrab_update_kernel(StageArgs a) {
   const int64_t nb = (a.n_items + EPB - 1) / EPB;
   for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
     for (int st = 0; st < MrabUpdate<S>::nstep; ++st) {
-      MrabUpdate<S>::step(st, threadIdx.x, sm, a, b * EPB);
+      int t = threadIdx.x;
+      __asm__ volatile("" : "+v"(t));
+      MrabUpdate<S>::step(st, t, sm, a, b * EPB);
       __syncthreads();
     }
   }
