@@ -61,12 +61,26 @@ struct HexStage {
 
   HD static void phase(int ph, int tid, Smem& sm, const StageArgs& a, int64_t e0) {
     const int64_t K = a.K;
+    // Global loads of a phase are issued together, from indices clamped to
+    // an element of the batch (item e0 always exists), and used after.
+    const int64_t e_any = item(a, e0);
     if (ph == 0) {
-      for (int it = tid; it < 4 * EPB * Np; it += NT) {
-        const int f = it / (EPB * Np), r = it % (EPB * Np);
-        const int el = r / Np, i = r % Np;
+      constexpr int NL = 4 * EPB * Np, RL = (NL + NT - 1) / NT;
+      float v[RL];
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int it = tid + r * NT;
+        const int itc = it < NL ? it : 0;
+        const int f = itc / (EPB * Np), rr = itc % (EPB * Np);
+        const int el = rr / Np, i = rr % Np;
         const int64_t e = item(a, e0 + el);
-        (&sm.u[0][0][0])[it] = (e >= 0) ? a.U[(int64_t)f * K * Np + e * Np + i] : 0.0f;
+        v[r] = a.U[(int64_t)f * K * Np + (e >= 0 ? e : e_any) * Np + i];
+        if (e < 0) v[r] = 0.f;
+      }
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int it = tid + r * NT;
+        if (it < NL) (&sm.u[0][0][0])[it] = v[r];
       }
       for (int it = tid; it < EPB; it += NT) {
         const int64_t e = item(a, e0 + it);
@@ -74,14 +88,45 @@ struct HexStage {
         sm.mat[it][1] = e >= 0 ? a.mat[e].y : 0.f;
       }
     } else if (ph == 1) {
-      for (int it = tid; it < EPB * 6 * Nfq; it += NT) {
+      constexpr int NF = EPB * 6 * Nfq, RF = (NF + NT - 1) / NT;
+      float4 fg[RF], fp[RF];
+      float2 ftau[RF];
+      int fo[RF], fnb[RF];
+#pragma unroll
+      for (int r = 0; r < RF; ++r) {
+        const int it = tid + r * NT;
+        const int itc = it < NF ? it : 0;
+        const int el = itc / (6 * Nfq), rr = itc % (6 * Nfq);
+        const int f = rr / Nfq, q = rr % Nfq;
+        const int64_t e0v = item(a, e0 + el);
+        const int64_t e = e0v >= 0 ? e0v : e_any;
+        const int64_t slot = a.slot0 + e * 6 + f;
+        fg[r] = a.fgeo[(e * 6 + f) * Nfq + q];
+        fo[r] = a.ori[slot];
+        fnb[r] = a.nbr[slot];
+        ftau[r] = a.tau[slot];
+      }
+#pragma unroll
+      for (int r = 0; r < RF; ++r) {
+        const int it = tid + r * NT;
+        const int itc = it < NF ? it : 0;
+        const int el = itc / (6 * Nfq), rr = itc % (6 * Nfq);
+        const int f = rr / Nfq, q = rr % Nfq;
+        const int64_t e0v = item(a, e0 + el);
+        const int64_t e = e0v >= 0 ? e0v : e_any;
+        const int64_t slot = a.slot0 + e * 6 + f;
+        if (fnb[r] >= 0) fp[r] = neighbour_src(a, slot, fnb[r])[(int64_t)fnb[r] * Nfq + q];
+      }
+#pragma unroll
+      for (int r = 0; r < RF; ++r) {
+        const int it = tid + r * NT;
+        if (it >= NF) continue;
         const int el = it / (6 * Nfq), rr = it % (6 * Nfq);
         const int f = rr / Nfq, q = rr % Nfq;
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
-        const int64_t slot = a.slot0 + e * 6 + f;
-        const float4 g = a.fgeo[(e * 6 + f) * Nfq + q];
-        const int l = sm.qperm[a.ori[slot]][q];
+        const float4 g = fg[r];
+        const int l = sm.qperm[fo[r]][q];
         // own trace recomputed from the state (Algorithm 2), not read back
         const int l1 = l % n1, l2 = l / n1;
         const float* L = sm.Lf[f & 1];
@@ -91,21 +136,34 @@ struct HexStage {
           for (int c = 0; c < 4; ++c) mv[c] += L[k] * sm.u[c][el][nd];
         }
         const float4 m = make_float4(mv[0], mv[1], mv[2], mv[3]);
-        const int nb = a.nbr[slot];
-        const float4 p = nb >= 0 ? neighbour_src(a, slot, nb)[(int64_t)nb * Nfq + q]
-                                 : mirror_state(m, -nb - 1, g.x, g.y, g.z);
+        const int nb = fnb[r];
+        const float4 p = nb >= 0 ? fp[r] : mirror_state(m, -nb - 1, g.x, g.y, g.z);
         float out[4];
-        upwind_flux(m, p, g, a.tau[slot], false, out);
+        upwind_flux(m, p, g, ftau[r], false, out);
         for (int c = 0; c < 4; ++c) sm.g[el][f][l][c] = out[c];
       }
     } else if (ph == 2) {
-      for (int it = tid; it < EPB * Np; it += NT) {
+      constexpr int NN = EPB * Np, RN = (NN + NT - 1) / NT;
+      float rq[RN][4], gq[RN][10];
+#pragma unroll
+      for (int r = 0; r < RN; ++r) {
+        const int it = tid + r * NT;
+        const int itc = it < NN ? it : 0;
+        const int64_t e = item(a, e0 + itc / Np);
+        const int64_t es = e >= 0 ? e : e_any;
+        load_residual(a, es * Np + itc % Np, Np, rq[r]);
+        const float* gp = a.geo + es * 10 * Np + itc % Np;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) gq[r][k] = gp[k * Np];
+      }
+#pragma unroll
+      for (int r = 0; r < RN; ++r) {
+        const int it = tid + r * NT;
+        if (it >= NN) continue;
         const int el = it / Np, node = it % Np;
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
         const int64_t base = e * Np + node;
-        float r0[4];
-        load_residual(a, base, Np, r0);
         const int i = node % n1, j = (node / n1) % n1, k = node / (n1 * n1);
         float du[4][3];
         for (int c = 0; c < 4; ++c) {
@@ -120,13 +178,12 @@ struct HexStage {
           du[c][2] = dt;
         }
         float G[3][3];
-        const float* gp = a.geo + e * 10 * Np + node;
-        for (int r = 0; r < 3; ++r)
-          for (int d = 0; d < 3; ++d) G[r][d] = gp[(3 * r + d) * Np];
-        const float iwJ = gp[9 * Np];
+        for (int x = 0; x < 3; ++x)
+          for (int d = 0; d < 3; ++d) G[x][d] = gq[r][3 * x + d];
+        const float iwJ = gq[r][9];
         float div = 0.f;
-        for (int r = 0; r < 3; ++r)
-          for (int d = 0; d < 3; ++d) div += G[r][d] * du[1 + d][r];
+        for (int x = 0; x < 3; ++x)
+          for (int d = 0; d < 3; ++d) div += G[x][d] * du[1 + d][x];
         float surf[4];
         for (int c = 0; c < 4; ++c)
           surf[c] = sm.Lf[0][i] * sm.g[el][0][k * n1 + j][c] + sm.Lf[1][i] * sm.g[el][1][k * n1 + j][c] +
@@ -137,17 +194,29 @@ struct HexStage {
         rhs[0] = kap * (-div + iwJ * surf[0]);
         for (int d = 0; d < 3; ++d)
           rhs[1 + d] = irho * (-(G[0][d] * du[0][0] + G[1][d] * du[0][1] + G[2][d] * du[0][2]) + iwJ * surf[1 + d]);
-        node_update(a, e, Np, base, rhs, r0, &sm.u[0][el][node], &sm.un[0][el][node], EPB * Np);
+        node_update(a, e, Np, base, rhs, rq[r], &sm.u[0][el][node], &sm.un[0][el][node], EPB * Np);
       }
     } else if (ph == 3) {
       const float(*src)[EPB][Np] = (a.mode == kModeTrace) ? sm.u : sm.un;
-      for (int it = tid; it < EPB * 6 * Nfq; it += NT) {
+      constexpr int NF = EPB * 6 * Nfq, RF = (NF + NT - 1) / NT;
+      int fo[RF];
+#pragma unroll
+      for (int r = 0; r < RF; ++r) {
+        const int it = tid + r * NT;
+        const int itc = it < NF ? it : 0;
+        const int64_t e = item(a, e0 + itc / (6 * Nfq));
+        fo[r] = a.ori[a.slot0 + (e >= 0 ? e : e_any) * 6 + (itc % (6 * Nfq)) / Nfq];
+      }
+#pragma unroll
+      for (int r = 0; r < RF; ++r) {
+        const int it = tid + r * NT;
+        if (it >= NF) continue;
         const int el = it / (6 * Nfq), rr = it % (6 * Nfq);
         const int f = rr / Nfq, q = rr % Nfq;
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
         const int64_t slot = a.slot0 + e * 6 + f;
-        const int l = sm.qperm[a.ori[slot]][q];
+        const int l = sm.qperm[fo[r]][q];
         const int l1 = l % n1, l2 = l / n1;
         const float* L = sm.Lf[f & 1];
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
