@@ -210,7 +210,10 @@ struct MrabUpdate {
     StageArgs b = a;
     b.mode = kModeStage;
     if (st == 0) {
-      S::phase(0, tid, sm, a, e0);
+      // phase 0 in trace mode only loads the batch's state
+      StageArgs l = a;
+      l.mode = kModeTrace;
+      S::phase(0, tid, sm, l, e0);
     } else if (st == 1) {
       combine(tid, sm, a, e0, false);
     } else if (st < 2 + T) {

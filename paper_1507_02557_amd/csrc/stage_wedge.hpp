@@ -29,8 +29,8 @@ struct WedgeStage {
   static constexpr int Nfn = Ntri;
   static constexpr int NT = 256;
   static constexpr int kEPB = EPB;
-  static constexpr int nphase = 8;
-  static constexpr int kTraceBegin = 5;  // first phase that writes traces
+  static constexpr int nphase = 6;
+  static constexpr int kTraceBegin = 3;  // first phase that writes traces
   // ops: Pt, Ptr, Ptt [Nct][Ntri]; tri_w [Nct]; P1, dP1 [n1][n1]; w1 [n1];
   //      P1f [2][n1]; Ftri [Nfn][Ntri]; Fedge [3][n1][Ntri]; Ican [Nfq][Nfn]
   static constexpr int oPt = 0, oPtr = oPt + Nct * Ntri, oPtt = oPtr + Nct * Ntri, oTw = oPtt + Nct * Ntri;
@@ -44,22 +44,23 @@ struct WedgeStage {
     int qperm[8][Nfq];
     int tperm[6][Nfn];
     float u[4][EPB][Np];
-    // buffers whose lifetimes do not overlap share storage (phases in
-    // brackets write / read them):
+    // buffers whose lifetimes do not overlap share storage (phase parts in
+    // brackets write / read them: 0 loads and face fluxes, 1a s-contraction,
+    // 1b volume values, 2a test contractions, 2b node update, 3-5 traces):
     union {
-      float A[5][EPB][n1][Ntri];  // s-contracted state [1] / [2]
-      float T[5][EPB][n1][Ntri];  // test contractions with the quad faces folded in [3] / [4]
+      float A[5][EPB][n1][Ntri];  // s-contracted state [1a] / [1b]
+      float T[5][EPB][n1][Ntri];  // test contractions with the quad faces folded in [2a] / [2b]
     };
     union {
-      float B[7][EPB][Nq];            // trial integrands at the volume points [2] / [3]
-      float W[EPB][3][n1][n1][4];     // quad-face trace operands [5] / [6]
+      float B[7][EPB][Nq];            // trial integrands at the volume points [1b] / [2a]
+      float W[EPB][3][n1][n1][4];     // quad-face trace operands [3] / [4]
     };
     union {
-      float g[EPB][5][Nfq][4];  // weighted face fluxes [1] / [2, 3]
-      float un[4][EPB][Np];     // updated state [4] / [5, 6, 7]
+      float g[EPB][5][Nfq][4];  // weighted face fluxes [0] / [1b, 2a]
+      float un[4][EPB][Np];     // updated state [2b] / [3, 4, 5]
     };
     float c[EPB][2][Nfn][4];
-    float z[EPB][2][Ntri][4];   // triangle-face operands [3, 5] / [4, 6]
+    float z[EPB][2][Ntri][4];   // triangle-face operands [2a, 3] / [2b, 4]
     float mat[EPB][2];
   };
 
@@ -105,18 +106,9 @@ struct WedgeStage {
         v[r] = a.U[(int64_t)f * K * Np + (e >= 0 ? e : e_any) * Np + i];
         if (e < 0) v[r] = 0.f;
       }
-#pragma unroll
-      for (int r = 0; r < RL; ++r) {
-        const int it = tid + r * NT;
-        if (it < NL) (&sm.u[0][0][0])[it] = v[r];
-      }
-      for (int it = tid; it < EPB; it += NT) {
-        const int64_t e = item(a, e0 + it);
-        sm.mat[it][0] = e >= 0 ? a.mat[e].x : 0.f;
-        sm.mat[it][1] = e >= 0 ? a.mat[e].y : 0.f;
-      }
-    } else if (ph == 1) {
-      // face data first, in flight during the s-contraction
+      // faces: the own trace comes from the trace buffer, so the flux needs no
+      // state and its loads are in flight together with the state loads
+      const bool flux = a.mode != kModeTrace;
       constexpr int NF = EPB * 5 * Nfq, RF = (NF + NT - 1) / NT;
       float4 fg[RF], fm[RF], fp[RF];
       float fisj[RF];
@@ -131,6 +123,10 @@ struct WedgeStage {
         const int64_t e0v = item(a, e0 + el);
         const int64_t e = e0v >= 0 ? e0v : e_any;
         const int64_t slot = a.slot0 + e * 5 + f;
+        if (!flux) {
+          fdst[r] = -1;
+          continue;
+        }
         fg[r] = a.fgeo[(e * 5 + f) * Nfq + q];
         face_states(a, slot, Nfq, q, fg[r], fm[r], fp[r]);
         ftau[r] = a.tau[slot];
@@ -138,15 +134,15 @@ struct WedgeStage {
         fl[r] = (f < 2) ? q : sm.qperm[a.ori[slot]][q];
         fdst[r] = (it < NF && e0v >= 0) ? el * 5 + f : -1;
       }
-      for (int it = tid; it < EPB * 5 * n1 * Ntri; it += NT) {
-        const int el = it / (5 * n1 * Ntri), rr = it % (5 * n1 * Ntri);
-        const int c = rr / (n1 * Ntri), r2 = rr % (n1 * Ntri);
-        const int qs = r2 / Ntri, jt = r2 % Ntri;
-        const float* op = (c < 4) ? P1 : dP1;
-        const int src = (c < 4) ? c : 0;
-        float acc = 0.f;
-        for (int js = 0; js < n1; ++js) acc += op[qs * n1 + js] * sm.u[src][el][js * Ntri + jt];
-        sm.A[c][el][qs][jt] = acc;
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int it = tid + r * NT;
+        if (it < NL) (&sm.u[0][0][0])[it] = v[r];
+      }
+      for (int it = tid; it < EPB; it += NT) {
+        const int64_t e = item(a, e0 + it);
+        sm.mat[it][0] = e >= 0 ? a.mat[e].x : 0.f;
+        sm.mat[it][1] = e >= 0 ? a.mat[e].y : 0.f;
       }
 #pragma unroll
       for (int r = 0; r < RF; ++r) {
@@ -156,7 +152,8 @@ struct WedgeStage {
         float* gd = sm.g[fdst[r] / 5][fdst[r] % 5][fl[r]];
         for (int c = 0; c < 4; ++c) gd[c] = out[c] * fisj[r];
       }
-    } else if (ph == 2) {
+    } else if (ph == 1) {
+      // geometric factors in flight during the s-contraction
       constexpr int NB = EPB * Nq, RB = (NB + NT - 1) / NT;
       float gq[RB][12];
 #pragma unroll
@@ -168,6 +165,19 @@ struct WedgeStage {
 #pragma unroll
         for (int k = 0; k < 12; ++k) gq[r][k] = gp[k * Nq];
       }
+      for (int it = tid; it < EPB * 5 * n1 * Ntri; it += NT) {
+        const int el = it / (5 * n1 * Ntri), rr = it % (5 * n1 * Ntri);
+        const int c = rr / (n1 * Ntri), r2 = rr % (n1 * Ntri);
+        const int qs = r2 / Ntri, jt = r2 % Ntri;
+        const float* op = (c < 4) ? P1 : dP1;
+        const int src = (c < 4) ? c : 0;
+        float acc = 0.f;
+        for (int js = 0; js < n1; ++js) acc += op[qs * n1 + js] * sm.u[src][el][js * Ntri + jt];
+        sm.A[c][el][qs][jt] = acc;
+      }
+      // the rest of the phase reads what the first part wrote: one barrier
+      // (every thread of the block runs every phase)
+      __syncthreads();
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         const int it = tid + r * NT;
@@ -214,7 +224,17 @@ struct WedgeStage {
         const int l = sm.tperm[o][m];
         for (int c = 0; c < 4; ++c) sm.c[el][tf][l][c] = acc[c];
       }
-    } else if (ph == 3) {
+    } else if (ph == 2) {
+      // residual in flight during the test contractions
+      constexpr int NN = EPB * Np, RN = (NN + NT - 1) / NT;
+      float rq[RN][4];
+#pragma unroll
+      for (int r = 0; r < RN; ++r) {
+        const int it = tid + r * NT;
+        const int itc = it < NN ? it : 0;
+        const int64_t e = item(a, e0 + itc / Np);
+        load_residual(a, (e >= 0 ? e : e_any) * Np + itc % Np, Np, rq[r]);
+      }
       for (int it = tid; it < EPB * n1 * Ntri; it += NT) {
         const int el = it / (n1 * Ntri), rr = it % (n1 * Ntri);
         const int qs = rr / Ntri, jt = rr % Ntri;
@@ -257,16 +277,9 @@ struct WedgeStage {
         }
         for (int c = 0; c < 4; ++c) sm.z[el][tf][jt][c] = acc[c];
       }
-    } else if (ph == 4) {
-      constexpr int NN = EPB * Np, RN = (NN + NT - 1) / NT;
-      float rq[RN][4];
-#pragma unroll
-      for (int r = 0; r < RN; ++r) {
-        const int it = tid + r * NT;
-        const int itc = it < NN ? it : 0;
-        const int64_t e = item(a, e0 + itc / Np);
-        load_residual(a, (e >= 0 ? e : e_any) * Np + itc % Np, Np, rq[r]);
-      }
+      // the rest of the phase reads what the first part wrote: one barrier
+      // (every thread of the block runs every phase)
+      __syncthreads();
 #pragma unroll
       for (int r = 0; r < RN; ++r) {
         const int it = tid + r * NT;
@@ -294,7 +307,7 @@ struct WedgeStage {
         for (int d = 0; d < 3; ++d) rhs[1 + d] = irho * (vu[d] + sf[1 + d]);
         node_update(a, e, Np, base, rhs, rq[r], &sm.u[0][el][m], &sm.un[0][el][m], EPB * Np);
       }
-    } else if (ph == 5) {
+    } else if (ph == 3) {
       // s-contractions of the traces: triangle faces z[tf][jt] = sum_js P1f[tf][js] u[js][jt],
       // quad faces W[ef][l1][js] = sum_jt Fe[ef][l1][jt] u[js][jt]
       const float(*src)[EPB][Np] = (a.mode == kModeTrace) ? sm.u : sm.un;
@@ -319,7 +332,7 @@ struct WedgeStage {
         }
         for (int c = 0; c < 4; ++c) sm.W[el][ef][l1][js][c] = acc[c];
       }
-    } else if (ph == 6) {
+    } else if (ph == 4) {
       // triangle lattice values c = Ft z; quad traces sum_js P1[l2][js] W[ef][l1][js] / sqrt(J)
       constexpr int NQ = EPB * 3 * Nfq, RQ = (NQ + NT - 1) / NT;
       int qo[RQ];
@@ -365,7 +378,7 @@ struct WedgeStage {
         const float isj = qisj[r];
         a.tr_out[slot * Nfq + q] = make_float4(acc[0] * isj, acc[1] * isj, acc[2] * isj, acc[3] * isj);
       }
-    } else if (ph == 7) {
+    } else if (ph == 5) {
       for (int it = tid; it < EPB * 2 * Nfq; it += NT) {
         const int el = it / (2 * Nfq), rr = it % (2 * Nfq);
         const int tf = rr / Nfq, q = rr % Nfq;
