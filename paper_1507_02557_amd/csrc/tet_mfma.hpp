@@ -43,7 +43,12 @@ struct TetMfma {
   static constexpr int Mt = (Np + 15) / 16;  // 16-row tiles of the element operators
   static constexpr int Ks = (Np + 3) / 4;    // k-steps over element nodes
   static constexpr int Kf = (Nfn + 3) / 4;   // k-steps over one face's lattice
-  static constexpr int SX = (4 * Ks) | 1;    // odd row strides, padded rows stay zero
+  // Odd row strides.  An odd Np is its own stride: the tile is then one flat
+  // array, so the tile stores read aligned 16-byte LDS vectors, and a
+  // B-fragment read past the end of a row meets finite values of the next
+  // row (the operator columns there are zero).  Otherwise the rows are padded
+  // and the padding stays zero.
+  static constexpr int SX = (Np & 1) ? Np : ((4 * Ks) | 1);
   static constexpr int SF = (4 * Kf) | 1;
   static constexpr int NT = 64 * NW;
   static constexpr int KsP = (Np + KK - 1) / KK;   // k-steps over nodes at this precision
@@ -53,7 +58,7 @@ struct TetMfma {
   static constexpr int kOpsFloats = kDFloats + kLFloats + 2;  // + inverse operator scales
   static constexpr int kOpsInts = 4 * Nfn + 6 * Nfn;
 
-  struct Wave {
+  struct alignas(16) Wave {
     float X[4][16][SX];  // state tile (p, ux, uy, uz)
     float F[4][16][SF];  // one face's scaled flux; staging of one output field
   };
@@ -123,8 +128,10 @@ struct TetMfma {
   template <int S>
   __device__ static void put_field(float (*dst)[S], const float4 (&v)[JQ], int lane) {
 #pragma unroll
-    for (int j = 0; j < JQ; ++j)
-      if (lane + 64 * j < Q4) put4<S>(dst, 4 * (lane + 64 * j), v[j]);
+    for (int j = 0; j < JQ; ++j) {
+      if (lane + 64 * j >= Q4) continue;
+      put4<S>(dst, 4 * (lane + 64 * j), v[j]);
+    }
   }
   template <int S>
   __device__ static void store_tile(float* dst, const float (*src)[S], const StageArgs& a, int64_t e0, int lane,
@@ -132,8 +139,13 @@ struct TetMfma {
     if (contig) {
       float4* d4 = reinterpret_cast<float4*>(dst + e0 * Np);
 #pragma unroll
-      for (int j = 0; j < JQ; ++j)
-        if (lane + 64 * j < Q4) d4[lane + 64 * j] = get4<S>(src, 4 * (lane + 64 * j));
+      for (int j = 0; j < JQ; ++j) {
+        if (lane + 64 * j >= Q4) continue;
+        if constexpr (S == Np)
+          d4[lane + 64 * j] = reinterpret_cast<const float4*>(&src[0][0])[lane + 64 * j];
+        else
+          d4[lane + 64 * j] = get4<S>(src, 4 * (lane + 64 * j));
+      }
     } else {
       store_rows<S>(dst, src, a, e0, lane);
     }
