@@ -59,12 +59,32 @@ __global__ __launch_bounds__(S::NT) void mrab_update_kernel(StageArgs a) {
   }
 }
 
+// Blocks of a kernel that the whole device holds at once.  The persistent
+// grid is never larger: blocks beyond that number would start only when the
+// first ones finish, and the last of them would run alone.
+static int64_t resident_blocks(const void* kernel, int nt) {
+  int per_cu = 0, dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess || per_cu < 1 || ncu < 1)
+    return 2048;
+  return (int64_t)per_cu * ncu;
+}
+
 template <class S>
 static int go(const StageArgs& a, hipStream_t s, bool mrab) {
   static_assert(sizeof(typename S::Smem) <= 160 * 1024, "LDS budget exceeded");
   if (a.n_items == 0) return 0;
   const int64_t nb = (a.n_items + S::kEPB - 1) / S::kEPB;
-  const unsigned grid = (unsigned)(nb < 2048 ? nb : 2048);
+  int64_t cap;
+  if (mrab) {
+    static const int64_t c = resident_blocks(reinterpret_cast<const void*>(&mrab_update_kernel<S>), S::NT);
+    cap = c;
+  } else {
+    static const int64_t c = resident_blocks(reinterpret_cast<const void*>(&stage_kernel<S>), S::NT);
+    cap = c;
+  }
+  const unsigned grid = (unsigned)(nb < cap ? nb : cap);
   if (mrab) hipLaunchKernelGGL(mrab_update_kernel<S>, dim3(grid), dim3(S::NT), 0, s, a);
   else hipLaunchKernelGGL(stage_kernel<S>, dim3(grid), dim3(S::NT), 0, s, a);
   return 0;
