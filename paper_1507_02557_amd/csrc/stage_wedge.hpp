@@ -62,6 +62,8 @@ struct WedgeStage {
     float c[EPB][2][Nfn][4];
     float z[EPB][2][Ntri][4];   // triangle-face operands [2a, 3] / [2b, 4]
     float mat[EPB][2];
+    float isj[EPB][5][Nfq];  // 1/sqrt(J) at the face points [0] / [0, 4, 5]
+    int fori[EPB][5];        // face orientation codes [0] / [0, 4, 5]
   };
 
   HD static bool active(int ph, int mode) {
@@ -113,7 +115,7 @@ struct WedgeStage {
       float4 fg[RF], fm[RF], fp[RF];
       float fisj[RF];
       float2 ftau[RF];
-      int fl[RF], fdst[RF];
+      int fo[RF], fdst[RF];
 #pragma unroll
       for (int r = 0; r < RF; ++r) {
         const int it = tid + r * NT;
@@ -123,16 +125,13 @@ struct WedgeStage {
         const int64_t e0v = item(a, e0 + el);
         const int64_t e = e0v >= 0 ? e0v : e_any;
         const int64_t slot = a.slot0 + e * 5 + f;
-        if (!flux) {
-          fdst[r] = -1;
-          continue;
-        }
+        fisj[r] = a.isqJ[(e * 5 + f) * Nfq + q];
+        fo[r] = a.ori[slot];
+        fdst[r] = (it < NF && e0v >= 0) ? el * 5 + f : -1;
+        if (!flux) continue;
         fg[r] = a.fgeo[(e * 5 + f) * Nfq + q];
         face_states(a, slot, Nfq, q, fg[r], fm[r], fp[r]);
         ftau[r] = a.tau[slot];
-        fisj[r] = a.isqJ[(e * 5 + f) * Nfq + q];
-        fl[r] = (f < 2) ? q : sm.qperm[a.ori[slot]][q];
-        fdst[r] = (it < NF && e0v >= 0) ? el * 5 + f : -1;
       }
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
@@ -147,9 +146,14 @@ struct WedgeStage {
 #pragma unroll
       for (int r = 0; r < RF; ++r) {
         if (fdst[r] < 0) continue;
+        const int el = fdst[r] / 5, f = fdst[r] % 5, q = (tid + r * NT) % Nfq;
+        sm.isj[el][f][q] = fisj[r];
+        if (q == 0) sm.fori[el][f] = fo[r];
+        if (!flux) continue;
         float out[4];
         upwind_flux(fm[r], fp[r], fg[r], ftau[r], true, out);
-        float* gd = sm.g[fdst[r] / 5][fdst[r] % 5][fl[r]];
+        const int l = (f < 2) ? q : sm.qperm[fo[r]][q];
+        float* gd = sm.g[el][f][l];
         for (int c = 0; c < 4; ++c) gd[c] = out[c] * fisj[r];
       }
     } else if (ph == 1) {
@@ -215,7 +219,7 @@ struct WedgeStage {
         const int tf = rr / Nfn, m = rr % Nfn;
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
-        const int o = a.ori[a.slot0 + e * 5 + tf];
+        const int o = sm.fori[el][tf];
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int q = 0; q < Nfq; ++q) {
           const float w = Ic[q * Nfn + m];
@@ -334,20 +338,6 @@ struct WedgeStage {
       }
     } else if (ph == 4) {
       // triangle lattice values c = Ft z; quad traces sum_js P1[l2][js] W[ef][l1][js] / sqrt(J)
-      constexpr int NQ = EPB * 3 * Nfq, RQ = (NQ + NT - 1) / NT;
-      int qo[RQ];
-      float qisj[RQ];
-#pragma unroll
-      for (int r = 0; r < RQ; ++r) {
-        const int it = tid + r * NT;
-        const int itc = it < NQ ? it : 0;
-        const int el = itc / (3 * Nfq), rr = itc % (3 * Nfq);
-        const int f = 2 + rr / Nfq, q = rr % Nfq;
-        const int64_t e = item(a, e0 + el);
-        const int64_t es = e >= 0 ? e : e_any;
-        qo[r] = a.ori[a.slot0 + es * 5 + f];
-        qisj[r] = a.isqJ[(es * 5 + f) * Nfq + q];
-      }
       for (int it = tid; it < EPB * 2 * Nfn; it += NT) {
         const int el = it / (2 * Nfn), rr = it % (2 * Nfn);
         const int tf = rr / Nfn, l = rr % Nfn;
@@ -358,24 +348,21 @@ struct WedgeStage {
         }
         for (int c = 0; c < 4; ++c) sm.c[el][tf][l][c] = acc[c];
       }
-#pragma unroll
-      for (int r = 0; r < RQ; ++r) {
-        const int it = tid + r * NT;
-        if (it >= NQ) continue;
+      for (int it = tid; it < EPB * 3 * Nfq; it += NT) {
         const int el = it / (3 * Nfq), rr = it % (3 * Nfq);
         const int ef = rr / Nfq, q = rr % Nfq;
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
         const int f = 2 + ef;
         const int64_t slot = a.slot0 + e * 5 + f;
-        const int l = sm.qperm[qo[r]][q];
+        const int l = sm.qperm[sm.fori[el][f]][q];
         const int l1 = l % n1, l2 = l / n1;
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int js = 0; js < n1; ++js) {
           const float w = P1[l2 * n1 + js];
           for (int c = 0; c < 4; ++c) acc[c] += w * sm.W[el][ef][l1][js][c];
         }
-        const float isj = qisj[r];
+        const float isj = sm.isj[el][f][q];
         a.tr_out[slot * Nfq + q] = make_float4(acc[0] * isj, acc[1] * isj, acc[2] * isj, acc[3] * isj);
       }
     } else if (ph == 5) {
@@ -385,14 +372,14 @@ struct WedgeStage {
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
         const int64_t slot = a.slot0 + e * 5 + tf;
-        const int o = a.ori[slot];
+        const int o = sm.fori[el][tf];
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int m = 0; m < Nfn; ++m) {
           const float w = Ic[q * Nfn + m];
           const int l = sm.tperm[o][m];
           for (int c = 0; c < 4; ++c) acc[c] += w * sm.c[el][tf][l][c];
         }
-        const float isj = a.isqJ[(e * 5 + tf) * Nfq + q];
+        const float isj = sm.isj[el][tf][q];
         a.tr_out[slot * Nfq + q] = make_float4(acc[0] * isj, acc[1] * isj, acc[2] * isj, acc[3] * isj);
       }
     }

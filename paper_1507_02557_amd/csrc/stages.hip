@@ -18,7 +18,7 @@ struct Occupancy {
 };
 template <int N, int E>
 struct Occupancy<WedgeStage<N, E>> {
-  static constexpr int value = N <= 4 ? 3 : 1;
+  static constexpr int value = N == 4 ? 5 : (N < 4 ? 3 : 1);
 };
 
 template <class S>
