@@ -25,7 +25,7 @@ PATHS = [hdg.PATH_AUTO, hdg.PATH_GENERIC]
 
 
 @pytest.fixture(scope="module")
-def c1_mesh():
+def slab4_mesh():
     return four_slab_mesh(4, seed=0, jitter=0.1)
 
 
@@ -36,9 +36,9 @@ def _global_dt(disc, d_el):
     return out
 
 
-def test_dt_matches_oracle(c1_mesh):
-    d = Disc(c1_mesh, 3)
-    s = hdg.Solver(c1_mesh, 3)
+def test_dt_matches_oracle(slab4_mesh):
+    d = Disc(slab4_mesh, 3)
+    s = hdg.Solver(slab4_mesh, 3)
     dte, mn = s.dt(0.5)
     ref = _global_dt(d, d.dt_elements(0.5))
     assert np.max(np.abs(dte - ref) / ref) < 1e-12
@@ -47,9 +47,9 @@ def test_dt_matches_oracle(c1_mesh):
 
 @pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 5])
-def test_rhs_matches_oracle(c1_mesh, N, path):
-    d = Disc(c1_mesh, N)
-    s = hdg.Solver(c1_mesh, N, path=path)
+def test_rhs_matches_oracle(slab4_mesh, N, path):
+    d = Disc(slab4_mesh, N)
+    s = hdg.Solver(slab4_mesh, N, path=path)
     assert s.get_path() == (path, 1 if path == hdg.PATH_AUTO else 0)
     U = random_state(d, seed=N)
     set_lib_state(s, U)
@@ -93,13 +93,13 @@ def test_single_type_meshes(slabs, n, path):
 
 @pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("N", [2, 4])
-def test_ragged_batches_match_oracle(c1_mesh, N, path):
+def test_ragged_batches_match_oracle(slab4_mesh, N, path):
     """A patch of the n=4 mesh whose per-type element counts are not multiples
     of the kernels' batch and tile sizes (odd counts, partial 16-element tiles):
     right-hand side and three LSERK4 steps against the oracle."""
     rng = np.random.default_rng(11)
-    centre = np.concatenate([rng.choice(np.nonzero(c1_mesh.etype == t)[0], 3, replace=False) for t in range(4)])
-    m, _, _ = patch_mesh(c1_mesh, centre)
+    centre = np.concatenate([rng.choice(np.nonzero(slab4_mesh.etype == t)[0], 3, replace=False) for t in range(4)])
+    m, _, _ = patch_mesh(slab4_mesh, centre)
     counts = [int(np.sum(m.etype == t)) for t in range(4)]
     print("element counts per type", counts)
     assert any(k % 2 == 1 for k in counts) and any(k % 16 != 0 for k in counts)
@@ -120,20 +120,20 @@ def test_ragged_batches_match_oracle(c1_mesh, N, path):
     assert rel < 1e-5
 
 
-def test_projection_matches_oracle(c1_mesh):
-    d = Disc(c1_mesh, 3)
-    s = hdg.Solver(c1_mesh, 3)
+def test_projection_matches_oracle(slab4_mesh):
+    d = Disc(slab4_mesh, 3)
+    s = hdg.Solver(slab4_mesh, 3)
     s.project_function(standing_mode_rigid)
     err = type_rel_err(lib_state_to_oracle(s), d.project(standing_mode_rigid))
     assert max(err.values()) < 1e-6, err
 
 
 @pytest.mark.parametrize("path", PATHS)
-def test_c1_standing_mode_100_steps(c1_mesh, path):
-    """Configuration 1: n=4 jittered four-slab mesh, N=3, rigid walls, standing
+def test_slab4_standing_mode_100_steps(slab4_mesh, path):
+    """The n=4 jittered four-slab mesh, N=3, rigid walls, standing
     mode, 100 LSERK4 steps at the derived stable step: rel L2 <= 1e-5."""
-    d = Disc(c1_mesh, 3)
-    s = hdg.Solver(c1_mesh, 3, path=path)
+    d = Disc(slab4_mesh, 3)
+    s = hdg.Solver(slab4_mesh, 3, path=path)
     dt = d.dt_min(0.5)
     Uo = d.project(standing_mode_rigid)
     s.project_function(standing_mode_rigid)
@@ -144,7 +144,7 @@ def test_c1_standing_mode_100_steps(c1_mesh, path):
     s.step(dt, 100)
     Ul = lib_state_to_oracle(s)
     rel = d.rel_l2(Ul, Uo)
-    print("C1 rel L2 after 100 steps:", rel)
+    print("n=4 mesh, rel L2 after 100 steps:", rel)
     assert rel < 1e-5
     E1 = s.energy()
     assert abs(E1 - d.energy(Uo)) < 1e-6 * E1
@@ -154,8 +154,8 @@ def test_c1_standing_mode_100_steps(c1_mesh, path):
     assert abs(e_lib - e_or) < 1e-3 * e_or
 
 
-def test_energy_nonincreasing(c1_mesh):
-    s = hdg.Solver(c1_mesh, 3)
+def test_energy_nonincreasing(slab4_mesh):
+    s = hdg.Solver(slab4_mesh, 3)
     s.project_function(standing_mode_rigid)
     _, dt = s.dt(0.5)
     E = [s.energy()]
@@ -165,10 +165,10 @@ def test_energy_nonincreasing(c1_mesh):
     assert all(b <= a * (1 + 1e-6) for a, b in zip(E, E[1:])), E
 
 
-def test_bitwise_deterministic(c1_mesh):
+def test_bitwise_deterministic(slab4_mesh):
     out = []
     for _ in range(2):
-        s = hdg.Solver(c1_mesh, 4)
+        s = hdg.Solver(slab4_mesh, 4)
         s.project_function(standing_mode_rigid)
         _, dt = s.dt(0.5)
         s.step(dt, 7)
@@ -185,8 +185,8 @@ def test_inverted_element_rejected():
 
 
 def test_full_size_sampled_rhs():
-    """Configuration 2 size (n=48 four-slab mesh, N=4, 527,616 elements) in the
-    benchmark's launch configuration: a random state, one right-hand side,
+    """The benchmark's workload (n=48 four-slab mesh, N=4, 527,616 elements) in
+    its launch configuration: a random state, one right-hand side,
     checked against the oracle on a patch around 160 sampled elements."""
     m = four_slab_mesh(48, seed=0, jitter=0.1)
     s = hdg.Solver(m, 4)
@@ -231,14 +231,14 @@ def test_full_size_sampled_rhs():
 
 @pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("N,L", [(2, 3), (3, 2)])
-def test_mrab_matches_oracle(c1_mesh, N, L, path):
+def test_mrab_matches_oracle(slab4_mesh, N, L, path):
     """Multi-rate AB3 (levels, start-up and coarse steps) against the oracle."""
     from oracle.mrab import MRAB3
-    d = Disc(c1_mesh, N)
+    d = Disc(slab4_mesh, N)
     mr = MRAB3(d, L)
-    s = hdg.Solver(c1_mesh, N, path=path)
+    s = hdg.Solver(slab4_mesh, N, path=path)
     dtmin, cnt, lev = s.mrab_setup(L)
-    g = np.zeros(c1_mesh.n_elem, dtype=np.int64)
+    g = np.zeros(slab4_mesh.n_elem, dtype=np.int64)
     for t in d.types:
         g[d.els[t]] = mr.level[t]
     assert np.array_equal(g, lev.astype(np.int64))
@@ -256,7 +256,7 @@ def test_mrab_matches_oracle(c1_mesh, N, L, path):
 
 
 def test_mrab_full_size_runs_and_stays_bounded():
-    """Configuration-3 style multi-rate run on the n=48 four-slab mesh, N=3, three
+    """Multi-rate run on the n=48 four-slab mesh, N=3, three
     levels: start-up and one coarse step stay finite with bounded energy."""
     m = four_slab_mesh(48, seed=0, jitter=0.1)
     s = hdg.Solver(m, 3)
@@ -269,18 +269,18 @@ def test_mrab_full_size_runs_and_stays_bounded():
     assert np.isfinite(E1) and E1 <= E0 * (1 + 1e-3)
 
 
-def test_paths_agree_after_steps(c1_mesh):
+def test_paths_agree_after_steps(slab4_mesh):
     """Lattice traces with matrix-core tetrahedra and cubature traces with the
     vector kernels compute the same operator: 20 LSERK4 steps agree to FP32
     rounding."""
     out = []
     for path in PATHS:
-        s = hdg.Solver(c1_mesh, 4, path=path)
+        s = hdg.Solver(slab4_mesh, 4, path=path)
         s.project_function(standing_mode_rigid)
         _, dt = s.dt(0.5)
         s.step(dt, 20)
         out.append({t: s.get_field(t).double().cpu().numpy() for t in s.types})
-    d = Disc(c1_mesh, 4)
+    d = Disc(slab4_mesh, 4)
     assert d.rel_l2(out[0], out[1]) < 2e-6
 
 
@@ -318,11 +318,11 @@ PRECS = [hdg.PREC_FP16X2, hdg.PREC_FP16X2_K16]
 
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 5])
-def test_split_precision_rhs_matches_oracle(c1_mesh, N, prec):
+def test_split_precision_rhs_matches_oracle(slab4_mesh, N, prec):
     """Split-FP16 matrix-core products: the right-hand side stays within the
     FP32 tolerance of the FP64 oracle."""
-    d = Disc(c1_mesh, N)
-    s = hdg.Solver(c1_mesh, N, precision=prec)
+    d = Disc(slab4_mesh, N)
+    s = hdg.Solver(slab4_mesh, N, precision=prec)
     U = random_state(d, seed=20 + N)
     set_lib_state(s, U)
     Rl = {t: v.double().cpu().numpy() for t, v in s.rhs().items()}
@@ -332,10 +332,10 @@ def test_split_precision_rhs_matches_oracle(c1_mesh, N, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_split_precision_c1_100_steps(c1_mesh, prec):
-    """Configuration 1 with split-FP16 products: rel L2 <= 1e-5 after 100 steps."""
-    d = Disc(c1_mesh, 3)
-    s = hdg.Solver(c1_mesh, 3, precision=prec)
+def test_split_precision_slab4_100_steps(slab4_mesh, prec):
+    """The n=4 mesh at N=3 with split-FP16 products: rel L2 <= 1e-5 after 100 steps."""
+    d = Disc(slab4_mesh, 3)
+    s = hdg.Solver(slab4_mesh, 3, precision=prec)
     dt = d.dt_min(0.5)
     Uo = d.project(standing_mode_rigid)
     s.project_function(standing_mode_rigid)
@@ -343,15 +343,15 @@ def test_split_precision_c1_100_steps(c1_mesh, prec):
         Uo = lserk4_step(d, Uo, dt)
     s.step(dt, 100)
     rel = d.rel_l2(lib_state_to_oracle(s), Uo)
-    print("prec", prec, "C1 rel L2 after 100 steps:", rel)
+    print("prec", prec, "n=4 mesh, rel L2 after 100 steps:", rel)
     assert rel < 1e-5
 
 
-def test_split_precision_mrab(c1_mesh):
+def test_split_precision_mrab(slab4_mesh):
     from oracle.mrab import MRAB3
-    d = Disc(c1_mesh, 3)
+    d = Disc(slab4_mesh, 3)
     mr = MRAB3(d, 3)
-    s = hdg.Solver(c1_mesh, 3, precision=hdg.PREC_FP16X2)
+    s = hdg.Solver(slab4_mesh, 3, precision=hdg.PREC_FP16X2)
     s.mrab_setup(3)
     U = mr.startup(d.project(standing_mode_rigid))
     s.project_function(standing_mode_rigid)

@@ -7,7 +7,7 @@ from oracle.mesh import match_faces, vertex_map
 from paper_1507_02557_amd.inputs import HEX, PYR, TET, WEDGE, four_slab_mesh
 
 
-def test_c1_counts():
+def test_slab4_counts():
     m = four_slab_mesh(4, seed=0)
     assert m.counts() == {"hex": 16, "wedge": 32, "pyr": 16, "tet": 256}
 

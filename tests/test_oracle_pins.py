@@ -290,7 +290,7 @@ def test_lserk4_stability_polynomial():
     assert 0.0 < c[5] < 1.0 / 120
 
 
-def test_standing_mode_rigid_c1():
+def test_standing_mode_rigid_slab4():
     """Rigid-walled cube, N=3, jittered n=4 mesh, 100 LSERK4 steps at the derived dt:
     the error stays at the projection-error level and the energy does not grow."""
     d = Disc(four_slab_mesh(4, seed=0, jitter=0.1), 3)
