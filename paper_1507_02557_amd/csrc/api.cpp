@@ -186,9 +186,12 @@ int build_tables(hdg_ctx* c, int t, std::vector<float>& ops, std::vector<int>& i
     iops.insert(iops.end(), ft.tri_perm.begin(), ft.tri_perm.end());
   } else {
     const WedgeRef& W = c->wedge;
-    append(ops, W.Pt);
-    append(ops, W.Ptr);
-    append(ops, W.Ptt);
+    for (size_t i = 0; i < W.Pt.size(); ++i) {
+      ops.push_back((float)W.Pt[i]);
+      ops.push_back((float)W.Ptr[i]);
+      ops.push_back((float)W.Ptt[i]);
+      ops.push_back(0.f);
+    }
     append(ops, W.tri_w);
     append(ops, W.P1);
     append(ops, W.dP1);

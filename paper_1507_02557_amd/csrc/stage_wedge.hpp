@@ -31,9 +31,9 @@ struct WedgeStage {
   static constexpr int kEPB = EPB;
   static constexpr int nphase = 6;
   static constexpr int kTraceBegin = 3;  // first phase that writes traces
-  // ops: Pt, Ptr, Ptt [Nct][Ntri]; tri_w [Nct]; P1, dP1 [n1][n1]; w1 [n1];
+  // ops: (Pt, Ptr, Ptt, 0) [Nct][Ntri][4]; tri_w [Nct]; P1, dP1 [n1][n1]; w1 [n1];
   //      P1f [2][n1]; Ftri [Nfn][Ntri]; Fedge [3][n1][Ntri]; Ican [Nfq][Nfn]
-  static constexpr int oPt = 0, oPtr = oPt + Nct * Ntri, oPtt = oPtr + Nct * Ntri, oTw = oPtt + Nct * Ntri;
+  static constexpr int oP3 = 0, oTw = oP3 + 4 * Nct * Ntri;
   static constexpr int oP1 = oTw + Nct, odP1 = oP1 + n1 * n1, ow1 = odP1 + n1 * n1, oP1f = ow1 + n1;
   static constexpr int oFt = oP1f + 2 * n1, oFe = oFt + Nfn * Ntri, oIc = oFe + 3 * n1 * Ntri;
   static constexpr int kOpsFloats = oIc + Nfq * Nfn;
@@ -52,8 +52,8 @@ struct WedgeStage {
       float T[5][EPB][n1][Ntri];  // test contractions with the quad faces folded in [2a] / [2b]
     };
     union {
-      float B[7][EPB][Nq];            // trial integrands at the volume points [1b] / [2a]
-      float W[EPB][3][n1][n1][4];     // quad-face trace operands [3] / [4]
+      alignas(16) float B[EPB][Nq][8];  // trial integrands at the volume points (7 used) [1b] / [2a]
+      float W[EPB][3][n1][n1][4];       // quad-face trace operands [3] / [4]
     };
     union {
       float g[EPB][5][Nfq][4];  // weighted face fluxes [0] / [1b, 2a]
@@ -81,9 +81,8 @@ struct WedgeStage {
   HD static void phase(int ph, int tid, Smem& sm, const StageArgs& a, int64_t e0) {
     const int64_t K = a.K;
     const float* O = sm.ops;
-    const float* Pt = O + oPt;
-    const float* Ptr = O + oPtr;
-    const float* Ptt = O + oPtt;
+    // triangle basis and its r, t derivatives at the triangle points, read as one vector
+    const float4* P3 = reinterpret_cast<const float4*>(O + oP3);
     const float* Tw = O + oTw;
     const float* P1 = O + oP1;
     const float* dP1 = O + odP1;
@@ -189,17 +188,19 @@ struct WedgeStage {
         const int el = it / Nq, q = it % Nq;
         const int qs = q / Nct, qt = q % Nct;
         const int64_t e = item(a, e0 + el);
+        float4* bd = reinterpret_cast<float4*>(sm.B[el][q]);
         if (e < 0) {
-          for (int k = 0; k < 7; ++k) sm.B[k][el][q] = 0.f;
+          bd[0] = bd[1] = make_float4(0.f, 0.f, 0.f, 0.f);
           continue;
         }
         float P = 0.f, dPr = 0.f, dPt = 0.f, dPs = 0.f, U[3] = {0.f, 0.f, 0.f};
         for (int jt = 0; jt < Ntri; ++jt) {
-          const float pt = Pt[qt * Ntri + jt];
+          const float4 pv = P3[qt * Ntri + jt];
+          const float pt = pv.x;
           const float a0 = sm.A[0][el][qs][jt];
           P += pt * a0;
-          dPr += Ptr[qt * Ntri + jt] * a0;
-          dPt += Ptt[qt * Ntri + jt] * a0;
+          dPr += pv.y * a0;
+          dPt += pv.z * a0;
           dPs += pt * sm.A[4][el][qs][jt];
           for (int d = 0; d < 3; ++d) U[d] += pt * sm.A[1 + d][el][qs][jt];
         }
@@ -209,10 +210,12 @@ struct WedgeStage {
         for (int d = 0; d < 3; ++d) hJ[d] = gq[r][9 + d];
         const float w = Tw[qt] * w1[qs];
         const float dP[3] = {dPr, dPs, dPt};
-        for (int i = 0; i < 3; ++i) sm.B[i][el][q] = w * (G[i][0] * U[0] + G[i][1] * U[1] + G[i][2] * U[2]);
-        sm.B[3][el][q] = w * (hJ[0] * U[0] + hJ[1] * U[1] + hJ[2] * U[2]);
-        for (int d = 0; d < 3; ++d)
-          sm.B[4 + d][el][q] = w * (G[0][d] * dP[0] + G[1][d] * dP[1] + G[2][d] * dP[2] - P * hJ[d]);
+        float Bv[7];
+        for (int i = 0; i < 3; ++i) Bv[i] = w * (G[i][0] * U[0] + G[i][1] * U[1] + G[i][2] * U[2]);
+        Bv[3] = w * (hJ[0] * U[0] + hJ[1] * U[1] + hJ[2] * U[2]);
+        for (int d = 0; d < 3; ++d) Bv[4 + d] = w * (G[0][d] * dP[0] + G[1][d] * dP[1] + G[2][d] * dP[2] - P * hJ[d]);
+        bd[0] = make_float4(Bv[0], Bv[1], Bv[2], Bv[3]);
+        bd[1] = make_float4(Bv[4], Bv[5], Bv[6], 0.f);
       }
       for (int it = tid; it < EPB * 2 * Nfn; it += NT) {
         const int el = it / (2 * Nfn), rr = it % (2 * Nfn);
@@ -246,12 +249,14 @@ struct WedgeStage {
 #pragma unroll 5
         for (int qt = 0; qt < Nct; ++qt) {
           const int q = qs * Nct + qt;
-          const float pt = Pt[qt * Ntri + jt];
-          t0 += Ptr[qt * Ntri + jt] * sm.B[0][el][q] + Ptt[qt * Ntri + jt] * sm.B[2][el][q] - pt * sm.B[3][el][q];
-          t1 += pt * sm.B[1][el][q];
-          t2 += pt * sm.B[4][el][q];
-          t3 += pt * sm.B[5][el][q];
-          t4 += pt * sm.B[6][el][q];
+          const float4 pv = P3[qt * Ntri + jt];
+          const float4* bs = reinterpret_cast<const float4*>(sm.B[el][q]);
+          const float4 b0 = bs[0], b1 = bs[1];
+          t0 += pv.y * b0.x + pv.z * b0.z - pv.x * b0.w;
+          t1 += pv.x * b0.y;
+          t2 += pv.x * b1.x;
+          t3 += pv.x * b1.y;
+          t4 += pv.x * b1.z;
         }
         // quad faces: their s points are the volume points qs, so their test
         // integrals share the final s-contraction with the volume terms
