@@ -807,15 +807,16 @@ int hdg_create(hdg_ctx** out, const hdg_mesh* m, int N, int precision, void* hip
 
 void hdg_destroy(hdg_ctx* c) {
   if (!c) return;
+  // teardown: errors cannot be reported any more, every resource is released anyway
   if (!c->allocs.empty()) {
-    if (c->stream) hipStreamSynchronize(c->stream);
-    else hipDeviceSynchronize();
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
   }
   for (auto& p : c->ev_pool) {
-    hipEventDestroy(p[0]);
-    hipEventDestroy(p[1]);
+    (void)hipEventDestroy(p[0]);
+    (void)hipEventDestroy(p[1]);
   }
-  for (void* p : c->allocs) hipFree(p);
+  for (void* p : c->allocs) (void)hipFree(p);
   delete c;
 }
 
@@ -869,8 +870,9 @@ int hdg_project(hdg_ctx* c, int t, const double* p, const double* ux, const doub
                  c->stream);
   hipError_t e = hipGetLastError();
   if (tmp) {
-    hipStreamSynchronize(c->stream);
-    hipFree(tmp);
+    const hipError_t es = hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);  // freed on every path; a failure here is reported by the next call
+    if (e == hipSuccess) e = es;
   }
   if (e != hipSuccess) return fail(c, HDG_EHIP, std::string("projection: ") + hipGetErrorString(e));
   c->traces_valid = false;
