@@ -147,7 +147,7 @@ def main():
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.copy_mib > 0:
         copy_calibration(args.copy_mib)
