@@ -375,6 +375,24 @@ class Disc:
         return np.sqrt(err)
 
     # ------------------------------------------------------------------
+    def min_jacobian(self, t):
+        """min J of each element of type t, the 1/||J^{-1}||_inf of C_J^K (Section 3.4).
+
+        The paper approximates the sup norms by maxima over quadrature points;
+        here the element's vertices are added to the volume points (hex GL
+        nodes, pyramid semi-nodal points (a_i, b_j)), so that a corner where
+        the trilinear Jacobian dips below its value at the GL nodes is seen.
+        For the pyramid J is bilinear in (a, b) and independent of c, so the
+        four base vertices give its exact minimum.  Tetrahedra: J is constant.
+        """
+        J = self.geo[t]["J"]
+        if J.ndim == 1:
+            return J
+        E = self.refs[t]
+        corners = E.vref if t == R.HEX else E.vref[:4]
+        _, _, Jv, _ = OM.vertex_map(E, corners, self.V[t])
+        return np.minimum(np.min(J, axis=1), np.min(Jv, axis=1))
+
     def dt_elements(self, cfl: float = 0.5):
         """Local stable steps dtau_K = C / (C_rhokappa C_T(N) C_J^K) (Section 3, eq. dtK)."""
         out = {}
@@ -393,9 +411,7 @@ class Disc:
             if t == R.WEDGE:
                 cj = np.max((jsr / self.fJ[sl]).reshape(e.size, -1), axis=1)
             else:
-                J = self.geo[t]["J"]
-                jmin = J if J.ndim == 1 else np.min(J, axis=1)
-                cj = np.max(jsr.reshape(e.size, -1), axis=1) / jmin
+                cj = np.max(jsr.reshape(e.size, -1), axis=1) / self.min_jacobian(t)
             out[t] = cfl / (c_rk * trace_constant(t, self.N) * cj)
         return out
 

@@ -45,6 +45,19 @@ __global__ __launch_bounds__(64) void geometry_kernel(GeoArgs g) {
       g.geo[base + 9 * g.nvp] = (type == 0) ? (float)(1.0 / (g.vw[i] * J)) : (float)J;
     }
   }
+  // ---- vertices: ||J^-1||_inf of C_J^K is taken over the volume points and
+  // the corners (hex: all eight; pyramid: the four base vertices, where its
+  // J, bilinear in (a, b) and independent of c, takes its extremes)
+  if (type == 0 || type == 2) {
+    const int ncorner = type == 0 ? 8 : 4;
+    for (int v = 0; v < ncorner; ++v) {
+      double x[3], F[3][3];
+      const double X[3] = {T.vref[type][v][0], T.vref[type][v][1], T.vref[type][v][2]};
+      vmap(type, V, X, x, F);
+      const double J = det3(F);
+      minJ = J < minJ ? J : minJ;
+    }
+  }
   // ---- faces
   minJall = minJ;
   double cj = 0.0;
