@@ -134,25 +134,41 @@ int hdg_type_info(const hdg_ctx* ctx, int t, int64_t* n_elem, int32_t* np, int32
  * dt_min_out (host) the minimum.  Either may be NULL.  cfl = C > 0. */
 int hdg_dt(hdg_ctx* ctx, double cfl, double* dt_out, double* dt_min_out);
 
-/* Physical sample points (device, float64 [K_t][n_sample][3]) of type t. */
+/* Physical sample points of type t: the images under the element's vertex
+ * map (Section 2.1, the vertex-mapped elements of each type) of the
+ * reference sample points that hdg_type_info counts.  xyz_dev: device,
+ * float64 [K_t][n_sample][3], caller-owned, written asynchronously on the
+ * context's stream.  Errors: HDG_EINVAL (type absent from the mesh, NULL). */
 int hdg_get_points(hdg_ctx* ctx, int t, double* xyz_dev);
 
 /* Set the state of type t from samples of the four fields at the points of
- * hdg_get_points (device, float64, each [K_t][n_sample]): interpolation at
- * nodes (hex, tet); L2 projection with the element's own mass (wedge:
- * u_i = sum_q w_q sqrt(J_q) phi_i(q) f_q; pyramid:
- * u_i = sum_q w_q J_q phi_i(q) f_q / J(a_i, b_j)). */
+ * hdg_get_points (device, float64, each [K_t][n_sample], caller-owned):
+ * interpolation at nodes (hex, tet: nodal bases of Sections 2.1.1-2.1.2);
+ * L2 projection with the element's own mass (wedge, Section 2.1.3, LSC-DG
+ * mass = I: u_i = sum_q w_q sqrt(J_q) phi_i(q) f_q; pyramid, Section 2.1.4,
+ * diagonal mass J(a_i, b_j): u_i = sum_q w_q J_q phi_i(q) f_q / J(a_i, b_j)).
+ * The paper does not say how initial data enter; this is the projection its
+ * mass matrices define.  Wedges and pyramids use a device work buffer of
+ * 4 K_t n_sample doubles that the call allocates and frees (it synchronises
+ * the stream).  Errors: HDG_EINVAL, HDG_ENOMEM, HDG_EHIP. */
 int hdg_project(hdg_ctx* ctx, int t, const double* p, const double* ux, const double* uy,
                 const double* uz);
 
-/* Copy the state (which = 0) or the last right-hand side (which = 1) of type
- * t into / out of caller device buffers, each float [K_t][Np]. */
+/* Copy the state (which = 0) or the last right-hand side / LSERK residual
+ * (which = 1) of type t into / out of caller device buffers, each float
+ * [K_t][Np] (the dofs of the type's basis, Section 2.1; meaning per type in
+ * the conventions above).  Asynchronous device-to-device copies on the
+ * context's stream; nothing is retained.  hdg_set_state invalidates the
+ * traces and the multi-rate history (the next step rebuilds the traces and
+ * restarts the history) and leaves the time unchanged.  Errors: HDG_EINVAL. */
 int hdg_set_state(hdg_ctx* ctx, int t, const float* p, const float* ux, const float* uy,
                   const float* uz);
 int hdg_get_field(hdg_ctx* ctx, int which, int t, float* p, float* ux, float* uy, float* uz);
 
 /* Evaluate the semi-discrete right-hand side dU/dt = M^{-1} A U of the
- * current state into the context's rhs buffers (read with hdg_get_field). */
+ * current state (Section 2.2 flux, Section 2.3 volume/surface/update
+ * kernels, Section 3.1 for the operator A) into the context's rhs buffers
+ * (read with hdg_get_field, which = 1).  Asynchronous.  Errors: HDG_EHIP. */
 int hdg_rhs(hdg_ctx* ctx);
 
 /* Advance the state by n_steps single-rate LSERK4 steps of size dt (the
@@ -181,9 +197,63 @@ int hdg_mrab_setup(hdg_ctx* ctx, int n_levels, double cfl, double* dt_min_out, i
  * Errors: HDG_ESTATE if hdg_mrab_setup was not called. */
 int hdg_mrab_advance(hdg_ctx* ctx, int64_t n_coarse, double* t_advanced);
 
-/* Energy E = 1/2 sum_K (p^T M p / kappa + rho u^T M u) of the current state,
- * accumulated in FP64 on the device (synchronises the stream). */
+/* Energy E = 1/2 sum_K (p^T M p / kappa + rho u^T M u) of the current state
+ * (Section 3.1: the quantity eq. sym shows the upwind flux cannot increase),
+ * with the element mass matrices of Section 2.1, accumulated in FP64 on the
+ * device; E (host) receives it.  Synchronises the stream.  Errors:
+ * HDG_EINVAL (NULL), HDG_ENONFINITE (E is NaN or Inf; *E is still set). */
 int hdg_energy(hdg_ctx* ctx, double* E);
+
+/* Simulated time of the context's state (host value).  hdg_create sets 0;
+ * hdg_step adds n_steps dt, hdg_mrab_advance the time it advances,
+ * hdg_advance ends at t_final; hdg_project and hdg_set_state leave it
+ * unchanged (set it with hdg_set_time).  Errors: HDG_EINVAL (NULL, t not
+ * finite). */
+int hdg_get_time(const hdg_ctx* ctx, double* t);
+int hdg_set_time(hdg_ctx* ctx, double t);
+
+/* Watchdog: HDG_ENONFINITE if any state value of any type is NaN or Inf,
+ * else HDG_OK.  Synchronises the stream.  Errors: HDG_EHIP. */
+int hdg_check_finite(hdg_ctx* ctx);
+
+#define HDG_STEPPER_LSERK4 0
+#define HDG_STEPPER_MRAB3 1
+
+/* Advance from the current time t to t_final (Section 2.2 poses the problem
+ * on a time interval [0, T]).  The step is shortened so that it divides the
+ * interval exactly:
+ *   HDG_STEPPER_LSERK4: n = ceil((t_final - t) / dtau_min) steps of
+ *     dt = (t_final - t) / n, dtau_min = min_K dtau_K(cfl) (Section 3.4,
+ *     eq. dtK);
+ *   HDG_STEPPER_MRAB3 (after hdg_mrab_setup; cfl is ignored, the levels
+ *     keep the set-up's): n coarse steps of the levels' coarse step, all
+ *     level steps scaled by the same factor <= 1.  If the scaled steps differ
+ *     from those of the history in flight (or no history exists yet) the
+ *     history is restarted (start-up of two coarse steps, so n >= 2).
+ * Every check_every steps (coarse steps for MRAB3; 0: only at the end) and at
+ * the end, the state is checked for NaN/Inf; a non-finite state stops the
+ * advance with HDG_ENONFINITE.  steps_done (host, may be NULL) receives the
+ * steps taken (LSERK4 steps or coarse steps, start-up included).  On success
+ * the time is t_final.  Synchronises the stream at each check.  Errors:
+ * HDG_EINVAL (t_final < t, cfl <= 0 for LSERK4, bad stepper), HDG_ESTATE
+ * (MRAB3 without hdg_mrab_setup), HDG_ENONFINITE, HDG_EHIP. */
+int hdg_advance(hdg_ctx* ctx, double t_final, int stepper, double cfl, int64_t check_every,
+                int64_t* steps_done);
+
+/* Checkpoint / resume.  A checkpoint holds the time, the state of every
+ * type and, when a multi-rate history is in flight, the right-hand-side
+ * history of every level (Section 2.4: each level keeps the right-hand sides
+ * of its last three steps), the history slot rotation and the level step; a
+ * run continued from hdg_checkpoint_load takes bit-identical steps to the
+ * uninterrupted one.  host_buf: host memory of hdg_checkpoint_size bytes,
+ * caller-owned (save writes it, load reads it; both synchronise the
+ * stream).  Loading into a context needs the same mesh and order, and for a
+ * multi-rate checkpoint the same hdg_mrab_setup (checked by level counts and
+ * a hash of the level of every element).  Errors: HDG_EINVAL (NULL, size too
+ * small, checkpoint of another mesh/order/level set-up), HDG_EHIP. */
+int hdg_checkpoint_size(const hdg_ctx* ctx, int64_t* bytes);
+int hdg_checkpoint_save(hdg_ctx* ctx, void* host_buf, int64_t bytes);
+int hdg_checkpoint_load(hdg_ctx* ctx, const void* host_buf, int64_t bytes);
 
 /* Kernel timing for benchmarking.  While enabled (on != 0), hdg_step and
  * hdg_rhs bracket every stage-kernel launch with HIP events on the context's

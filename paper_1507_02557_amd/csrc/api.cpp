@@ -104,6 +104,9 @@ struct hdg_ctx {
   std::vector<std::array<hipEvent_t, 2>> ev_pool;
   std::vector<int> ev_type;
   size_t ev_used = 0;
+  double time = 0.0;           // simulated time of the state
+  double mr_dtmin0 = 0.0;      // dtau_min of hdg_mrab_setup (hdg_advance may scale it down)
+  std::vector<int8_t> level_h; // multi-rate level per element (mesh order)
 };
 
 namespace {
@@ -919,9 +922,11 @@ int hdg_step(hdg_ctx* c, double dt, int64_t n_steps) {
   int rc = ensure_traces(c);
   if (rc) return rc;
   c->mr_ready = false;
-  for (int64_t n = 0; n < n_steps; ++n)
+  for (int64_t n = 0; n < n_steps; ++n) {
     for (int s = 0; s < 5; ++s)
       if ((rc = run_stage(c, kModeStage, (float)kRkA[s], (float)kRkB[s], (float)dt))) return rc;
+    c->time += dt;
+  }
   return HDG_OK;
 }
 
@@ -1053,6 +1058,8 @@ int hdg_mrab_setup(hdg_ctx* c, int n_levels, double cfl, double* dt_min_out, int
   }
   c->L = L;
   c->mr_dtmin = dtmin;
+  c->mr_dtmin0 = dtmin;
+  c->level_h.assign(lev.begin(), lev.end());
   std::vector<int8_t> slev(c->nslot);
   for (int64_t s = 0; s < c->nslot; ++s) slev[s] = (int8_t)lev[c->slot_elem_h[s]];
   if (!c->slevel && (rc = dalloc(c, &c->slevel, c->nslot))) return rc;
@@ -1090,10 +1097,11 @@ int hdg_mrab_setup(hdg_ctx* c, int n_levels, double cfl, double* dt_min_out, int
   return HDG_OK;
 }
 
-int hdg_mrab_advance(hdg_ctx* c, int64_t n_coarse, double* t_advanced) {
-  if (!c) return HDG_EINVAL;
-  if (c->L < 1) return fail(c, HDG_ESTATE, "hdg_mrab_setup has not been called");
-  if (n_coarse < 0) return fail(c, HDG_EINVAL, "n_coarse must be >= 0");
+namespace {
+
+// n_coarse multi-rate coarse steps after the start-up (which runs first, for
+// two coarse steps, when no history is in flight); adds the simulated time.
+int mrab_run(hdg_ctx* c, int64_t n_coarse, double* t_advanced) {
   int rc = ensure_traces(c);
   if (rc) return rc;
   const int L = c->L;
@@ -1118,7 +1126,241 @@ int hdg_mrab_advance(hdg_ctx* c, int64_t n_coarse, double* t_advanced) {
     }
     tadv += nsub * c->mr_dtmin;
   }
+  c->time += tadv;
   if (t_advanced) *t_advanced = tadv;
+  return HDG_OK;
+}
+
+// flag[0] = 1 if any state value is NaN or Inf (flag cleared by a fill
+// kernel, so the sequence may sit in a captured graph)
+int check_finite_impl(hdg_ctx* c, bool* finite) {
+  launch_fill_int(c->flag, 1, 0, c->stream);
+  for (int t = 0; t < 4; ++t) {
+    const TypeData& d = c->td[t];
+    if (d.present) launch_finite((int64_t)4 * d.K * d.Np, d.U, c->flag, c->stream);
+  }
+  HIPCHK(c, hipGetLastError());
+  int h = 0;
+  HIPCHK(c, hipMemcpyAsync(&h, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *finite = h == 0;
+  return HDG_OK;
+}
+
+}  // namespace
+
+int hdg_mrab_advance(hdg_ctx* c, int64_t n_coarse, double* t_advanced) {
+  if (!c) return HDG_EINVAL;
+  if (c->L < 1) return fail(c, HDG_ESTATE, "hdg_mrab_setup has not been called");
+  if (n_coarse < 0) return fail(c, HDG_EINVAL, "n_coarse must be >= 0");
+  return mrab_run(c, n_coarse, t_advanced);
+}
+
+int hdg_get_time(const hdg_ctx* c, double* t) {
+  if (!c || !t) return HDG_EINVAL;
+  *t = c->time;
+  return HDG_OK;
+}
+
+int hdg_set_time(hdg_ctx* c, double t) {
+  if (!c) return HDG_EINVAL;
+  if (!std::isfinite(t)) return fail(c, HDG_EINVAL, "time must be finite");
+  c->time = t;
+  return HDG_OK;
+}
+
+int hdg_check_finite(hdg_ctx* c) {
+  if (!c) return HDG_EINVAL;
+  bool fin = true;
+  int rc = check_finite_impl(c, &fin);
+  if (rc) return rc;
+  return fin ? HDG_OK : fail(c, HDG_ENONFINITE, "the state holds a NaN or Inf");
+}
+
+int hdg_advance(hdg_ctx* c, double t_final, int stepper, double cfl, int64_t check_every, int64_t* steps_done) {
+  if (!c) return HDG_EINVAL;
+  if (steps_done) *steps_done = 0;
+  if (stepper != HDG_STEPPER_LSERK4 && stepper != HDG_STEPPER_MRAB3) return fail(c, HDG_EINVAL, "unknown stepper");
+  if (!std::isfinite(t_final) || t_final < c->time) return fail(c, HDG_EINVAL, "t_final must be finite and >= t");
+  if (check_every < 0) return fail(c, HDG_EINVAL, "check_every must be >= 0");
+  const double span = t_final - c->time;
+  int64_t n = 0, done = 0;
+  int rc;
+  if (stepper == HDG_STEPPER_LSERK4) {
+    if (!(cfl > 0.0)) return fail(c, HDG_EINVAL, "CFL constant must be positive");
+    double dtmin = 0.0;
+    if ((rc = hdg_dt(c, cfl, nullptr, &dtmin))) return rc;
+    if (span > 0.0) n = std::max<int64_t>(1, (int64_t)std::ceil(span / dtmin * (1.0 - 1e-12)));
+    const double dt = n > 0 ? span / (double)n : 0.0;
+    const double t0 = c->time;
+    while (done < n) {
+      const int64_t m = check_every > 0 ? std::min(check_every, n - done) : n - done;
+      if ((rc = hdg_step(c, dt, m))) return rc;
+      done += m;
+      if (steps_done) *steps_done = done;
+      bool fin = true;
+      if ((rc = check_finite_impl(c, &fin))) return rc;
+      if (!fin)
+        return fail(c, HDG_ENONFINITE, "non-finite state after LSERK4 step " + std::to_string(done));
+    }
+    c->time = n > 0 ? t_final : t0;
+    return HDG_OK;
+  }
+  if (c->L < 1) return fail(c, HDG_ESTATE, "hdg_mrab_setup has not been called");
+  const int nsub = 1 << (c->L - 1);
+  if (span > 0.0) {
+    n = std::max<int64_t>(1, (int64_t)std::ceil(span / (nsub * c->mr_dtmin0) * (1.0 - 1e-12)));
+    double dtmin = span / ((double)n * nsub);
+    if (!c->mr_ready || std::fabs(dtmin - c->mr_dtmin) > 1e-13 * c->mr_dtmin) {
+      // the history in flight belongs to another step: restart it
+      if (n < 2) {
+        n = 2;
+        dtmin = span / ((double)n * nsub);
+      }
+      c->mr_dtmin = dtmin;
+      c->mr_ready = false;
+    }
+  }
+  const double t0 = c->time;
+  while (done < n) {
+    int64_t m = check_every > 0 ? std::min(check_every, n - done) : n - done;
+    int64_t run = m;
+    if (!c->mr_ready) {
+      m = std::max<int64_t>(m, 2);  // the start-up takes two coarse steps
+      run = m - 2;
+    }
+    if ((rc = mrab_run(c, run, nullptr))) return rc;
+    done += m;
+    if (steps_done) *steps_done = done;
+    bool fin = true;
+    if ((rc = check_finite_impl(c, &fin))) return rc;
+    if (!fin) return fail(c, HDG_ENONFINITE, "non-finite state after coarse step " + std::to_string(done));
+  }
+  c->time = n > 0 ? t_final : t0;
+  return HDG_OK;
+}
+
+// ---- checkpoint / resume ---------------------------------------------------
+namespace {
+
+struct CkptHeader {
+  char magic[8];
+  int32_t N, L, mr_ready, pad;
+  int64_t K[4];
+  int32_t Np[4];
+  int32_t hmod[10];
+  double time, mr_dtmin, mr_dtmin0;
+  int64_t level_count[10];
+  uint64_t level_hash;
+};
+
+uint64_t level_hash(const std::vector<int8_t>& lev) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a
+  for (int8_t v : lev) {
+    h ^= (uint8_t)v;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+int64_t ckpt_bytes(const hdg_ctx* c, bool with_hist) {
+  int64_t b = sizeof(CkptHeader);
+  for (int t = 0; t < 4; ++t) {
+    const TypeData& d = c->td[t];
+    if (!d.present) continue;
+    b += (int64_t)4 * d.K * d.Np * (int64_t)sizeof(float);
+    if (with_hist) b += (int64_t)12 * d.K * d.Np * (int64_t)sizeof(float);
+  }
+  return b;
+}
+
+}  // namespace
+
+int hdg_checkpoint_size(const hdg_ctx* c, int64_t* bytes) {
+  if (!c || !bytes) return HDG_EINVAL;
+  *bytes = ckpt_bytes(c, c->L >= 1 && c->mr_ready);
+  return HDG_OK;
+}
+
+int hdg_checkpoint_save(hdg_ctx* c, void* buf, int64_t bytes) {
+  if (!c) return HDG_EINVAL;
+  if (!buf) return fail(c, HDG_EINVAL, "checkpoint buffer is NULL");
+  const bool hist = c->L >= 1 && c->mr_ready;
+  if (bytes < ckpt_bytes(c, hist)) return fail(c, HDG_EINVAL, "checkpoint buffer too small");
+  CkptHeader h{};
+  std::memcpy(h.magic, "HDGCKPT1", 8);
+  h.N = c->N;
+  h.L = c->L;
+  h.mr_ready = hist ? 1 : 0;
+  for (int t = 0; t < 4; ++t) {
+    h.K[t] = c->td[t].K;
+    h.Np[t] = c->td[t].present ? c->td[t].Np : 0;
+  }
+  for (int l = 0; l < 10; ++l) h.hmod[l] = (int32_t)(c->hcount[l] % 3);
+  h.time = c->time;
+  h.mr_dtmin = c->mr_dtmin;
+  h.mr_dtmin0 = c->mr_dtmin0;
+  for (int8_t v : c->level_h) h.level_count[v]++;
+  h.level_hash = level_hash(c->level_h);
+  char* p = static_cast<char*>(buf);
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  for (int t = 0; t < 4; ++t) {
+    const TypeData& d = c->td[t];
+    if (!d.present) continue;
+    const size_t n = (size_t)4 * d.K * d.Np * sizeof(float);
+    HIPCHK(c, hipMemcpyAsync(p, d.U, n, hipMemcpyDeviceToHost, c->stream));
+    p += n;
+    if (hist) {
+      HIPCHK(c, hipMemcpyAsync(p, d.H, 3 * n, hipMemcpyDeviceToHost, c->stream));
+      p += 3 * n;
+    }
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return HDG_OK;
+}
+
+int hdg_checkpoint_load(hdg_ctx* c, const void* buf, int64_t bytes) {
+  if (!c) return HDG_EINVAL;
+  if (!buf || bytes < (int64_t)sizeof(CkptHeader)) return fail(c, HDG_EINVAL, "checkpoint buffer too small");
+  CkptHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (std::memcmp(h.magic, "HDGCKPT1", 8) != 0) return fail(c, HDG_EINVAL, "not a checkpoint of this library");
+  if (h.N != c->N) return fail(c, HDG_EINVAL, "checkpoint of another order");
+  for (int t = 0; t < 4; ++t)
+    if (h.K[t] != c->td[t].K) return fail(c, HDG_EINVAL, "checkpoint of another mesh");
+  const bool hist = h.mr_ready != 0;
+  if (hist) {
+    if (h.L != c->L) return fail(c, HDG_EINVAL, "checkpoint of another multi-rate set-up (levels)");
+    int64_t cnt[10] = {};
+    for (int8_t v : c->level_h) cnt[v]++;
+    for (int l = 0; l < 10; ++l)
+      if (cnt[l] != h.level_count[l]) return fail(c, HDG_EINVAL, "checkpoint of another multi-rate set-up");
+    if (h.level_hash != level_hash(c->level_h))
+      return fail(c, HDG_EINVAL, "checkpoint of another multi-rate set-up (levels differ)");
+  }
+  if (bytes < ckpt_bytes(c, hist)) return fail(c, HDG_EINVAL, "checkpoint buffer too small");
+  const char* p = static_cast<const char*>(buf) + sizeof(h);
+  for (int t = 0; t < 4; ++t) {
+    TypeData& d = c->td[t];
+    if (!d.present) continue;
+    const size_t n = (size_t)4 * d.K * d.Np * sizeof(float);
+    HIPCHK(c, hipMemcpyAsync(d.U, p, n, hipMemcpyHostToDevice, c->stream));
+    p += n;
+    if (hist) {
+      HIPCHK(c, hipMemcpyAsync(d.H, p, 3 * n, hipMemcpyHostToDevice, c->stream));
+      p += 3 * n;
+    }
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->time = h.time;
+  c->traces_valid = false;
+  c->mr_ready = hist;
+  if (hist) {
+    for (int l = 0; l < 10; ++l) c->hcount[l] = h.hmod[l];
+    c->mr_dtmin = h.mr_dtmin;
+    c->mr_dtmin0 = h.mr_dtmin0;
+  }
   return HDG_OK;
 }
 

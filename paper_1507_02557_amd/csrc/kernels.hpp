@@ -45,6 +45,7 @@ void launch_project(int type, int64_t K, int nv, const double* V, const double* 
                     const double* f2, const double* f3, double* tmp, float* U, hipStream_t s);
 int launch_energy(const EnergyArgs& a, hipStream_t s);
 void launch_finite(int64_t n, const float* x, int* flag, hipStream_t s);
+void launch_fill_int(int* p, int n, int v, hipStream_t s);
 
 // Fused stage kernel for one element type; returns 0 or -1 if (type, N) has
 // no instantiation.

@@ -211,6 +211,11 @@ __global__ void energy_kernel(EnergyArgs a) {
   if (threadIdx.x == 0) a.partial[blockIdx.x] = red[0];
 }
 
+__global__ void fill_int_kernel(int* p, int n, int v) {
+  const int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it < n) p[it] = v;
+}
+
 // Finite check of a float array: flag[0] = 1 if any entry is NaN or Inf.
 __global__ void finite_kernel(int64_t n, const float* x, int* flag) {
   const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -252,6 +257,11 @@ int launch_energy(const EnergyArgs& a, hipStream_t s) {
   const unsigned nb = nblk(a.K, 256);
   hipLaunchKernelGGL(energy_kernel, dim3(nb), dim3(256), 0, s, a);
   return (int)nb;
+}
+
+void launch_fill_int(int* p, int n, int v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_int_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, p, n, v);
 }
 
 void launch_finite(int64_t n, const float* x, int* flag, hipStream_t s) {

@@ -17,6 +17,8 @@ HEX, WEDGE, PYR, TET = 0, 1, 2, 3
 BC_FREE_SURFACE, BC_RIGID_WALL = 0, 1
 PREC_FP32, PREC_FP16X2, PREC_FP16X2_K16 = 0, 1, 2
 PATH_AUTO, PATH_GENERIC = 0, 1
+STEPPER_LSERK4, STEPPER_MRAB3 = 0, 1
+OK, EINVAL, EMESH, ENOMEM, EHIP, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhdg.so")
@@ -37,6 +39,14 @@ _SIGS = [
     ("hdg_rhs", ctypes.c_int, [_P]),
     ("hdg_step", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int64]),
     ("hdg_energy", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    ("hdg_get_time", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    ("hdg_set_time", ctypes.c_int, [_P, ctypes.c_double]),
+    ("hdg_check_finite", ctypes.c_int, [_P]),
+    ("hdg_advance", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int64,
+                                   ctypes.POINTER(ctypes.c_int64)]),
+    ("hdg_checkpoint_size", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    ("hdg_checkpoint_save", ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    ("hdg_checkpoint_load", ctypes.c_int, [_P, _P, ctypes.c_int64]),
     ("hdg_mrab_setup", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _P, _P]),
     ("hdg_mrab_advance", ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     ("hdg_profile", ctypes.c_int, [_P, ctypes.c_int]),
@@ -53,7 +63,9 @@ class HdgMesh(ctypes.Structure):
 
 
 class HdgError(RuntimeError):
-    pass
+    def __init__(self, msg: str, code: int = 0):
+        super().__init__(msg)
+        self.code = code
 
 
 _LIBS: dict = {}
@@ -123,7 +135,7 @@ class Solver:
 
     def _check(self, rc: int):
         if rc != 0:
-            raise HdgError(f"hdg call failed ({rc}): {self._lib.hdg_last_error(self._h).decode()}")
+            raise HdgError(f"hdg call failed ({rc}): {self._lib.hdg_last_error(self._h).decode()}", rc)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -181,6 +193,41 @@ class Solver:
         E = ctypes.c_double()
         self._check(self._lib.hdg_energy(self._h, ctypes.byref(E)))
         return E.value
+
+    @property
+    def time(self) -> float:
+        t = ctypes.c_double()
+        self._check(self._lib.hdg_get_time(self._h, ctypes.byref(t)))
+        return t.value
+
+    @time.setter
+    def time(self, t: float):
+        self._check(self._lib.hdg_set_time(self._h, float(t)))
+
+    def check_finite(self):
+        self._check(self._lib.hdg_check_finite(self._h))
+
+    def advance(self, t_final: float, stepper: int = STEPPER_LSERK4, cfl: float = 0.5,
+                check_every: int = 0) -> int:
+        """Advance to t_final (step shortened to divide the interval); returns the steps taken."""
+        n = ctypes.c_int64()
+        rc = self._lib.hdg_advance(self._h, float(t_final), int(stepper), float(cfl), int(check_every),
+                                   ctypes.byref(n))
+        self.steps_done = n.value
+        self._check(rc)
+        return n.value
+
+    def checkpoint(self) -> np.ndarray:
+        """Checkpoint (time, state, multi-rate history) as a host byte array."""
+        b = ctypes.c_int64()
+        self._check(self._lib.hdg_checkpoint_size(self._h, ctypes.byref(b)))
+        buf = np.empty(b.value, dtype=np.uint8)
+        self._check(self._lib.hdg_checkpoint_save(self._h, buf.ctypes.data, b.value))
+        return buf
+
+    def restore(self, buf: np.ndarray):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self._lib.hdg_checkpoint_load(self._h, buf.ctypes.data, buf.size))
 
     def mrab_setup(self, n_levels: int, cfl: float = 0.5):
         """Multi-rate levels; returns (dt_min, elements per level, level per element)."""

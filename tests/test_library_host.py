@@ -95,3 +95,18 @@ def test_binding_fails_loudly_without_a_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(hdg.HdgError):
         hdg.Solver(_tets([[0, 1, 2, 3]], XYZ), 2)
+
+
+def test_calls_on_a_null_context_are_rejected():
+    lib = hdg.load_library()
+    t = ctypes.c_double()
+    n = ctypes.c_int64()
+    buf = (ctypes.c_uint8 * 64)()
+    assert lib.hdg_get_time(None, ctypes.byref(t)) == hdg.EINVAL
+    assert lib.hdg_set_time(None, 1.0) == hdg.EINVAL
+    assert lib.hdg_check_finite(None) == hdg.EINVAL
+    assert lib.hdg_advance(None, 1.0, hdg.STEPPER_LSERK4, 0.5, 0, ctypes.byref(n)) == hdg.EINVAL
+    assert lib.hdg_checkpoint_size(None, ctypes.byref(n)) == hdg.EINVAL
+    assert lib.hdg_checkpoint_save(None, buf, 64) == hdg.EINVAL
+    assert lib.hdg_checkpoint_load(None, buf, 64) == hdg.EINVAL
+    assert lib.hdg_project(None, 0, None, None, None, None) == hdg.EINVAL
