@@ -154,6 +154,21 @@ int hdg_get_points(hdg_ctx* ctx, int t, double* xyz_dev);
 int hdg_project(hdg_ctx* ctx, int t, const double* p, const double* ux, const double* uy,
                 const double* uz);
 
+/* hdg_project without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, result and errors as hdg_project, with
+ * the work buffer taken from a fixed device array of the library
+ * (HDG_PROJECT_SCRATCH_BYTES per GPU, held until the process ends): elements
+ * are projected in chunks of at most HDG_PROJECT_SCRATCH_BYTES /
+ * (32 n_sample) at a time, in stream order.  Nothing is allocated or freed
+ * and the stream is not synchronised.  Every call on one GPU shares that
+ * array: calls that overlap in time on one GPU (different streams or
+ * threads) race and must be serialised by the caller.  Errors: HDG_EINVAL
+ * (also when one element's 4 n_sample doubles exceed the array), HDG_EHIP. */
+#define HDG_PROJECT_SCRATCH_BYTES (16 * 1024 * 1024)
+int hdg_project_noalloc(hdg_ctx* ctx, int t, const double* p, const double* ux, const double* uy,
+                        const double* uz);
+
 /* Copy the state (which = 0) or the last right-hand side / LSERK residual
  * (which = 1) of type t into / out of caller device buffers, each float
  * [K_t][Np] (the dofs of the type's basis, Section 2.1; meaning per type in

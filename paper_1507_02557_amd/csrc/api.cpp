@@ -107,6 +107,7 @@ struct hdg_ctx {
   double time = 0.0;           // simulated time of the state
   double mr_dtmin0 = 0.0;      // dtau_min of hdg_mrab_setup (hdg_advance may scale it down)
   std::vector<int8_t> level_h; // multi-rate level per element (mesh order)
+  double* pscratch = nullptr;  // fixed work buffer of hdg_project_noalloc on this context's GPU
 };
 
 namespace {
@@ -618,6 +619,7 @@ int create_impl(hdg_ctx* c, const hdg_mesh* m, int N) {
     HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     if (ncu > 0) c->max_blocks = ncu;
   }
+  if (project_scratch(&c->pscratch)) return fail(c, HDG_EHIP, "address of the projection work buffer not found");
   int rc;
   if ((rc = upload(c, &c->nbr, nbr))) return rc;
   if ((rc = upload(c, &c->ori, ori))) return rc;
@@ -869,7 +871,7 @@ int hdg_project(hdg_ctx* c, int t, const double* p, const double* ux, const doub
     if (hipMalloc((void**)&tmp, (size_t)4 * d.K * d.nsample * sizeof(double)) != hipSuccess)
       return fail(c, HDG_ENOMEM, "projection scratch allocation failed");
   }
-  launch_project(t, d.K, d.nv, d.V, d.spts, d.sw, d.nsample, d.Np, d.Phi, d.gpts, p, ux, uy, uz, tmp, d.U,
+  launch_project(t, d.K, d.nv, d.V, d.spts, d.sw, d.nsample, d.Np, d.Phi, d.gpts, p, ux, uy, uz, tmp, d.K, d.U,
                  c->stream);
   hipError_t e = hipGetLastError();
   if (tmp) {
@@ -878,6 +880,27 @@ int hdg_project(hdg_ctx* c, int t, const double* p, const double* ux, const doub
     if (e == hipSuccess) e = es;
   }
   if (e != hipSuccess) return fail(c, HDG_EHIP, std::string("projection: ") + hipGetErrorString(e));
+  c->traces_valid = false;
+  c->mr_ready = false;
+  return HDG_OK;
+}
+
+int hdg_project_noalloc(hdg_ctx* c, int t, const double* p, const double* ux, const double* uy,
+                        const double* uz) {
+  if (!c) return HDG_EINVAL;
+  if (check_type(c, t) || !p || !ux || !uy || !uz) return fail(c, HDG_EINVAL, "bad type or NULL input");
+  TypeData& d = c->td[t];
+  int64_t chunk = d.K;
+  if (t == kWedge || t == kPyr) {
+    const int64_t per_elem = (int64_t)4 * d.nsample * (int64_t)sizeof(double);
+    if (per_elem > kProjectScratchBytes)
+      return fail(c, HDG_EINVAL, "one element's samples exceed the fixed projection work buffer");
+    if (!c->pscratch) return fail(c, HDG_EHIP, "projection work buffer unavailable");
+    chunk = kProjectScratchBytes / per_elem;
+  }
+  launch_project(t, d.K, d.nv, d.V, d.spts, d.sw, d.nsample, d.Np, d.Phi, d.gpts, p, ux, uy, uz, c->pscratch,
+                 chunk, d.U, c->stream);
+  HIPCHK(c, hipGetLastError());
   c->traces_valid = false;
   c->mr_ready = false;
   return HDG_OK;

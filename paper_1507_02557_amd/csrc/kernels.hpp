@@ -40,12 +40,21 @@ struct EnergyArgs {
 void launch_geometry(const GeoArgs& g, hipStream_t s);
 void launch_points(int type, int64_t K, int nv, const double* V, const double* pts, int npts, double* out,
                    hipStream_t s);
+// Projection of sampled initial data (wedge, pyramid: in chunks of at most
+// `chunk` elements through the work buffer tmp of 4 chunk npts doubles;
+// chunk < 1: all K at once).
 void launch_project(int type, int64_t K, int nv, const double* V, const double* pts, const double* w, int npts,
                     int Np, const double* Phi, const double* geo_pts, const double* f0, const double* f1,
-                    const double* f2, const double* f3, double* tmp, float* U, hipStream_t s);
+                    const double* f2, const double* f3, double* tmp, int64_t chunk, float* U, hipStream_t s);
+// Fixed device work buffer of the allocation-free projection (bytes per GPU).
+constexpr int64_t kProjectScratchBytes = 16 * 1024 * 1024;
+constexpr int kMaxDevices = 64;
+// Device address of that buffer on the current device (looked up once per
+// device with hipGetSymbolAddress); 0 on success, -1 on a HIP error.
+int project_scratch(double** ptr);
+void launch_fill_int(int* p, int n, int v, hipStream_t s);
 int launch_energy(const EnergyArgs& a, hipStream_t s);
 void launch_finite(int64_t n, const float* x, int* flag, hipStream_t s);
-void launch_fill_int(int* p, int n, int v, hipStream_t s);
 
 // Fused stage kernel for one element type; returns 0 or -1 if (type, N) has
 // no instantiation.

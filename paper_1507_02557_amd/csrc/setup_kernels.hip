@@ -2,6 +2,8 @@
 // surface Jacobians, sample points and projection of initial data, energy.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "geom.hpp"
 #include "kernels.hpp"
 
@@ -113,14 +115,15 @@ __global__ void points_kernel(int type, int64_t K, int nv, const double* Vall, c
   for (int d = 0; d < 3; ++d) out[it * 3 + d] = x[d];
 }
 
-// Projection step 1: tmp[c][e][q] = w_q * jw(J_q) * f_c(e, q), with
-// jw = sqrt(J) (LSC wedge) or J (pyramid).
-__global__ void project_weight_kernel(int type, int64_t K, int nv, const double* Vall, const double* pts,
-                                      const double* w, int npts, const double* f0, const double* f1,
-                                      const double* f2, const double* f3, double* tmp) {
+// Projection step 1, elements e0 .. e0+Kc-1:
+// tmp[c][e-e0][q] = w_q * jw(J_q) * f_c(e, q), with jw = sqrt(J) (LSC wedge)
+// or J (pyramid).
+__global__ void project_weight_kernel(int type, int64_t e0, int64_t Kc, int nv, const double* Vall,
+                                      const double* pts, const double* w, int npts, const double* f0,
+                                      const double* f1, const double* f2, const double* f3, double* tmp) {
   const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (it >= K * npts) return;
-  const int64_t e = it / npts;
+  if (it >= Kc * npts) return;
+  const int64_t e = e0 + it / npts;
   const int q = (int)(it % npts);
   double V[8][3];
   load_verts(Vall, e, nv, V);
@@ -128,21 +131,23 @@ __global__ void project_weight_kernel(int type, int64_t K, int nv, const double*
   vmap(type, V, pts + 3 * q, x, F);
   const double J = det3(F);
   const double s = w[q] * (type == 1 ? sqrt(J) : J);
-  const int64_t n = K * npts;
-  tmp[it] = s * f0[it];
-  tmp[n + it] = s * f1[it];
-  tmp[2 * n + it] = s * f2[it];
-  tmp[3 * n + it] = s * f3[it];
+  const int64_t n = Kc * npts, gi = e0 * npts + it;
+  tmp[it] = s * f0[gi];
+  tmp[n + it] = s * f1[gi];
+  tmp[2 * n + it] = s * f2[gi];
+  tmp[3 * n + it] = s * f3[gi];
 }
 
-// Projection step 2: U[c][e][i] = sum_q Phi[q][i] tmp[c][e][q] / m_i, with
-// m_i = J(a_i, b_j) for the pyramid and 1 for the wedge.
-__global__ void project_apply_kernel(int type, int64_t K, int nv, const double* Vall, const double* Phi, int npts,
-                                     int Np, const double* geo_pts, const double* tmp, float* U) {
-  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (it >= K * Np) return;
-  const int64_t e = it / Np;
-  const int i = (int)(it % Np);
+// Projection step 2, elements e0 .. e0+Kc-1 of K:
+// U[c][e][i] = sum_q Phi[q][i] tmp[c][e-e0][q] / m_i, with m_i = J(a_i, b_j)
+// for the pyramid and 1 for the wedge.
+__global__ void project_apply_kernel(int type, int64_t e0, int64_t Kc, int64_t K, int nv, const double* Vall,
+                                     const double* Phi, int npts, int Np, const double* geo_pts,
+                                     const double* tmp, float* U) {
+  const int64_t lt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (lt >= Kc * Np) return;
+  const int64_t el = lt / Np, e = e0 + el, it = e * Np + lt % Np;
+  const int i = (int)(lt % Np);
   double m = 1.0;
   if (type == 2) {
     double V[8][3];
@@ -151,10 +156,10 @@ __global__ void project_apply_kernel(int type, int64_t K, int nv, const double* 
     vmap(type, V, geo_pts + 3 * i, x, F);
     m = det3(F);
   }
-  const int64_t n = K * npts;
+  const int64_t n = Kc * npts;
   for (int c = 0; c < 4; ++c) {
     double s = 0.0;
-    for (int q = 0; q < npts; ++q) s += Phi[(int64_t)q * Np + i] * tmp[c * n + e * npts + q];
+    for (int q = 0; q < npts; ++q) s += Phi[(int64_t)q * Np + i] * tmp[c * n + el * npts + q];
     U[(int64_t)c * K * Np + it] = (float)(s / m);
   }
 }
@@ -240,16 +245,48 @@ void launch_points(int type, int64_t K, int nv, const double* V, const double* p
 
 void launch_project(int type, int64_t K, int nv, const double* V, const double* pts, const double* w, int npts,
                     int Np, const double* Phi, const double* geo_pts, const double* f0, const double* f1,
-                    const double* f2, const double* f3, double* tmp, float* U, hipStream_t s) {
+                    const double* f2, const double* f3, double* tmp, int64_t chunk, float* U, hipStream_t s) {
   if (K == 0) return;
   if (type == 0 || type == 3) {
     hipLaunchKernelGGL(copy_samples_kernel, dim3(nblk(K * Np, 256)), dim3(256), 0, s, K * Np, f0, f1, f2, f3, U);
     return;
   }
-  hipLaunchKernelGGL(project_weight_kernel, dim3(nblk(K * npts, 256)), dim3(256), 0, s, type, K, nv, V, pts, w,
-                     npts, f0, f1, f2, f3, tmp);
-  hipLaunchKernelGGL(project_apply_kernel, dim3(nblk(K * Np, 256)), dim3(256), 0, s, type, K, nv, V, Phi, npts, Np,
-                     geo_pts, tmp, U);
+  if (chunk < 1) chunk = K;
+  // chunks run in stream order: each reuses tmp after the previous one has read it
+  for (int64_t e0 = 0; e0 < K; e0 += chunk) {
+    const int64_t Kc = K - e0 < chunk ? K - e0 : chunk;
+    hipLaunchKernelGGL(project_weight_kernel, dim3(nblk(Kc * npts, 256)), dim3(256), 0, s, type, e0, Kc, nv, V,
+                       pts, w, npts, f0, f1, f2, f3, tmp);
+    hipLaunchKernelGGL(project_apply_kernel, dim3(nblk(Kc * Np, 256)), dim3(256), 0, s, type, e0, Kc, K, nv, V,
+                       Phi, npts, Np, geo_pts, tmp, U);
+  }
+}
+
+// Work buffer of hdg_project_noalloc: a fixed device array, one copy per GPU.
+// Host code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address): project_scratch() returns the device
+// address that hipGetSymbolAddress reports for the current device.
+static __device__ __align__(256) double scratch[kProjectScratchBytes / sizeof(double)];
+
+int project_scratch(double** ptr) {
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  *ptr = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return -1;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -1;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *ptr = addr[dev];
+  return 0;
+}
+
+void launch_fill_int(int* p, int n, int v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_int_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, p, n, v);
 }
 
 int launch_energy(const EnergyArgs& a, hipStream_t s) {
@@ -257,11 +294,6 @@ int launch_energy(const EnergyArgs& a, hipStream_t s) {
   const unsigned nb = nblk(a.K, 256);
   hipLaunchKernelGGL(energy_kernel, dim3(nb), dim3(256), 0, s, a);
   return (int)nb;
-}
-
-void launch_fill_int(int* p, int n, int v, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(fill_int_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, p, n, v);
 }
 
 void launch_finite(int64_t n, const float* x, int* flag, hipStream_t s) {

@@ -18,6 +18,7 @@ BC_FREE_SURFACE, BC_RIGID_WALL = 0, 1
 PREC_FP32, PREC_FP16X2, PREC_FP16X2_K16 = 0, 1, 2
 PATH_AUTO, PATH_GENERIC = 0, 1
 STEPPER_LSERK4, STEPPER_MRAB3 = 0, 1
+PROJECT_SCRATCH_BYTES = 16 * 1024 * 1024  # HDG_PROJECT_SCRATCH_BYTES
 OK, EINVAL, EMESH, ENOMEM, EHIP, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -34,6 +35,7 @@ _SIGS = [
     ("hdg_dt", ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double)]),
     ("hdg_get_points", ctypes.c_int, [_P, ctypes.c_int, _P]),
     ("hdg_project", ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
+    ("hdg_project_noalloc", ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
     ("hdg_set_state", ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
     ("hdg_get_field", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P]),
     ("hdg_rhs", ctypes.c_int, [_P]),
@@ -164,6 +166,13 @@ class Solver:
     def project(self, t: int, fields):
         f = [torch.as_tensor(v, dtype=torch.float64, device=self.device).contiguous() for v in fields]
         self._check(self._lib.hdg_project(self._h, t, *[_ptr(v) for v in f]))
+        if self.device.type == "cuda":
+            torch.cuda.current_stream(self.device).synchronize()
+
+    def project_noalloc(self, t: int, fields):
+        """hdg_project through the library's fixed work buffer (no device allocation, no sync)."""
+        f = [torch.as_tensor(v, dtype=torch.float64, device=self.device).contiguous() for v in fields]
+        self._check(self._lib.hdg_project_noalloc(self._h, t, *[_ptr(v) for v in f]))
         if self.device.type == "cuda":
             torch.cuda.current_stream(self.device).synchronize()
 

@@ -109,4 +109,11 @@ def test_calls_on_a_null_context_are_rejected():
     assert lib.hdg_checkpoint_size(None, ctypes.byref(n)) == hdg.EINVAL
     assert lib.hdg_checkpoint_save(None, buf, 64) == hdg.EINVAL
     assert lib.hdg_checkpoint_load(None, buf, 64) == hdg.EINVAL
+    assert lib.hdg_project_noalloc(None, 0, None, None, None, None) == hdg.EINVAL
     assert lib.hdg_project(None, 0, None, None, None, None) == hdg.EINVAL
+
+
+def test_header_scratch_size_matches_binding():
+    src = open(os.path.join(ROOT, "include", "hdg.h")).read()
+    m = re.search(r"#define HDG_PROJECT_SCRATCH_BYTES \((\d+) \* (\d+) \* (\d+)\)", src)
+    assert m and int(m.group(1)) * int(m.group(2)) * int(m.group(3)) == hdg.PROJECT_SCRATCH_BYTES
