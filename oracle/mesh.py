@@ -87,3 +87,51 @@ def canonical_perm(gids):
     if gids[nxt] < gids[prv]:
         return (p, nxt, (p + 2) % 4, prv)
     return (p, prv, (p + 2) % 4, nxt)
+
+
+def nonconforming_faces(types, everts, refs, slot_elem, slot_face, nbr, hanging):
+    """1:4 non-conforming triangular faces.
+
+    ``hanging`` rows (v, a, b): vertex v is the midpoint of the edge (a, b).
+    An unmatched triangular face (v0, v1, v2) whose three edge midpoints are
+    all hanging vertices is a coarse face; its four sub-faces are the
+    triangles of its midpoint subdivision,
+      (v0, m01, m20), (v1, m12, m01), (v2, m20, m12), (m01, m12, m20),
+    each of which must be an unmatched face of exactly one element.
+    Returns a list of (coarse slot, [(fine slot, {vertex id: barycentric
+    coordinates w.r.t. the coarse face's local vertices (v0, v1, v2)})] * 4).
+    """
+    hanging = np.asarray(hanging, dtype=np.int64).reshape(-1, 3)
+    if hanging.shape[0] == 0:
+        return []
+    mid = {(min(a, b), max(a, b)): int(v) for v, a, b in hanging}
+    first = {}
+    free_tri = {}
+    for s in np.nonzero(nbr < 0)[0]:
+        e, f = int(slot_elem[s]), int(slot_face[s])
+        fv = refs[int(types[e])].faces[f]
+        if len(fv) != 3:
+            continue
+        g = tuple(int(everts[e, v]) for v in fv)
+        first[s] = g
+        free_tri[tuple(sorted(g))] = int(s)
+    out = []
+    used = set()
+    for s, g in first.items():
+        v0, v1, v2 = g
+        m01 = mid.get((min(v0, v1), max(v0, v1)))
+        m12 = mid.get((min(v1, v2), max(v1, v2)))
+        m20 = mid.get((min(v2, v0), max(v2, v0)))
+        if m01 is None or m12 is None or m20 is None:
+            continue
+        bary = {v0: np.array([1.0, 0.0, 0.0]), v1: np.array([0.0, 1.0, 0.0]), v2: np.array([0.0, 0.0, 1.0]),
+                m01: np.array([0.5, 0.5, 0.0]), m12: np.array([0.0, 0.5, 0.5]), m20: np.array([0.5, 0.0, 0.5])}
+        subs = []
+        for tri in ((v0, m01, m20), (v1, m12, m01), (v2, m20, m12), (m01, m12, m20)):
+            fs = free_tri.get(tuple(sorted(tri)))
+            if fs is None or fs in used:
+                raise ValueError("a sub-face of a refined triangular face has no element")
+            used.add(fs)
+            subs.append((fs, {v: bary[v] for v in tri}))
+        out.append((int(s), subs))
+    return out

@@ -5,7 +5,8 @@ Binning: element K takes the coarsest level whose step does not exceed its
 stable step dtau_K (the printed inequality reads the other way round; this
 is the reading that keeps every element stable).  A sweep then moves
 elements to finer levels until face neighbours differ by at most one level,
-repeated to a fixed point.
+repeated to a fixed point.  On a 1:4 non-conforming face the four fine
+elements are moved to the finest level among them.
 
 A coarse step (dtau_1) has 2^(L-1) substeps of dtau_min at t_k = t_0 + k dtau_min;
 level l is active at substep k when k is a multiple of 2^(L-l).  At a substep:
@@ -49,14 +50,20 @@ def bin_levels(disc: Disc, L: int, cfl: float = 0.5):
         j = np.floor(np.log2(ratio * (1.0 + 1e-12))).astype(np.int64)
         j = np.clip(j, 0, L - 1)
         lev[disc.els[t]] = L - j
-    # neighbours differ by at most one level: move coarser elements finer
+    # neighbours differ by at most one level: move coarser elements finer;
+    # the four elements on the sub-faces of one non-conforming coarse face
+    # share a level (the finest among them), so the coarse element's view of
+    # its face is of one level
     inner = disc.nbr >= 0
     a = disc.slot_elem[inner]
     b = disc.slot_elem[disc.nbr[inner]]
+    groups = getattr(disc, "nc_groups", [])
     while True:
         need = np.maximum(lev[a], lev[b] - 1)
         new = lev.copy()
         np.maximum.at(new, a, need)
+        for g in groups:
+            new[g] = np.max(new[g])
         if np.array_equal(new, lev):
             break
         lev = new

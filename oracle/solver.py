@@ -24,6 +24,17 @@ All surface integrals use face cubature points placed in the canonical face
 frame (``oracle.mesh``): (N+1)^2 Gauss-Legendre points on quadrilaterals and
 the (N+1)^2 collapsed Gauss-Jacobi rule on triangles.
 
+1:4 non-conforming triangular faces (a coarse face split into the four
+triangles of its midpoint subdivision, each the face of a finer element; the
+paper's meshes are conforming, so this follows the same flux pointwise): on
+every sub-face the coarse element evaluates its trace at the fine face's
+canonical points, the flux is formed there exactly as on a conforming face,
+and the coarse element's integral over its face is the sum of the four
+sub-face integrals.  The coarse element's side of each sub-face is held as
+an extra ("mortar") slot paired with the fine element's slot; the coarse
+face's own slot keeps its geometry (it enters the time step) but carries no
+weight.
+
 State layout: dict type -> array (K_t, 4, Np) with fields (p, ux, uy, uz).
 """
 from __future__ import annotations
@@ -132,6 +143,9 @@ class Disc:
                     glist.append((np.array(idx), Phi))
                 self.groups[(t, f)] = glist
 
+        # ---- 1:4 non-conforming faces: mortar slots ----------------------
+        self._build_mortars(mesh, types, slot_face)
+
         # ---- volume geometry and operators -----------------------------
         self.geo = {}
         for t in self.types:
@@ -169,6 +183,69 @@ class Disc:
                 raise ValueError("non-positive Jacobian")
             self.geo[t] = g
 
+    def _build_mortars(self, mesh, types, slot_face):
+        hang = getattr(mesh, "hanging", None)
+        hang = np.zeros((0, 3), dtype=np.int64) if hang is None else hang
+        nc = OM.nonconforming_faces(types, mesh.everts, self.refs, self.slot_elem, slot_face, self.nbr, hang)
+        ns0 = self.nslot
+        self.is_parent = np.zeros(ns0, dtype=bool)
+        self.nc_groups = []          # elements on the four sub-faces of each coarse face
+        self.mortar = {}             # type -> (mortar slots, element index within type, trace matrices)
+        pairs = [(s, fs, bary) for s, subs in nc for fs, bary in subs]
+        nm = len(pairs)
+        if nm == 0:
+            return
+        ext = lambda a, fill=0.0: np.concatenate([a, np.full((nm,) + a.shape[1:], fill, dtype=a.dtype)])
+        self.slot_elem = ext(self.slot_elem, 0)
+        self.nbr = ext(self.nbr, -1)
+        self.fx, self.Js, self.Js_ref = ext(self.fx), ext(self.Js), ext(self.Js_ref)
+        self.nrm, self.wq, self.fJ = ext(self.nrm), ext(self.wq), ext(self.fJ, 1.0)
+        self.is_parent = ext(self.is_parent, False)
+        eta, _ = self.face_rule[3]
+        S, _ = R.face_shape(3, eta)
+        local = {}
+        for t in self.types:
+            for k, e in enumerate(self.els[t]):
+                local[int(e)] = (t, k)
+        per_type = {}
+        for s, subs in nc:
+            self.is_parent[s] = True
+            self.wq[s] = 0.0
+            self.nc_groups.append(np.array([self.slot_elem[fs] for fs, _ in subs]))
+        for i, (s, fs, bary) in enumerate(pairs):
+            m = ns0 + i
+            e = int(self.slot_elem[s])
+            t, k = local[e]
+            E = self.refs[t]
+            fv = list(E.faces[int(slot_face[s])])
+            fe = int(self.slot_elem[fs])
+            fE = self.refs[int(types[fe])]
+            fg = mesh.everts[fe, list(fE.faces[int(slot_face[fs])])]
+            cv = sorted(int(v) for v in fg)                 # the fine face's canonical vertex order
+            B = np.array([bary[v] for v in cv])            # canonical sub-face vertices in coarse barycentrics
+            Xq = S @ B @ E.vref[fv]                         # coarse reference coordinates of the fine points
+            xm, _, J, _ = OM.vertex_map(E, Xq, self.V[t][k:k + 1])
+            if np.max(np.abs(xm[0] - self.fx[fs])) > 1e-11:
+                raise ValueError("sub-face points of the coarse element and the fine face differ")
+            nrm = self.nrm[s][0]
+            if np.max(np.abs(nrm[None, :] + self.nrm[fs])) > 1e-9:
+                raise ValueError("coarse and fine normals of a sub-face are not opposite")
+            Phi, _ = E.basis(Xq)
+            self.slot_elem[m] = e
+            self.nbr[m], self.nbr[fs] = fs, m
+            self.fx[m] = self.fx[fs]
+            self.Js[m] = self.Js[fs]
+            self.wq[m] = self.wq[fs]
+            self.nrm[m] = nrm[None, :]
+            self.fJ[m] = J[0]
+            per_type.setdefault(t, ([], [], []))
+            per_type[t][0].append(m)
+            per_type[t][1].append(k)
+            per_type[t][2].append(Phi)
+        self.nslot = ns0 + nm
+        for t, (ms, ks, phis) in per_type.items():
+            self.mortar[t] = (np.array(ms), np.array(ks), np.stack(phis))
+
     # ------------------------------------------------------------------
     def zeros(self):
         return {t: np.zeros((self.els[t].size, 4, self.refs[t].Np)) for t in self.types}
@@ -180,8 +257,13 @@ class Disc:
             for f in range(self.refs[t].nfaces):
                 for idx, Phi in self.groups[(t, f)]:
                     TR[self.slot[t][idx, f]] = np.einsum("qj,kcj->kqc", Phi, U[t][idx])
+            if t in self.mortar:
+                ms, ks, phis = self.mortar[t]
+                TR[ms] = np.einsum("mqj,mcj->mqc", phis, U[t][ks])
             if t == R.WEDGE:
                 sl = self.slot[t].ravel()
+                if t in self.mortar:
+                    sl = np.concatenate([sl, self.mortar[t][0]])
                 TR[sl] /= np.sqrt(self.fJ[sl])[:, :, None]
         return TR
 
@@ -230,6 +312,13 @@ class Disc:
             flux = np.concatenate([fp[sl][:, :, None], fu[sl]], axis=2) * scale[:, :, None]
             for idx, Phi in self.groups[(t, f)]:
                 S[idx] += np.einsum("qi,kqc->kci", Phi, flux[idx])
+        if t in self.mortar:
+            ms, ks, phis = self.mortar[t]
+            scale = self.wq[ms] * self.Js[ms]
+            if t == R.WEDGE:
+                scale = scale / np.sqrt(self.fJ[ms])
+            flux = np.concatenate([fp[ms][:, :, None], fu[ms]], axis=2) * scale[:, :, None]
+            np.add.at(S, ks, np.einsum("mqi,mqc->mci", phis, flux))
         return S
 
     def rhs(self, U):
@@ -401,11 +490,19 @@ class Disc:
         inner = self.nbr >= 0
         rc_nb[inner] = self.rhoc[self.slot_elem[self.nbr[inner]]]
         avg = 0.5 * (rc_own + rc_nb)
+        # penalty maxima over each element's faces (sub-faces for a coarse
+        # non-conforming face, whose own slot is left out)
+        ne = self.kappa.shape[0]
+        use = ~self.is_parent
+        taup_e = np.zeros(ne)
+        tauu_e = np.zeros(ne)
+        np.maximum.at(taup_e, self.slot_elem[use], 1.0 / avg[use])
+        np.maximum.at(tauu_e, self.slot_elem[use], avg[use])
         for t in self.types:
             sl = self.slot[t]
             e = self.els[t]
-            tau_p = np.max(1.0 / avg[sl], axis=1)
-            tau_u = np.max(avg[sl], axis=1)
+            tau_p = taup_e[e]
+            tau_u = tauu_e[e]
             c_rk = np.maximum(tau_p * self.kappa[e], tau_u / self.rho[e])
             jsr = self.Js_ref[sl]                      # (K, nf, Nfq)
             if t == R.WEDGE:

@@ -30,6 +30,21 @@ meshes, the subdivision of hexahedra into pyramids used in Section 4.1.
 All choices above are conforming: every interior face is shared by exactly
 two elements with the same vertex set.
 
+Refined last slab (``refine_last=2``): the last slab, which must be of kind
+``tet``, is built on a grid of half the spacing (every cube cut into eight,
+each cut into its six Kuhn tetrahedra).  Its face with the previous slab is
+then non-conforming 1:4: every triangle of the coarse side (the
+(min,min)-(max,max) diagonal split of a coarse cube face) is the union of the
+four triangles of its midpoint subdivision on the fine side, because the
+fine Kuhn diagonals run the same way.  The fine grid points on that face
+that are not coarse vertices are *hanging vertices*: each is the midpoint of
+a coarse edge (a square edge or the square's diagonal), placed at the
+midpoint of the two (jittered) coarse vertices and not jittered itself, so
+the four fine triangles lie exactly in the plane of their coarse triangle.
+``Mesh.hanging`` lists them as rows (vertex, parent a, parent b).  The fine
+grid's own interior vertices are jittered by ``jitter * h / 2`` from the same
+generator, drawn after the coarse vertices, in fine-grid id order.
+
 Element-local vertex orders are those of the reference elements:
 
 * hex   (r,s,t) in [-1,1]^3: 0(-1,-1,-1) 1(1,-1,-1) 2(1,1,-1) 3(-1,1,-1)
@@ -76,6 +91,7 @@ class Mesh:
     rho: np.ndarray            # (n_elem,) float64 density
     n: int = 0
     info: dict = field(default_factory=dict)
+    hanging: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), dtype=np.int64))
 
     @property
     def n_elem(self) -> int:
@@ -118,17 +134,26 @@ def _orient(kind: int, v: list, P: np.ndarray) -> list:
 
 
 def four_slab_mesh(n: int, seed: int = 0, jitter: float = 0.1,
-                   slabs=DEFAULT_SLABS, kappa: float = 1.0, rho: float = 1.0) -> Mesh:
+                   slabs=DEFAULT_SLABS, kappa: float = 1.0, rho: float = 1.0, refine_last: int = 1) -> Mesh:
     """Build the four-slab hybrid cube mesh described in the module docstring.
 
     ``slabs`` lists the kind of each x-slab ("hex", "wedge", "pyrtet", "tet",
     "pyr6"); its length sets the number of slabs (a one-element list gives a
-    single-type mesh).
+    single-type mesh).  ``refine_last=2`` builds the last slab (kind "tet", not
+    the first slab) on the half-spacing grid with a 1:4 non-conforming face.
     """
     if n < 1:
         raise ValueError("n must be >= 1")
     slabs = tuple(slabs)
     nslab = len(slabs)
+    if refine_last not in (1, 2):
+        raise ValueError("refine_last must be 1 or 2")
+    if refine_last == 2 and (slabs[-1] != "tet" or nslab < 2):
+        raise ValueError("only a last slab of kind 'tet' after another slab can be refined")
+    # first coarse layer of the refined slab (n: no refined slab)
+    i_ref = int(round((nslab - 1) * n / nslab)) if refine_last == 2 else n
+    if i_ref <= 0 or i_ref >= n + (refine_last == 1):
+        raise ValueError("the refined slab must be non-empty and not the whole mesh")
     h = 1.0 / n
     n1 = n + 1
 
@@ -156,7 +181,7 @@ def four_slab_mesh(n: int, seed: int = 0, jitter: float = 0.1,
 
     for k in range(n):
         for j in range(n):
-            for i in range(n):
+            for i in range(i_ref):
                 kind = kind_of(i)
                 c = [[[gid(i + a, j + b, k + d) for d in (0, 1)] for b in (0, 1)] for a in (0, 1)]
                 # c[a][b][d]: corner at (x_i+a, y_j+b, z_k+d)
@@ -212,6 +237,12 @@ def four_slab_mesh(n: int, seed: int = 0, jitter: float = 0.1,
                     raise ValueError(f"unknown slab kind {kind!r}")
 
     allpts = np.concatenate([pts, np.array(centres, dtype=np.float64).reshape(-1, 3)], axis=0)
+    n_coarse = allpts.shape[0]
+    hanging = np.zeros((0, 3), dtype=np.int64)
+    if refine_last == 2:
+        fine_pts, hanging, fine_elems = _refined_tet_slab(n, i_ref, gid, n_coarse)
+        allpts = np.concatenate([allpts, fine_pts], axis=0)
+        elems.extend(fine_elems)
     n_vert = allpts.shape[0]
     # orientation decisions use the unjittered positions
     fixed = [(t, _orient(t, v, allpts)) for (t, _, v) in elems]
@@ -222,16 +253,72 @@ def four_slab_mesh(n: int, seed: int = 0, jitter: float = 0.1,
         everts[e, : len(v)] = v
 
     rng = np.random.default_rng(seed)
-    disp = rng.uniform(-jitter * h, jitter * h, size=(n_vert, 3))
+    disp = rng.uniform(-jitter * h, jitter * h, size=(n_coarse, 3))
+    if n_vert > n_coarse:
+        disp = np.concatenate([disp, rng.uniform(-jitter * h / 2, jitter * h / 2, size=(n_vert - n_coarse, 3))])
     tol = 1e-12
     on_bnd = np.any((allpts < tol) | (allpts > 1.0 - tol), axis=1)
     disp[on_bnd] = 0.0
+    if hanging.shape[0]:
+        disp[hanging[:, 0]] = 0.0
     xyz = allpts + disp
+    if hanging.shape[0]:
+        # hanging vertices: midpoints of their (jittered) coarse edges
+        xyz[hanging[:, 0]] = 0.5 * (xyz[hanging[:, 1]] + xyz[hanging[:, 2]])
 
     ne = etype.shape[0]
     return Mesh(xyz=xyz, etype=etype, everts=everts,
                 kappa=np.full(ne, float(kappa)), rho=np.full(ne, float(rho)), n=n,
-                info={"seed": seed, "jitter": jitter, "slabs": list(slabs)})
+                info={"seed": seed, "jitter": jitter, "slabs": list(slabs), "refine_last": refine_last},
+                hanging=hanging)
+
+
+def _refined_tet_slab(n: int, i0: int, gid, id0: int):
+    """Kuhn tetrahedra of the half-spacing grid over the coarse layers i0..n-1.
+
+    Fine grid point (a, b, c), a in 0..2(n-i0), b, c in 0..2n, sits at
+    ((i0 + a/2) h, b h/2, c h/2).  On the face a = 0, points with b and c even
+    are the coarse vertices gid(i0, b/2, c/2); the others are hanging vertices
+    (midpoints of a coarse square edge, or of its (min,min)-(max,max)
+    diagonal when b and c are both odd).  Every other fine point is a new
+    vertex, numbered from id0 in order a fastest, then b, then c.
+    Returns (points, hanging rows (vertex, parent a, parent b), elements).
+    """
+    h = 1.0 / n
+    na, nb = 2 * (n - i0), 2 * n
+    ids = -np.ones((na + 1, nb + 1, nb + 1), dtype=np.int64)
+    pts, hang = [], []
+    nxt = id0
+    for c in range(nb + 1):
+        for b in range(nb + 1):
+            for a in range(na + 1):
+                if a == 0 and b % 2 == 0 and c % 2 == 0:
+                    ids[a, b, c] = gid(i0, b // 2, c // 2)
+                    continue
+                ids[a, b, c] = nxt
+                pts.append(((i0 + a / 2.0) * h, b * h / 2.0, c * h / 2.0))
+                if a == 0:
+                    if b % 2 and c % 2:
+                        pa, pb = gid(i0, (b - 1) // 2, (c - 1) // 2), gid(i0, (b + 1) // 2, (c + 1) // 2)
+                    elif b % 2:
+                        pa, pb = gid(i0, (b - 1) // 2, c // 2), gid(i0, (b + 1) // 2, c // 2)
+                    else:
+                        pa, pb = gid(i0, b // 2, (c - 1) // 2), gid(i0, b // 2, (c + 1) // 2)
+                    hang.append((nxt, pa, pb))
+                nxt += 1
+    elems = []
+    perms = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+    for c in range(nb):
+        for b in range(nb):
+            for a in range(na):
+                for perm in perms:
+                    p = [a, b, c]
+                    v = [int(ids[a, b, c])]
+                    for ax in perm:
+                        p[ax] += 1
+                        v.append(int(ids[p[0], p[1], p[2]]))
+                    elems.append((TET, None, v))
+    return (np.array(pts, dtype=np.float64).reshape(-1, 3), np.array(hang, dtype=np.int64).reshape(-1, 3), elems)
 
 
 # ---------------------------------------------------------------------------
