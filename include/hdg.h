@@ -90,7 +90,19 @@ typedef struct hdg_ctx hdg_ctx;
  *     pyramid: (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1) apex (-1,-1,1)
  *     tet:     (-1,-1,-1) (1,-1,-1) (-1,1,-1) (-1,-1,1)
  *   kappa,rho [n_elem]    bulk modulus and density (> 0)
- *   bc                    boundary condition on every boundary face        */
+ *   bc                    boundary condition on every boundary face
+ *   n_hanging, hanging    [3*n_hanging] rows (v, a, b): vertex v is the
+ *                         midpoint of the edge (a, b) (may be 0 / NULL).
+ * 1:4 non-conforming faces (an extension: the paper's meshes are
+ * conforming, Section 4.2).  A triangular face matched by no other element
+ * whose three edge midpoints are hanging vertices is a coarse face; the four
+ * triangles of its midpoint subdivision, (v0, m01, m20), (v1, m12, m01),
+ * (v2, m20, m12), (m01, m12, m20), must each be the unmatched face of one
+ * element.  On every sub-face the flux of Section 2.2 is applied pointwise
+ * between the fine element's trace and the coarse element's trace there;
+ * the coarse element's face integral is the sum over its sub-faces.  Both
+ * sides must be tetrahedra, and hanging vertices must lie at the midpoints
+ * of their edges (relative tolerance 1e-12), else HDG_EMESH.                */
 typedef struct hdg_mesh {
   int64_t n_vert;
   const double* xyz;
@@ -100,6 +112,8 @@ typedef struct hdg_mesh {
   const double* kappa;
   const double* rho;
   int32_t bc;
+  int64_t n_hanging;
+  const int64_t* hanging;
 } hdg_mesh;
 
 /* Create a solver context for order N (1 <= N <= 5) on mesh m (Section 2).
@@ -127,7 +141,8 @@ int hdg_type_info(const hdg_ctx* ctx, int t, int64_t* n_elem, int32_t* np, int32
 
 /* Local stable time steps (Section 3.4, eq. dtK):
  *   dtau_K = C / (C_rhokappa^K C_T(N) C_J^K),
- * C_rhokappa^K = max(tau_p,K kappa_K, tau_u,K / rho_K) (face maxima),
+ * C_rhokappa^K = max(tau_p,K kappa_K, tau_u,K / rho_K) (maxima over the
+ * element's faces; over the four sub-faces for a non-conforming coarse face),
  * C_J^K = max|J^s| max|1/J| (hex, pyramid, tet) or max|J^s/J| (LSC wedge)
  * over cubature points, C_T(N) the computed trace constants of Appendix B.
  * dt_out (host) receives dtau_K for every element in mesh order [n_elem];
@@ -288,7 +303,9 @@ int hdg_profile_read(hdg_ctx* ctx, double* ms_out, int64_t* count_out);
  * on the matrix cores.  Otherwise, or with HDG_PATH_GENERIC,
  * every face exchanges traces at the canonical cubature points.
  * hdg_set_path: path is HDG_PATH_AUTO or HDG_PATH_GENERIC (else
- * HDG_EINVAL); HDG_ESTATE after hdg_mrab_setup.  Traces are rebuilt from the
+ * HDG_EINVAL); HDG_ESTATE after hdg_mrab_setup; HDG_EINVAL for
+ * HDG_PATH_GENERIC on a mesh with non-conforming faces (their coupling uses
+ * the lattice traces).  Traces are rebuilt from the
  * state on the next step.  hdg_get_path: requested path and whether lattice
  * traces are in use (1) or not (0); either pointer may be NULL. */
 int hdg_set_path(hdg_ctx* ctx, int path);

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -108,6 +109,15 @@ struct hdg_ctx {
   double mr_dtmin0 = 0.0;      // dtau_min of hdg_mrab_setup (hdg_advance may scale it down)
   std::vector<int8_t> level_h; // multi-rate level per element (mesh order)
   double* pscratch = nullptr;  // fixed work buffer of hdg_project_noalloc on this context's GPU
+  // 1:4 non-conforming faces: slots [nslot0, nslot0 + 4 n_nc) are the
+  // virtual slots (the coarse trace at a sub-face, read by the fine
+  // element), then n_nc flux slots (the coarse face's flux)
+  int64_t n_nc = 0;
+  int64_t nslot0 = 0;
+  int* ncrec = nullptr;        // [n_nc][kNcRec]
+  float* ncI = nullptr;        // [nvar][Nfn][Nfn]
+  float* ncP = nullptr;        // [nvar][Nfn][Nfn]
+  std::vector<std::array<int64_t, 4>> nc_fine_elems;  // elements on the sub-faces of each coarse face
 };
 
 namespace {
@@ -460,7 +470,36 @@ int prof_begin(hdg_ctx* c, int t, hipEvent_t* stop) {
   return HDG_OK;
 }
 
+// Virtual-slot traces and coarse-face fluxes of the non-conforming faces for
+// a right-hand-side evaluation that reads trace buffer tr (multi-rate: with
+// the mid-step buffer and the substep's level rule).
+int run_mortar(hdg_ctx* c, float4* tr, float4* tr_half, int ksub, int dense) {
+  if (c->n_nc == 0) return HDG_OK;
+  MortarArgs m{};
+  m.n = c->n_nc;
+  m.rec = c->ncrec;
+  m.vslot0 = c->nslot0;
+  m.nfn = c->ft.Nfn;
+  m.nfq = c->ft.Nfq;
+  m.I = c->ncI;
+  m.P = c->ncP;
+  m.cgeo = c->td[kTet].fgeo;
+  m.cslot0 = c->td[kTet].slot0;
+  m.tau = c->tau;
+  m.tr = tr;
+  m.tr_half = tr_half;
+  m.slevel = c->slevel;
+  m.L = c->L;
+  m.ksub = ksub;
+  m.dense = dense;
+  launch_mortar(m, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return HDG_OK;
+}
+
 int run_stage(hdg_ctx* c, int mode, float ra, float rb, float dt) {
+  int rc0 = run_mortar(c, c->trace[c->cur], nullptr, 0, 0);
+  if (rc0) return rc0;
   for (int t = 0; t < 4; ++t) {
     TypeData& d = c->td[t];
     if (!d.present) continue;
@@ -493,6 +532,189 @@ int run_stage(hdg_ctx* c, int mode, float ra, float rb, float dt) {
   }
   HIPCHK(c, hipGetLastError());
   if (mode == kModeStage) c->cur = 1 - c->cur;
+  return HDG_OK;
+}
+
+// 1:4 non-conforming triangular faces (hdg.h, hdg_mesh): finds the coarse
+// faces among the unmatched triangles, appends four virtual slots and one
+// flux slot per coarse face to the slot arrays, pairs each fine face with its
+// virtual slot, and builds the mortar records and the interpolation /
+// projection tables of every distinct sub-face placement.
+int match_nonconforming(hdg_ctx* c, const hdg_mesh* m, std::vector<int>& nbr, std::vector<int8_t>& ori,
+                        std::vector<int64_t>& slot_elem, std::vector<int>& rec, std::vector<float>& Itab,
+                        std::vector<float>& Ptab) {
+  if (m->n_hanging <= 0) return HDG_OK;
+  if (!m->hanging) return fail(c, HDG_EINVAL, "hanging vertex list is NULL");
+  const int64_t ns0 = (int64_t)nbr.size();
+  std::map<std::pair<int64_t, int64_t>, int64_t> mid;
+  std::map<int64_t, std::pair<int64_t, int64_t>> parents;
+  for (int64_t r = 0; r < m->n_hanging; ++r) {
+    const int64_t v = m->hanging[3 * r], a = m->hanging[3 * r + 1], b = m->hanging[3 * r + 2];
+    if (v < 0 || a < 0 || b < 0 || v >= m->n_vert || a >= m->n_vert || b >= m->n_vert || a == b || v == a || v == b)
+      return fail(c, HDG_EINVAL, "hanging vertex row " + std::to_string(r) + " has a bad vertex id");
+    double scale = 1.0, dev = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      scale = std::max({scale, std::fabs(m->xyz[3 * a + d]), std::fabs(m->xyz[3 * b + d])});
+      dev = std::max(dev, std::fabs(m->xyz[3 * v + d] - 0.5 * (m->xyz[3 * a + d] + m->xyz[3 * b + d])));
+    }
+    if (dev > 1e-12 * scale)
+      return fail(c, HDG_EMESH, "hanging vertex " + std::to_string(v) + " is not the midpoint of its edge");
+    mid[{std::min(a, b), std::max(a, b)}] = v;
+    parents[v] = {a, b};
+  }
+  // unmatched triangular faces by sorted vertex ids
+  struct Tri {
+    int64_t slot, elem;
+    int type;
+    int64_t g[3];
+  };
+  std::vector<Tri> tris;
+  std::map<std::array<int64_t, 3>, size_t> free_tri;
+  for (int t = 0; t < 4; ++t) {
+    const TypeData& d = c->td[t];
+    const ElemDesc& E = elem_desc(t);
+    for (int64_t k = 0; k < d.K; ++k)
+      for (int f = 0; f < E.nf; ++f) {
+        const int64_t sl = d.slot0 + k * E.nf + f;
+        if (nbr[sl] >= 0 || E.fnv[f] != 3) continue;
+        Tri T{sl, d.elems[k], t, {0, 0, 0}};
+        for (int v = 0; v < 3; ++v) T.g[v] = m->verts[8 * d.elems[k] + E.fv[f][v]];
+        std::array<int64_t, 3> key{T.g[0], T.g[1], T.g[2]};
+        std::sort(key.begin(), key.end());
+        free_tri[key] = tris.size();
+        tris.push_back(T);
+      }
+  }
+  auto find_mid = [&](int64_t a, int64_t b) -> int64_t {
+    auto it = mid.find({std::min(a, b), std::max(a, b)});
+    return it == mid.end() ? -1 : it->second;
+  };
+  struct Nc {
+    size_t parent;
+    size_t fine[4];
+  };
+  std::vector<Nc> list;
+  std::vector<char> used(tris.size(), 0);
+  for (size_t i = 0; i < tris.size(); ++i) {
+    const Tri& T = tris[i];
+    const int64_t m01 = find_mid(T.g[0], T.g[1]), m12 = find_mid(T.g[1], T.g[2]), m20 = find_mid(T.g[2], T.g[0]);
+    if (m01 < 0 || m12 < 0 || m20 < 0) continue;
+    const int64_t sub[4][3] = {{T.g[0], m01, m20}, {T.g[1], m12, m01}, {T.g[2], m20, m12}, {m01, m12, m20}};
+    Nc nc{i, {0, 0, 0, 0}};
+    for (int q = 0; q < 4; ++q) {
+      std::array<int64_t, 3> key{sub[q][0], sub[q][1], sub[q][2]};
+      std::sort(key.begin(), key.end());
+      auto it = free_tri.find(key);
+      if (it == free_tri.end() || used[it->second])
+        return fail(c, HDG_EMESH, "a sub-face of a refined triangular face has no element");
+      used[it->second] = 1;
+      nc.fine[q] = it->second;
+    }
+    if (T.type != kTet) return fail(c, HDG_EMESH, "non-conforming faces are supported between tetrahedra only");
+    for (int q = 0; q < 4; ++q)
+      if (tris[nc.fine[q]].type != kTet)
+        return fail(c, HDG_EMESH, "non-conforming faces are supported between tetrahedra only");
+    list.push_back(nc);
+  }
+  if (list.empty()) return HDG_OK;
+  if (!c->lattice_ok) return fail(c, HDG_EMESH, "non-conforming faces need a mesh with lattice traces");
+  const int64_t nnc = (int64_t)list.size();
+  const int64_t ntot = ns0 + 5 * nnc;
+  if (ntot >= ((int64_t)1 << 31) - kNcBase) return fail(c, HDG_EINVAL, "mesh too large (face slots exceed int32)");
+  nbr.resize(ntot, -1 - m->bc);
+  ori.resize(ntot, 0);
+  slot_elem.resize(ntot, 0);
+  // sub-face placements: coarse barycentrics (x2) of the sub-face's canonical vertices
+  std::map<std::array<int, 9>, int> variants;
+  std::vector<std::array<int, 9>> vlist;
+  rec.assign((size_t)nnc * kNcRec, 0);
+  c->nc_fine_elems.clear();
+  for (int64_t i = 0; i < nnc; ++i) {
+    const Tri& P = tris[list[i].parent];
+    int64_t cc[3] = {P.g[0], P.g[1], P.g[2]};
+    std::sort(cc, cc + 3);
+    const int64_t flux = ns0 + 4 * nnc + i;
+    nbr[P.slot] = -(int)(kNcBase + flux);
+    slot_elem[flux] = P.elem;
+    int* r = &rec[(size_t)i * kNcRec];
+    r[0] = (int)P.slot;
+    r[1] = (int)flux;
+    std::array<int64_t, 4> fe{};
+    for (int q = 0; q < 4; ++q) {
+      const Tri& F = tris[list[i].fine[q]];
+      const int64_t vs = ns0 + 4 * i + q;
+      nbr[vs] = (int)F.slot;
+      nbr[F.slot] = (int)vs;
+      slot_elem[vs] = P.elem;
+      fe[q] = F.elem;
+      int64_t ff[3] = {F.g[0], F.g[1], F.g[2]};
+      std::sort(ff, ff + 3);
+      std::array<int, 9> B{};
+      for (int k = 0; k < 3; ++k) {
+        int64_t pa = ff[k], pb = ff[k];
+        auto it = parents.find(ff[k]);
+        if (it != parents.end()) {
+          pa = it->second.first;
+          pb = it->second.second;
+        }
+        for (int j = 0; j < 3; ++j) B[3 * k + j] = (pa == cc[j]) + (pb == cc[j]);
+        if (B[3 * k] + B[3 * k + 1] + B[3 * k + 2] != 2)
+          return fail(c, HDG_EMESH, "a sub-face vertex is neither a vertex nor an edge midpoint of its coarse face");
+      }
+      auto vit = variants.find(B);
+      int var;
+      if (vit == variants.end()) {
+        var = (int)vlist.size();
+        variants[B] = var;
+        vlist.push_back(B);
+      } else {
+        var = vit->second;
+      }
+      r[2 + q] = (int)F.slot;
+      r[6 + q] = var;
+    }
+    c->nc_fine_elems.push_back(fe);
+  }
+  // tables: I_v evaluates the coarse lattice basis at the sub-face lattice
+  // nodes; P_v = M^-1 I_v^T M maps sub-face lattice fluxes to the equivalent
+  // coarse lattice flux (M the lattice mass matrix)
+  const FaceTables& ft = c->ft;
+  const int Nfn = ft.Nfn, N = c->N;
+  const Vec M = tri_lattice_mass(ft);
+  Vec Mi;
+  if (!invert(Nfn, M, Mi)) return fail(c, HDG_EINVAL, "internal: singular face lattice mass matrix");
+  Itab.clear();
+  Ptab.clear();
+  for (const auto& B : vlist) {
+    Vec pts(2 * Nfn);
+    for (int q = 0; q < Nfn; ++q) {
+      const double lam[3] = {ft.lattice_ij[q][2] / (double)N, ft.lattice_ij[q][0] / (double)N,
+                             ft.lattice_ij[q][1] / (double)N};
+      double mu[3] = {0.0, 0.0, 0.0};
+      for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 3; ++j) mu[j] += 0.5 * lam[k] * B[3 * k + j];
+      pts[2 * q] = -1.0 + 2.0 * mu[1];
+      pts[2 * q + 1] = -1.0 + 2.0 * mu[2];
+    }
+    Vec I;
+    tri_lattice_basis(ft, pts, I);
+    Vec T((size_t)Nfn * Nfn, 0.0);  // I^T M
+    for (int a = 0; a < Nfn; ++a)
+      for (int b = 0; b < Nfn; ++b) {
+        double acc = 0.0;
+        for (int q = 0; q < Nfn; ++q) acc += I[q * Nfn + a] * M[q * Nfn + b];
+        T[a * Nfn + b] = acc;
+      }
+    for (double v : I) Itab.push_back((float)v);
+    for (int a = 0; a < Nfn; ++a)
+      for (int b = 0; b < Nfn; ++b) {
+        double acc = 0.0;
+        for (int q = 0; q < Nfn; ++q) acc += Mi[a * Nfn + q] * T[q * Nfn + b];
+        Ptab.push_back((float)acc);
+      }
+  }
+  c->n_nc = nnc;
+  c->nslot0 = ns0;
   return HDG_OK;
 }
 
@@ -597,15 +819,27 @@ int create_impl(hdg_ctx* c, const hdg_mesh* m, int N) {
       if ((ta == kWedge) != (tb == kWedge)) c->lattice_ok = false;
     }
   }
-  // penalties: tau_p = 1 / {rho c}, tau_u = {rho c}; boundary uses own rho c
-  std::vector<float2> tau(ns);
+  // 1:4 non-conforming faces: virtual and flux slots appended
+  std::vector<int> ncrec;
+  std::vector<float> ncI, ncP;
+  int rc = match_nonconforming(c, m, nbr, ori, slot_elem, ncrec, ncI, ncP);
+  if (rc) return rc;
+  c->nslot = (int64_t)nbr.size();
+  const int64_t nsall = c->nslot;
+  // penalties: tau_p = 1 / {rho c}, tau_u = {rho c}; boundary uses own rho c.
+  // An element's maxima run over its faces, and over the sub-faces (virtual
+  // slots) instead of a coarse non-conforming face (whose own slot and flux
+  // slot carry no penalty).
+  std::vector<float2> tau(nsall);
   std::vector<double> taup_max(ne, 0.0), tauu_max(ne, 0.0);
-  for (int64_t s = 0; s < ns; ++s) {
+  for (int64_t s = 0; s < nsall; ++s) {
     const int64_t e = slot_elem[s];
     const double rc = std::sqrt(m->kappa[e] * m->rho[e]);
     const double rn = nbr[s] >= 0 ? std::sqrt(m->kappa[slot_elem[nbr[s]]] * m->rho[slot_elem[nbr[s]]]) : rc;
     const double avg = 0.5 * (rc + rn);
     tau[s] = make_float2((float)(1.0 / avg), (float)avg);
+    const bool aux = nbr[s] <= -kNcBase || (c->n_nc > 0 && s >= c->nslot0 + 4 * c->n_nc);
+    if (aux) continue;
     taup_max[e] = std::max(taup_max[e], 1.0 / avg);
     tauu_max[e] = std::max(tauu_max[e], avg);
   }
@@ -620,10 +854,14 @@ int create_impl(hdg_ctx* c, const hdg_mesh* m, int N) {
     if (ncu > 0) c->max_blocks = ncu;
   }
   if (project_scratch(&c->pscratch)) return fail(c, HDG_EHIP, "address of the projection work buffer not found");
-  int rc;
   if ((rc = upload(c, &c->nbr, nbr))) return rc;
   if ((rc = upload(c, &c->ori, ori))) return rc;
   if ((rc = upload(c, &c->tau, tau))) return rc;
+  if (c->n_nc > 0) {
+    if ((rc = upload(c, &c->ncrec, ncrec))) return rc;
+    if ((rc = upload(c, &c->ncI, ncI))) return rc;
+    if ((rc = upload(c, &c->ncP, ncP))) return rc;
+  }
 
   // ---- geometry tables
   GeoTables G{};
@@ -763,8 +1001,8 @@ int create_impl(hdg_ctx* c, const hdg_mesh* m, int N) {
     HIPCHK(c, hipMemsetAsync(d.U, 0, nstate * sizeof(float), c->stream));
     HIPCHK(c, hipMemsetAsync(d.R, 0, nstate * sizeof(float), c->stream));
   }
-  if ((rc = dalloc(c, &c->trace[0], (size_t)ns * ft.Nfq))) return rc;
-  if ((rc = dalloc(c, &c->trace[1], (size_t)ns * ft.Nfq))) return rc;
+  if ((rc = dalloc(c, &c->trace[0], (size_t)nsall * ft.Nfq))) return rc;
+  if ((rc = dalloc(c, &c->trace[1], (size_t)nsall * ft.Nfq))) return rc;
   if ((rc = dalloc(c, &c->partial, (size_t)(ne / 256 + 8)))) return rc;
   if ((rc = dalloc(c, &c->flag, 1))) return rc;
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1015,6 +1253,8 @@ StageArgs mr_args(hdg_ctx* c, TypeData& d, int lmin, int k, int dense) {
 // Right-hand sides of the active elements into their levels' history.
 int mr_rhs(hdg_ctx* c, int k, int dense) {
   const int lmin = lmin_of(c->L, k);
+  int rc0 = run_mortar(c, c->trace[c->cur], dense ? c->trace[1 - c->cur] : nullptr, k, dense);
+  if (rc0) return rc0;
   for (int t = 0; t < 4; ++t) {
     TypeData& d = c->td[t];
     if (!d.present || d.n_from[lmin] == 0) continue;
@@ -1068,13 +1308,19 @@ int hdg_mrab_setup(hdg_ctx* c, int n_levels, double cfl, double* dt_min_out, int
     j = std::max(0, std::min(L - 1, j));
     lev[e] = L - j;
   }
-  // neighbours differ by at most one level: move coarser elements finer
+  // neighbours differ by at most one level: move coarser elements finer; the
+  // four elements on the sub-faces of a non-conforming coarse face share the
+  // finest level among them (the coarse element then sees one level there)
   for (;;) {
     std::vector<int> nw(lev);
     for (size_t s = 0; s < c->nbr_h.size(); ++s) {
       if (c->nbr_h[s] < 0) continue;
       const int64_t a = c->slot_elem_h[s], b = c->slot_elem_h[c->nbr_h[s]];
       nw[a] = std::max(nw[a], lev[b] - 1);
+    }
+    for (const auto& g : c->nc_fine_elems) {
+      const int mx = std::max({nw[g[0]], nw[g[1]], nw[g[2]], nw[g[3]]});
+      for (int q = 0; q < 4; ++q) nw[g[q]] = mx;
     }
     if (nw == lev) break;
     lev.swap(nw);
@@ -1418,6 +1664,8 @@ int hdg_set_path(hdg_ctx* c, int path) {
   if (!c) return HDG_EINVAL;
   if (path != HDG_PATH_AUTO && path != HDG_PATH_GENERIC) return fail(c, HDG_EINVAL, "unknown path");
   if (c->mr_ready) return fail(c, HDG_ESTATE, "the path cannot change after hdg_mrab_setup");
+  if (path == HDG_PATH_GENERIC && c->n_nc > 0)
+    return fail(c, HDG_EINVAL, "non-conforming faces need the lattice-trace path");
   if (path != c->path) {
     c->path = path;
     c->traces_valid = false;

@@ -37,6 +37,28 @@ struct EnergyArgs {
   double* partial;        // one per block
 };
 
+// 1:4 non-conforming triangular faces between tetrahedra with lattice traces.
+// Record i: coarse (parent) slot, flux slot, the four fine slots, the four
+// sub-face interpolation variants; the virtual slot that the fine element of
+// sub-face s reads as its neighbour is vslot0 + 4 i + s.
+constexpr int kNcRec = 10;
+struct MortarArgs {
+  int64_t n;              // non-conforming coarse faces
+  const int* rec;         // [n][kNcRec]
+  int64_t vslot0;
+  int nfn, nfq;
+  const float* I;         // [nvar][nfn][nfn] coarse lattice -> sub-face lattice (canonical frames)
+  const float* P;         // [nvar][nfn][nfn] sub-face lattice flux -> equivalent coarse lattice flux
+  const float4* cgeo;     // coarse type's face factors [K][4] (n, J^s)
+  int64_t cslot0;         // first slot of the coarse type
+  const float2* tau;      // [nslot]
+  float4* tr;             // traces of the current state (read; virtual and flux slots written)
+  float4* tr_half;        // multi-rate mid-step traces (virtual slots written), or NULL
+  const int8_t* slevel;   // multi-rate level per slot, or NULL
+  int L, ksub, dense;     // multi-rate substep (dense: a coarser fine side may be mid-step)
+};
+void launch_mortar(const MortarArgs& a, hipStream_t s);
+
 void launch_geometry(const GeoArgs& g, hipStream_t s);
 void launch_points(int type, int64_t K, int nv, const double* V, const double* pts, int npts, double* out,
                    hipStream_t s);

@@ -343,6 +343,34 @@ void build_face_tables(int N, FaceTables& ft) {
   }
 }
 
+void tri_lattice_basis(const FaceTables& ft, const Vec& pts, Vec& out) {
+  const int N = ft.N, Nfn = ft.Nfn;
+  std::vector<std::array<int, 2>> pw;
+  for (int a = 0; a <= N; ++a)
+    for (int b = 0; b + a <= N; ++b) pw.push_back({a, b});
+  Vec V((size_t)Nfn * Nfn), Vi;
+  for (int m = 0; m < Nfn; ++m)
+    for (int k = 0; k < Nfn; ++k) V[m * Nfn + k] = mono2(pw[k][0], pw[k][1], ft.lattice[2 * m], ft.lattice[2 * m + 1]);
+  if (!invert(Nfn, V, Vi)) throw std::runtime_error("singular triangle lattice Vandermonde");
+  const size_t np = pts.size() / 2;
+  out.assign(np * Nfn, 0.0);
+  for (size_t q = 0; q < np; ++q)
+    for (int m = 0; m < Nfn; ++m) {
+      double s = 0.0;
+      for (int k = 0; k < Nfn; ++k) s += mono2(pw[k][0], pw[k][1], pts[2 * q], pts[2 * q + 1]) * Vi[k * Nfn + m];
+      out[q * Nfn + m] = s;
+    }
+}
+
+Vec tri_lattice_mass(const FaceTables& ft) {
+  const int Nfn = ft.Nfn, Nfq = ft.Nfq;
+  Vec Mf((size_t)Nfn * Nfn, 0.0);
+  for (int q = 0; q < Nfq; ++q)
+    for (int x = 0; x < Nfn; ++x)
+      for (int y = 0; y < Nfn; ++y) Mf[x * Nfn + y] += ft.Ican[q * Nfn + x] * ft.tri_w[q] * ft.Ican[q * Nfn + y];
+  return Mf;
+}
+
 // ---------------------------------------------------------------------------
 // Hexahedron: GL nodal (Section 2.1.1, Algorithms 1-3)
 // ---------------------------------------------------------------------------

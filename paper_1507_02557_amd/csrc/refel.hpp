@@ -51,6 +51,12 @@ struct FaceTables {
   std::vector<int> tri_perm;   // [6][Nfn] canonical lattice node -> local node
 };
 void build_face_tables(int N, FaceTables& ft);
+// Lagrange basis of the equispaced face lattice at face-frame points
+// pts [np][2] (reference triangle (-1,-1), (1,-1), (-1,1)): out [np][Nfn].
+void tri_lattice_basis(const FaceTables& ft, const Vec& pts, Vec& out);
+// Mass matrix of the lattice Lagrange basis on the reference triangle,
+// Ican^T W Ican (exact: the canonical rule integrates degree 2N): [Nfn][Nfn].
+Vec tri_lattice_mass(const FaceTables& ft);
 
 // Orientation code of an element face from the global ids of its local
 // vertices (in the face's local order): triangles 0..5, quadrilaterals 0..7.

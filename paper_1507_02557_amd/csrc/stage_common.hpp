@@ -67,6 +67,12 @@ struct StageArgs {
 // kModeMrab: multi-rate update (state, traces, mid-step traces) of the items.
 enum { kModeStage = 0, kModeTrace = 1, kModeRhs = 2, kModeRhsHist = 3, kModeMrab = 4 };
 
+// Neighbour code of the coarse face of a 1:4 non-conforming interface:
+// nbr = -(kNcBase + s) says that trace slot s holds the face's flux (already
+// weighted by J^s, face-lattice values in canonical order) instead of a
+// neighbour trace.  Boundary codes -(1 + bc) stay above -kNcBase.
+constexpr int kNcBase = 16;
+
 // Element processed by item i, or -1 past the end of the launch.
 HD inline int64_t item(const StageArgs& a, int64_t i) {
   if (i >= a.n_items) return -1;

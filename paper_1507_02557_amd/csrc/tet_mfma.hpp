@@ -179,16 +179,19 @@ struct TetMfma {
   }
 
   // the neighbour's lattice trace values of face f at the lane's nodes
-  // m = g + 4 j (element n of the tile)
+  // m = g + 4 j (element n of the tile); on the coarse face of a
+  // non-conforming interface, the face's flux from its flux slot
   __device__ static void fetch_nbr(const StageArgs& a, const FaceRec& rec, int64_t e, int n, int g, int f,
                                    float4 (&pv)[JF]) {
     const int src = n + 16 * f;
     const int nb = __shfl(rec.nb, src);
     const float4* nsrc = __shfl(rec.half, src) ? a.tr_half : a.tr_in;
+    const int64_t base = nb >= 0 ? (int64_t)nb * Nfq : (int64_t)(-nb - kNcBase) * Nfq;
+    const bool fetch = nb >= 0 || nb <= -kNcBase;
 #pragma unroll
     for (int j = 0; j < JF; ++j) {
       const int m = g + 4 * j;
-      if (e >= 0 && m < Nfn && nb >= 0) pv[j] = nsrc[(int64_t)nb * Nfq + m];
+      if (e >= 0 && m < Nfn && fetch) pv[j] = nsrc[base + m];
     }
   }
 
@@ -312,9 +315,17 @@ struct TetMfma {
       if (e >= 0) {
         l = sm.tperm[fr.ori][m];
         const int node = sm.fnode[f][l];
-        const float4 own = make_float4(W.X[0][n][node], W.X[1][n][node], W.X[2][n][node], W.X[3][n][node]);
-        const float4 nb = fr.nb >= 0 ? pv[j] : mirror_state(own, -fr.nb - 1, fr.g.x, fr.g.y, fr.g.z);
-        upwind_flux(own, nb, fr.g, fr.tau, false, out);
+        if (fr.nb <= -kNcBase) {
+          // coarse face of a non-conforming interface: the flux itself
+          out[0] = pv[j].x;
+          out[1] = pv[j].y;
+          out[2] = pv[j].z;
+          out[3] = pv[j].w;
+        } else {
+          const float4 own = make_float4(W.X[0][n][node], W.X[1][n][node], W.X[2][n][node], W.X[3][n][node]);
+          const float4 nb = fr.nb >= 0 ? pv[j] : mirror_state(own, -fr.nb - 1, fr.g.x, fr.g.y, fr.g.z);
+          upwind_flux(own, nb, fr.g, fr.tau, false, out);
+        }
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c) W.F[c][n][l] = out[c] * iJ;

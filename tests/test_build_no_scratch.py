@@ -14,7 +14,7 @@ import pytest
 
 from paper_1507_02557_amd import build as B
 
-SOURCES = ["setup_kernels.hip", "stages.hip", "tet_mfma.hip", "pyr_mfma.hip"]
+SOURCES = [s for s in B.SOURCES if s.endswith(".hip")]
 
 
 @pytest.mark.parametrize("src", SOURCES)

@@ -1,0 +1,139 @@
+"""Parity of the HIP library with the FP64 oracle on meshes with a 1:4
+non-conforming face (needs an MI355X).
+
+The last slab of the four-slab mesh is built on the half-spacing grid: every
+coarse triangle on its face with the previous slab is the union of the four
+triangles of its midpoint subdivision (hanging vertices at the coarse-edge
+midpoints).  Both sides are tetrahedra.  The library couples them through
+virtual slots (the coarse trace at each sub-face's lattice nodes) and the
+coarse face's L2-projected flux; the oracle evaluates the coarse trace at the
+fine face's cubature points and sums the sub-face integrals.  Tolerances as
+in the conforming parity tests (FP32 arithmetic against FP64).
+"""
+import numpy as np
+import pytest
+
+from oracle.mrab import MRAB3
+from oracle.solver import BC_FREE_SURFACE, BC_RIGID_WALL, Disc, lserk4_step
+from paper_1507_02557_amd import hdg
+from paper_1507_02557_amd.inputs import four_slab_mesh, standing_mode_rigid
+
+from .parity_util import lib_state_to_oracle, random_state, set_lib_state, type_rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL_RHS = 1e-5
+
+
+@pytest.fixture(scope="module")
+def refined_mesh():
+    return four_slab_mesh(4, seed=0, jitter=0.1, refine_last=2)
+
+
+def _global(disc, per_type):
+    out = np.zeros(sum(disc.els[t].size for t in disc.types))
+    for t in disc.types:
+        out[disc.els[t]] = per_type[t]
+    return out
+
+
+def test_refined_mesh_is_non_conforming(refined_mesh):
+    assert refined_mesh.hanging.shape[0] > 0
+    s = hdg.Solver(refined_mesh, 2)
+    assert s.get_path() == (hdg.PATH_AUTO, 1)
+    with pytest.raises(hdg.HdgError):
+        s.set_path(hdg.PATH_GENERIC)
+
+
+def test_refined_dt_and_levels_match_oracle(refined_mesh):
+    d = Disc(refined_mesh, 3)
+    s = hdg.Solver(refined_mesh, 3)
+    dte, mn = s.dt(0.5)
+    ref = _global(d, d.dt_elements(0.5))
+    assert np.max(np.abs(dte - ref) / ref) < 1e-12
+    mr = MRAB3(d, 3)
+    dtmin, cnt, lev = s.mrab_setup(3)
+    g = np.zeros(refined_mesh.n_elem, dtype=np.int64)
+    for t in d.types:
+        g[d.els[t]] = mr.level[t]
+    assert np.array_equal(g, lev.astype(np.int64))
+    assert abs(dtmin - mr.dtmin) < 1e-12 * dtmin
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5])
+def test_refined_rhs_matches_oracle(refined_mesh, N):
+    d = Disc(refined_mesh, N)
+    s = hdg.Solver(refined_mesh, N)
+    U = random_state(d, seed=10 + N)
+    set_lib_state(s, U)
+    Rl = {t: v.double().cpu().numpy() for t, v in s.rhs().items()}
+    err = type_rel_err(Rl, d.rhs(U))
+    print("refined N", N, "rel err per type", err)
+    assert max(err.values()) < TOL_RHS, err
+
+
+@pytest.mark.parametrize("bc", [BC_FREE_SURFACE, BC_RIGID_WALL])
+def test_refined_rhs_tet_slabs_random_materials(bc):
+    """Two tetrahedral slabs, the second refined, random kappa and rho per
+    element (the sub-face penalties then differ across one coarse face)."""
+    m = four_slab_mesh(4, seed=2, jitter=0.1, slabs=("tet", "tet"), refine_last=2)
+    rng = np.random.default_rng(7)
+    m.kappa = rng.uniform(0.5, 2.0, m.n_elem)
+    m.rho = rng.uniform(0.5, 2.0, m.n_elem)
+    N = 3
+    d = Disc(m, N, bc=bc)
+    s = hdg.Solver(m, N, bc=bc)
+    U = random_state(d, seed=3)
+    set_lib_state(s, U)
+    Rl = {t: v.double().cpu().numpy() for t, v in s.rhs().items()}
+    err = type_rel_err(Rl, d.rhs(U))
+    assert max(err.values()) < TOL_RHS, err
+    dte, _ = s.dt(0.5)
+    ref = _global(d, d.dt_elements(0.5))
+    assert np.max(np.abs(dte - ref) / ref) < 1e-12
+
+
+def test_refined_standing_mode_steps(refined_mesh):
+    N = 3
+    d = Disc(refined_mesh, N)
+    s = hdg.Solver(refined_mesh, N)
+    dt = d.dt_min(0.5)
+    U = d.project(standing_mode_rigid)
+    s.project_function(standing_mode_rigid)
+    for _ in range(30):
+        U = lserk4_step(d, U, dt)
+    s.step(dt, 30)
+    rel = d.rel_l2(lib_state_to_oracle(s), U)
+    print("refined standing mode, 30 LSERK4 steps, rel L2", rel)
+    assert rel < 1e-5
+
+
+def test_refined_mrab_matches_oracle(refined_mesh):
+    """Three multi-rate levels across the non-conforming face: start-up and
+    coarse steps, with mid-step traces through the virtual slots."""
+    N, L = 3, 3
+    d = Disc(refined_mesh, N)
+    mr = MRAB3(d, L)
+    s = hdg.Solver(refined_mesh, N)
+    s.mrab_setup(L)
+    U = mr.startup(d.project(standing_mode_rigid))
+    s.project_function(standing_mode_rigid)
+    s.mrab_advance(0)
+    for _ in range(3):
+        U = mr.coarse_step(U)
+    s.mrab_advance(3)
+    rel = d.rel_l2(lib_state_to_oracle(s), U)
+    print("refined MRAB N", N, "L", L, "rel L2", rel)
+    assert rel < 1e-5
+
+
+@pytest.mark.parametrize("prec", [hdg.PREC_FP16X2, hdg.PREC_FP16X2_K16])
+def test_refined_split_precision_rhs(refined_mesh, prec):
+    N = 4
+    d = Disc(refined_mesh, N)
+    s = hdg.Solver(refined_mesh, N, precision=prec)
+    U = random_state(d, seed=21)
+    set_lib_state(s, U)
+    Rl = {t: v.double().cpu().numpy() for t, v in s.rhs().items()}
+    err = type_rel_err(Rl, d.rhs(U))
+    assert max(err.values()) < TOL_RHS, err

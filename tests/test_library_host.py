@@ -31,15 +31,16 @@ def test_library_exports_every_declared_function():
     assert sorted(hdg.EXPORTS) == declared
 
 
-def _create(mesh, N=2, bc=1, precision=0):
+def _create(mesh, N=2, bc=1, precision=0, hanging=None):
     lib = hdg.load_library()
     xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float64)
     et = np.ascontiguousarray(mesh.etype, dtype=np.int8)
     ev = np.ascontiguousarray(mesh.everts, dtype=np.int64)
     ka = np.ascontiguousarray(mesh.kappa, dtype=np.float64)
     rh = np.ascontiguousarray(mesh.rho, dtype=np.float64)
+    hg = np.ascontiguousarray(np.zeros((0, 3)) if hanging is None else hanging, dtype=np.int64).reshape(-1, 3)
     m = hdg.HdgMesh(xyz.shape[0], xyz.ctypes.data, et.shape[0], et.ctypes.data, ev.ctypes.data,
-                    ka.ctypes.data, rh.ctypes.data, bc)
+                    ka.ctypes.data, rh.ctypes.data, bc, hg.shape[0], hg.ctypes.data if hg.shape[0] else None)
     h = ctypes.c_void_p()
     rc = lib.hdg_create(ctypes.byref(h), ctypes.byref(m), N, precision, None)
     return rc, h, lib.hdg_last_error(None).decode()
@@ -117,3 +118,42 @@ def test_header_scratch_size_matches_binding():
     src = open(os.path.join(ROOT, "include", "hdg.h")).read()
     m = re.search(r"#define HDG_PROJECT_SCRATCH_BYTES \((\d+) \* (\d+) \* (\d+)\)", src)
     assert m and int(m.group(1)) * int(m.group(2)) * int(m.group(3)) == hdg.PROJECT_SCRATCH_BYTES
+
+
+# A coarse tetrahedron below the triangle (0, 1, 2) of z = 0 and four fine
+# tetrahedra above the four triangles of its midpoint subdivision (hanging
+# vertices 3, 4, 5 at the edge midpoints, apex 6).
+NC_XYZ = [[0, 0, 0], [1, 0, 0], [0, 1, 0], [0.5, 0, 0], [0.5, 0.5, 0], [0, 0.5, 0], [0.2, 0.2, 0.5],
+          [0.2, 0.2, -1]]
+NC_TETS = [[0, 1, 2, 7], [0, 3, 5, 6], [1, 4, 3, 6], [2, 5, 4, 6], [3, 4, 5, 6]]
+NC_HANG = [[3, 0, 1], [4, 1, 2], [5, 2, 0]]
+
+
+def test_create_rejects_hanging_vertex_off_its_midpoint():
+    xyz = np.array(NC_XYZ, dtype=np.float64)
+    xyz[4, 0] += 1e-6
+    rc, h, msg = _create(_tets(NC_TETS, xyz), hanging=NC_HANG)
+    assert rc == hdg.EMESH and not h.value and "midpoint" in msg
+
+
+def test_create_rejects_bad_hanging_rows():
+    rc, _, msg = _create(_tets(NC_TETS, NC_XYZ), hanging=[[3, 0, 0]])
+    assert rc == hdg.EINVAL and "hanging" in msg
+    rc, _, msg = _create(_tets(NC_TETS, NC_XYZ), hanging=[[3, 0, 99]])
+    assert rc == hdg.EINVAL and "hanging" in msg
+
+
+def test_create_rejects_a_refined_face_with_a_missing_sub_face():
+    # the middle sub-face (3, 4, 5) has no element
+    rc, _, msg = _create(_tets(NC_TETS[:4], NC_XYZ), hanging=NC_HANG)
+    assert rc == hdg.EMESH and "sub-face" in msg
+
+
+def test_create_accepts_the_refined_face_up_to_the_device():
+    # the non-conforming set-up is host work; without a GPU the call stops at
+    # the first device query, with a HIP error rather than a mesh error
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, _, msg = _create(_tets(NC_TETS, NC_XYZ), hanging=NC_HANG)
+    assert rc == hdg.EHIP, msg
