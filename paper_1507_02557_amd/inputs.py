@@ -133,6 +133,28 @@ def _orient(kind: int, v: list, P: np.ndarray) -> list:
     return v
 
 
+def _orient_all(etype: np.ndarray, everts: np.ndarray, P: np.ndarray) -> None:
+    """_orient applied to every element at once (in place), same tests."""
+    def det(rows, i0, i1, i2, i3):
+        v = everts[rows]
+        p0 = P[v[:, i0]]
+        a, b, c = P[v[:, i1]] - p0, P[v[:, i2]] - p0, P[v[:, i3]] - p0
+        return np.einsum("ij,ij->i", a, np.cross(b, c))
+
+    rows = np.nonzero(etype == TET)[0]
+    flip = rows[det(rows, 0, 1, 2, 3) < 0]
+    everts[flip, 2:4] = everts[flip][:, [3, 2]]
+    rows = np.nonzero(etype == PYR)[0]
+    flip = rows[det(rows, 0, 1, 3, 4) < 0]
+    everts[flip, :5] = everts[flip][:, [0, 3, 2, 1, 4]]
+    rows = np.nonzero(etype == WEDGE)[0]
+    flip = rows[det(rows, 0, 1, 3, 2) < 0]
+    everts[flip, :6] = everts[flip][:, [0, 2, 1, 3, 5, 4]]
+    rows = np.nonzero(etype == HEX)[0]
+    if np.any(det(rows, 0, 1, 3, 4) < 0):
+        raise ValueError("hex construction produced a negative Jacobian")
+
+
 def four_slab_mesh(n: int, seed: int = 0, jitter: float = 0.1,
                    slabs=DEFAULT_SLABS, kappa: float = 1.0, rho: float = 1.0, refine_last: int = 1) -> Mesh:
     """Build the four-slab hybrid cube mesh described in the module docstring.
@@ -244,13 +266,14 @@ def four_slab_mesh(n: int, seed: int = 0, jitter: float = 0.1,
         allpts = np.concatenate([allpts, fine_pts], axis=0)
         elems.extend(fine_elems)
     n_vert = allpts.shape[0]
+    etype = np.array([t for t, _, _ in elems], dtype=np.int8)
+    everts = -np.ones((len(elems), 8), dtype=np.int64)
+    for kind, nv in ((HEX, 8), (WEDGE, 6), (PYR, 5), (TET, 4)):
+        sel = np.nonzero(etype == kind)[0]
+        if sel.size:
+            everts[sel, :nv] = np.array([elems[e][2] for e in sel], dtype=np.int64)
     # orientation decisions use the unjittered positions
-    fixed = [(t, _orient(t, v, allpts)) for (t, _, v) in elems]
-
-    etype = np.array([t for t, _ in fixed], dtype=np.int8)
-    everts = -np.ones((len(fixed), 8), dtype=np.int64)
-    for e, (t, v) in enumerate(fixed):
-        everts[e, : len(v)] = v
+    _orient_all(etype, everts, allpts)
 
     rng = np.random.default_rng(seed)
     disp = rng.uniform(-jitter * h, jitter * h, size=(n_coarse, 3))
