@@ -285,11 +285,13 @@ int hdg_checkpoint_size(const hdg_ctx* ctx, int64_t* bytes);
 int hdg_checkpoint_save(hdg_ctx* ctx, void* host_buf, int64_t bytes);
 int hdg_checkpoint_load(hdg_ctx* ctx, const void* host_buf, int64_t bytes);
 
-/* Kernel timing for benchmarking.  While enabled (on != 0), hdg_step and
- * hdg_rhs bracket every stage-kernel launch with HIP events on the context's
- * stream.  hdg_profile_read synchronises the stream and returns, per element
- * type, the total kernel time in milliseconds (ms_out[4]) and the number of
- * launches (count_out[4]) since the last reset; either may be NULL.
+/* Kernel timing for benchmarking.  While enabled (on != 0), the stepping
+ * calls bracket every kernel launch with HIP events on the context's stream.
+ * hdg_profile_read synchronises the stream and returns the total kernel time
+ * in milliseconds (ms_out[12]) and the number of launches (count_out[12])
+ * since the last reset, indexed kind * 4 + element type with kind 0 the
+ * stage / right-hand-side kernels, 1 the multi-rate update kernels and 2 the
+ * non-conforming interface kernel (under HDG_TET); either may be NULL.
  * Enabling or disabling resets the counters. */
 int hdg_profile(hdg_ctx* ctx, int on);
 int hdg_profile_read(hdg_ctx* ctx, double* ms_out, int64_t* count_out);

@@ -58,6 +58,7 @@ struct TypeData {
   std::vector<double> cJ, minJ, crk;
   // multi-rate
   int* elist = nullptr;        // elements sorted by level, finest first
+  bool elist_identity = false; // the sorted order is the storage order (no indirection needed)
   int8_t* elevel = nullptr;    // level per element
   float* H = nullptr;          // right-hand-side history [3][4][K][Np]
   int64_t n_from[10] = {};     // number of elements with level >= l
@@ -453,6 +454,11 @@ int ensure_traces(hdg_ctx* c) {
   return HDG_OK;
 }
 
+// Profile categories: kind * 4 + type, kind 0 = stage / right-hand-side
+// kernels, 1 = multi-rate update kernels, 2 = non-conforming interface
+// (mortar) kernel, filed under the tetrahedra.
+constexpr int kProfRhs = 0, kProfUpdate = 1, kProfMortar = 2;
+
 int prof_begin(hdg_ctx* c, int t, hipEvent_t* stop) {
   *stop = nullptr;
   if (!c->prof) return HDG_OK;
@@ -492,7 +498,11 @@ int run_mortar(hdg_ctx* c, float4* tr, float4* tr_half, int ksub, int dense) {
   m.L = c->L;
   m.ksub = ksub;
   m.dense = dense;
+  hipEvent_t stop;
+  int rc = prof_begin(c, kProfMortar * 4 + kTet, &stop);
+  if (rc) return rc;
   launch_mortar(m, c->stream);
+  if (stop) HIPCHK(c, hipEventRecord(stop, c->stream));
   HIPCHK(c, hipGetLastError());
   return HDG_OK;
 }
@@ -1215,7 +1225,9 @@ StageArgs mr_args(hdg_ctx* c, TypeData& d, int lmin, int k, int dense) {
   StageArgs a{};
   a.K = d.K;
   a.n_items = d.n_from[lmin];
-  a.elist = d.elist;
+  // when the elements are already stored finest level first, the active set
+  // is a prefix of the storage order and tiles move as contiguous blocks
+  a.elist = d.elist_identity ? nullptr : d.elist;
   a.elevel = d.elevel;
   a.slevel = c->slevel;
   a.H = d.H;
@@ -1282,7 +1294,7 @@ int mr_update(hdg_ctx* c, int k) {
     for (int l = lmin; l <= c->L; ++l)
       for (int j = 0; j < 3; ++j) a.mr.hs[l][j] = (int)((c->hcount[l] - 1 - j + 3 * 1000) % 3);
     hipEvent_t stop;
-    int rc = prof_begin(c, t, &stop);
+    int rc = prof_begin(c, kProfUpdate * 4 + t, &stop);
     if (rc) return rc;
     if ((rc = launch_type(c, t, a, true))) return rc;
     if (stop) HIPCHK(c, hipEventRecord(stop, c->stream));
@@ -1353,6 +1365,8 @@ int hdg_mrab_setup(hdg_ctx* c, int n_levels, double cfl, double* dt_min_out, int
     if (!d.elevel && (rc = dalloc(c, &d.elevel, d.K))) return rc;
     if (!d.H && (rc = dalloc(c, &d.H, (size_t)3 * 4 * d.K * d.Np))) return rc;
     HIPCHK(c, hipMemcpyAsync(d.elist, order.data(), d.K * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    d.elist_identity = true;
+    for (int64_t k = 0; k < d.K && d.elist_identity; ++k) d.elist_identity = order[k] == (int)k;
     HIPCHK(c, hipMemcpyAsync(d.elevel, el.data(), d.K, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemsetAsync(d.H, 0, (size_t)3 * 4 * d.K * d.Np * sizeof(float), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1691,17 +1705,17 @@ int hdg_profile(hdg_ctx* c, int on) {
 int hdg_profile_read(hdg_ctx* c, double* ms_out, int64_t* count_out) {
   if (!c) return HDG_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  double ms[4] = {0, 0, 0, 0};
-  int64_t cnt[4] = {0, 0, 0, 0};
+  double ms[12] = {};
+  int64_t cnt[12] = {};
   for (size_t i = 0; i < c->ev_used; ++i) {
     float v = 0.f;
     HIPCHK(c, hipEventElapsedTime(&v, c->ev_pool[i][0], c->ev_pool[i][1]));
     ms[c->ev_type[i]] += v;
     cnt[c->ev_type[i]] += 1;
   }
-  for (int t = 0; t < 4; ++t) {
-    if (ms_out) ms_out[t] = ms[t];
-    if (count_out) count_out[t] = cnt[t];
+  for (int k = 0; k < 12; ++k) {
+    if (ms_out) ms_out[k] = ms[k];
+    if (count_out) count_out[k] = cnt[k];
   }
   c->ev_used = 0;
   return HDG_OK;

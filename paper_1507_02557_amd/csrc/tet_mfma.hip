@@ -15,6 +15,13 @@ __global__ __launch_bounds__(S::NT) void tet_mfma_kernel(StageArgs a) {
   S::run(sm, a);
 }
 
+// multi-rate AB3 update of the tetrahedra (kModeMrab)
+template <class S>
+__global__ __launch_bounds__(64 * S::NWU) void tet_mrab_update_kernel(StageArgs a) {
+  __shared__ typename S::USmem sm;
+  S::run_update(sm, a);
+}
+
 // wavefronts per block: as many as fit the LDS (operator fragments are held
 // once per block)
 template <int N, int P, int NW>
@@ -33,8 +40,24 @@ using TetM = TetMfma<N, tet_waves<N, P>(), P>;
 template <class S>
 static int go_mfma(const StageArgs& a, hipStream_t s, int max_blocks) {
   static_assert(sizeof(typename S::Smem) <= 160 * 1024, "LDS budget exceeded");
+  static_assert(sizeof(typename S::USmem) <= 160 * 1024, "LDS budget of the update kernel exceeded");
   if (a.n_items == 0) return 0;
   const int64_t ntile = (a.n_items + 15) / 16;
+  if (a.mode == kModeMrab) {
+    // persistent grid of the blocks the device holds at once
+    static const int64_t per_cu = [] {
+      int b = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &b, reinterpret_cast<const void*>(&tet_mrab_update_kernel<S>), 64 * S::NWU, 0) != hipSuccess || b < 1)
+        b = 1;
+      return (int64_t)b;
+    }();
+    const int64_t nblk = (ntile + S::NWU - 1) / S::NWU;
+    const int64_t cap = per_cu * max_blocks;
+    const unsigned grid = (unsigned)(nblk < cap ? nblk : cap);
+    hipLaunchKernelGGL(tet_mrab_update_kernel<S>, dim3(grid), dim3(64 * S::NWU), 0, s, a);
+    return 0;
+  }
   const int64_t nblk = (ntile + S::NT / 64 - 1) / (S::NT / 64);
   const unsigned grid = (unsigned)(nblk < max_blocks ? nblk : max_blocks);
   hipLaunchKernelGGL(tet_mfma_kernel<S>, dim3(grid), dim3(S::NT), 0, s, a);

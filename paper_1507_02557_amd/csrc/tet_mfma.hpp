@@ -196,7 +196,8 @@ struct TetMfma {
   }
 
   // face-node values of the tile's state, canonical lattice order
-  __device__ static void write_traces(const Smem& sm, const Wave& W, const StageArgs& a, int64_t e0, int lane,
+  template <class SM, class WV>
+  __device__ static void write_traces(const SM& sm, const WV& W, const StageArgs& a, int64_t e0, int lane,
                                       const FaceRec& rec, float4* tr) {
     const int n = lane & 15, g = lane >> 4;
     const int64_t e = item(a, e0 + n);
@@ -215,52 +216,102 @@ struct TetMfma {
     }
   }
 
-  // multi-rate AB3 update: u_half traces (dense output at mid-step), then
-  // u_new = u + dtau_l sum_j beta_j(1) r_{s-j} with its traces
-  __device__ static void mrab_update(const Smem& sm, Wave& W, const StageArgs& a, int64_t e0, int lane,
-                                     const FaceRec& rec) {
+  // ---- multi-rate AB3 update: a kernel of its own (no operator tables, a
+  // state tile per wavefront, its own register budget)
+  //   u_half = u + dtau_l sum_j beta_j(1/2) r_{s-j}   (dense output at mid-step)
+  //   u_new  = u + dtau_l sum_j beta_j(1)   r_{s-j}
+  // The history is read once, in the tile's flat node order (consecutive
+  // lanes, consecutive addresses): the tile becomes u_half while
+  // u_new - u_half stays in registers; the mid-step traces are written, then
+  // the tile becomes u_new, which is stored with its traces.
+  static constexpr int NWU = 4;  // wavefronts per block of the update kernel
+  static constexpr int JN = (16 * Np + 63) / 64;  // flat tile entries per lane
+  struct alignas(16) UWave {
+    float X[4][16][SX];
+  };
+  struct USmem {
+    MrabParams mr;  // per-level weights and history slots (indexed by the element's level)
+    int fnode[4][Nfn];
+    int tperm[6][Nfn];
+    UWave w[NWU];
+  };
+
+  __device__ static void update_tile(const USmem& sm, UWave& W, const StageArgs& a, int64_t e0, int lane) {
     const int64_t K = a.K;
     const int64_t hstr = 4 * K * Np;
     const int n = lane & 15, g = lane >> 4;
     const int64_t e = item(a, e0 + n);
-    const int lv = e >= 0 ? a.elevel[e] : 1;
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const int o = __shfl(rec.ori, n + 16 * f);
-      if (e < 0) continue;
-      const int64_t slot = a.slot0 + e * 4 + f;
-      for (int j = 0; j < JF; ++j) {
-        const int m = g + 4 * j;
-        if (m >= Nfn) continue;
-        const int node = sm.fnode[f][sm.tperm[o][m]];
-        float v[4];
-        for (int c = 0; c < 4; ++c) {
-          const int64_t gi = (int64_t)c * K * Np + e * Np + node;
-          const float acc = a.mr.bh[lv][0] * a.H[a.mr.hs[lv][0] * hstr + gi] +
-                            a.mr.bh[lv][1] * a.H[a.mr.hs[lv][1] * hstr + gi] +
-                            a.mr.bh[lv][2] * a.H[a.mr.hs[lv][2] * hstr + gi];
-          v[c] = W.X[c][n][node] + a.mr.dtl[lv] * acc;
-        }
-        a.tr_half[slot * Nfq + m] = make_float4(v[0], v[1], v[2], v[3]);
-      }
+    const bool contig = contiguous(a, e0);
+    wave_sync();
+    const FaceRec rec = load_rec(a, e, g);
+    if (contig) {
+      const int64_t fs = K * Np;
+      float4 v0[JQ], v1[JQ], v2[JQ], v3[JQ];
+      load_field(v0, a.U, e0, lane);
+      load_field(v1, a.U + fs, e0, lane);
+      load_field(v2, a.U + 2 * fs, e0, lane);
+      load_field(v3, a.U + 3 * fs, e0, lane);
+      put_field<SX>(W.X[0], v0, lane);
+      put_field<SX>(W.X[1], v1, lane);
+      put_field<SX>(W.X[2], v2, lane);
+      put_field<SX>(W.X[3], v3, lane);
+    } else {
+      for (int c = 0; c < 4; ++c) load_rows<SX>(W.X[c], a.U + (int64_t)c * K * Np, a, e0, lane);
     }
     wave_sync();
+    float dd[4][JN];
+#pragma unroll
     for (int c = 0; c < 4; ++c)
-      for (int it = lane; it < 16 * Np; it += 64) {
+#pragma unroll
+      for (int j = 0; j < JN; ++j) {
+        dd[c][j] = 0.f;
+        const int it = lane + 64 * j;
+        if (it >= 16 * Np) continue;
         const int nn = it / Np, k = it - nn * Np;
         const int64_t ee = item(a, e0 + nn);
         if (ee < 0) continue;
-        const int l2 = a.elevel[ee];
+        const int lv = a.elevel[ee];
+        const MrabParams& mr = sm.mr;
         const int64_t gi = (int64_t)c * K * Np + ee * Np + k;
-        const float acc = a.mr.b1[l2][0] * a.H[a.mr.hs[l2][0] * hstr + gi] +
-                          a.mr.b1[l2][1] * a.H[a.mr.hs[l2][1] * hstr + gi] +
-                          a.mr.b1[l2][2] * a.H[a.mr.hs[l2][2] * hstr + gi];
-        const float un = W.X[c][nn][k] + a.mr.dtl[l2] * acc;
-        W.X[c][nn][k] = un;
-        a.U[gi] = un;
+        const float h0 = a.H[mr.hs[lv][0] * hstr + gi], h1 = a.H[mr.hs[lv][1] * hstr + gi],
+                    h2 = a.H[mr.hs[lv][2] * hstr + gi];
+        const float dl = mr.dtl[lv];
+        const float d1 = dl * (mr.b1[lv][0] * h0 + mr.b1[lv][1] * h1 + mr.b1[lv][2] * h2);
+        const float dh = dl * (mr.bh[lv][0] * h0 + mr.bh[lv][1] * h1 + mr.bh[lv][2] * h2);
+        W.X[c][nn][k] += dh;
+        dd[c][j] = d1 - dh;
       }
     wave_sync();
+    write_traces(sm, W, a, e0, lane, rec, a.tr_half);
+    wave_sync();
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < JN; ++j) {
+        const int it = lane + 64 * j;
+        if (it >= 16 * Np) continue;
+        const int nn = it / Np, k = it - nn * Np;
+        W.X[c][nn][k] += dd[c][j];
+      }
+    wave_sync();
+#pragma unroll
+    for (int c = 0; c < 4; ++c) store_tile<SX>(a.U + (int64_t)c * K * Np, W.X[c], a, e0, lane, contig);
     write_traces(sm, W, a, e0, lane, rec, a.tr_out);
+  }
+
+  __device__ static void run_update(USmem& sm, const StageArgs& a) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid == 0) sm.mr = a.mr;
+    for (int i = tid; i < 4 * Nfn; i += 64 * NWU) (&sm.fnode[0][0])[i] = a.iops[i];
+    for (int i = tid; i < 6 * Nfn; i += 64 * NWU) (&sm.tperm[0][0])[i] = a.iops[4 * Nfn + i];
+    // padded rows of the tiles must hold finite values
+    float* wz = &sm.w[0].X[0][0][0];
+    for (int i = tid; i < (int)(NWU * sizeof(UWave) / sizeof(float)); i += 64 * NWU) wz[i] = 0.f;
+    __syncthreads();
+    UWave& W = sm.w[wv];
+    const int64_t ntile = (a.n_items + 15) / 16;
+    for (int64_t t = (int64_t)blockIdx.x * NWU + wv; t < ntile; t += (int64_t)gridDim.x * NWU)
+      update_tile(sm, W, a, t * 16, lane);
   }
 
   // acc += L_f F (one field) with split FP16 operands and a column scale.
@@ -433,10 +484,6 @@ struct TetMfma {
     wave_sync();
     if (a.mode == kModeTrace) {
       write_traces(sm, W, a, e0, lane, rec, a.tr_out);
-      return;
-    }
-    if (a.mode == kModeMrab) {
-      mrab_update(sm, W, a, e0, lane, rec);
       return;
     }
     const float iJ = G[9];

@@ -267,10 +267,13 @@ class Solver:
         return p.value, lat.value
 
     def profile_read(self):
-        ms = np.zeros(4, dtype=np.float64)
-        cnt = np.zeros(4, dtype=np.int64)
+        """Kernel milliseconds and launch counts since the last reset, each (3, 4):
+        [kind][type], kind 0 stage / right-hand side, 1 multi-rate update,
+        2 non-conforming interface (type TET)."""
+        ms = np.zeros(12, dtype=np.float64)
+        cnt = np.zeros(12, dtype=np.int64)
         self._check(self._lib.hdg_profile_read(self._h, ms.ctypes.data, cnt.ctypes.data))
-        return ms, cnt
+        return ms.reshape(3, 4), cnt.reshape(3, 4)
 
     def project_function(self, func, time: float = 0.0):
         """Sample func(x, y, z, t) -> (p, ux, uy, uz) at each type's points and project."""

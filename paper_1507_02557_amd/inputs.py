@@ -100,6 +100,20 @@ class Mesh:
     def counts(self) -> dict:
         return {TYPE_NAMES[t]: int(np.sum(self.etype == t)) for t in (HEX, WEDGE, PYR, TET)}
 
+    def permuted(self, order) -> "Mesh":
+        """The same mesh with element i of the result being element order[i]."""
+        order = np.asarray(order, dtype=np.int64)
+        if order.shape != (self.n_elem,) or not np.array_equal(np.sort(order), np.arange(self.n_elem)):
+            raise ValueError("order must be a permutation of the elements")
+        return Mesh(xyz=self.xyz, etype=self.etype[order], everts=self.everts[order], kappa=self.kappa[order],
+                    rho=self.rho[order], n=self.n, info=dict(self.info), hanging=self.hanging)
+
+    def level_order(self, level) -> np.ndarray:
+        """Element order that stores every type's elements finest level first
+        (highest level number first, mesh order within a level)."""
+        level = np.asarray(level, dtype=np.int64)
+        return np.lexsort((np.arange(self.n_elem), -level, self.etype.astype(np.int64)))
+
 
 def _slab_of_layer(n: int, layer: int, nslab: int) -> int:
     for k in range(nslab):
