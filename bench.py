@@ -1,13 +1,26 @@
 #!/usr/bin/env python3
 """Throughput of the hybrid-mesh DG hot path on one MI355X.
 
-Workload (default): the four-slab hybrid mesh on 48^3 cubes (hex | wedge |
-pyramid+tet | tet slabs, interior vertices jittered by 10% of h, seed 0),
-order N = 4, Gaussian pressure pulse (width 0.05, centre from the seed),
-u = 0, rigid walls, single-rate LSERK4 at the derived stable step for T = 0.5.
-One "step" is one LSERK4 step: five stages, each one fused kernel per
-element type.  The metric is GDOF/s per RK stage: element-node dofs of one
-scalar field updated per stage per second (x1e-9).
+Workload (default, ``--workload refined``): the four-slab hybrid mesh on 48^3
+cubes (hex | wedge | pyramid+tet | tet slabs, interior vertices jittered by
+10% of h, seed 0) with the tetrahedral slab refined 2x in h (a 1:4
+non-conforming face; 1,688,832 elements), order N = 4, Gaussian pressure
+pulse (width 0.05, centre from the seed), u = 0, rigid walls, advanced by the
+multi-rate AB3 scheme on three levels (Section 2.4).  Elements are stored
+finest level first, so every substep's active elements are a prefix of each
+type's storage.  One "step" is one coarse step: four substeps of dtau_min,
+each a right-hand-side kernel and an AB3 update kernel per element type over
+the active levels, plus the non-conforming interface kernel.
+
+The metric is GDOF/s per RK stage, mixed precision against FP32 plain: per
+substep, the element-node dofs of one scalar field of the active elements,
+per second (x1e-9).  Every precision runs the same workload; ``value`` is the
+fastest split-precision mode whose rel L2 error against the FP64 oracle
+(stored oracle states of the same construction on 4^3 cubes, see
+tests/golden/) is at most 1e-5.
+
+``--workload four-slab``: the conforming four-slab mesh on 48^3 cubes,
+single-rate LSERK4 (a step is five stages).
 
 Prints one JSON line (rank 0, N = 1).
 """
@@ -24,10 +37,46 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TOL_FP64 = 1e-5
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _np_of(t: int, N: int) -> int:
+    if t == 3:
+        return (N + 1) * (N + 2) * (N + 3) // 6
+    if t == 2:
+        return (N + 1) * (N + 2) * (2 * N + 3) // 6
+    if t == 1:
+        return (N + 1) * (N + 1) * (N + 2) // 2
+    return (N + 1) ** 3
+
+
+def _trace_points(t: int, N: int, lattice: bool) -> int:
+    """Trace values an element of type t exchanges over all its faces."""
+    n1 = N + 1
+    nfn, nfq = (N + 1) * (N + 2) // 2, n1 * n1
+    tri = nfn if lattice else nfq
+    if t == 3:
+        return 4 * tri
+    if t == 2:
+        return nfq + 4 * tri
+    if t == 1:
+        return 5 * nfq  # wedge-wedge triangles carry cubature values
+    return 6 * nfq
+
+
+def _geometry_bytes(t: int) -> int:
+    # the smaller of the FP64 vertices and the stored per-element factors
+    return {3: min(4 * 24, 48 + 4 * 16), 2: 5 * 24, 1: 6 * 24, 0: 8 * 24}[t]
+
+
+def _faces(t: int) -> int:
+    return {3: 4, 2: 5, 1: 5, 0: 6}[t]
 
 
 def alg_bytes(t: int, N: int, lattice: bool) -> int:
-    """Algorithmic HBM bytes per element per stage of the fused kernel of type t.
+    """Algorithmic HBM bytes per element per stage of the fused LSERK4 kernel
+    of type t.
 
     State: read U and res, write U and res (4 fields, FP32): 64 B per node.
     Traces: write the element's own trace and read the neighbour's (4 fields,
@@ -39,24 +88,37 @@ def alg_bytes(t: int, N: int, lattice: bool) -> int:
     floats + 4 face normals with J^s).  Material (kappa, 1/rho): 8 B.  Face
     records (neighbour slot, orientation, penalties): 13 B per face.
     """
-    n1 = N + 1
-    nfn, nfq = (N + 1) * (N + 2) // 2, n1 * n1
-    tri = nfn if lattice else nfq
-    if t == 3:  # tetrahedron
-        np_ = (N + 1) * (N + 2) * (N + 3) // 6
-        return 64 * np_ + 32 * 4 * tri + min(4 * 24, 48 + 4 * 16) + 8 + 4 * 13
-    if t == 2:  # pyramid: base quad + 4 triangles
-        np_ = (N + 1) * (N + 2) * (2 * N + 3) // 6
-        return 64 * np_ + 32 * (nfq + 4 * tri) + 5 * 24 + 8 + 5 * 13
-    if t == 1:  # wedge: 2 triangles (wedge-wedge: cubature) + 3 quads
-        np_ = n1 * nfn
-        return 64 * np_ + 32 * 5 * nfq + 6 * 24 + 8 + 5 * 13
-    np_ = n1 ** 3  # hexahedron
-    return 64 * np_ + 32 * 6 * nfq + 8 * 24 + 8 + 6 * 13
+    return (64 * _np_of(t, N) + 32 * _trace_points(t, N, lattice) + _geometry_bytes(t) + 8
+            + 13 * _faces(t))
 
 
 def tet_alg_bytes(N: int, lattice: bool) -> int:
     return alg_bytes(3, N, lattice)
+
+
+def mrab_alg_bytes(kind: int, t: int, N: int, lattice: bool) -> int:
+    """Algorithmic HBM bytes per active element of one multi-rate kernel.
+
+    kind 0, right-hand side into the history: read U and write one history
+    slot (32 B per node), read the neighbours' traces (16 B per trace point),
+    geometry, material, face records as in alg_bytes.
+    kind 1, AB3 update: read U and three history slots, write U (80 B per
+    node), write the synchronised and the mid-step traces (32 B per trace
+    point), orientation codes (1 B per face).
+    """
+    np_, tp, nf = _np_of(t, N), _trace_points(t, N, lattice), _faces(t)
+    if kind == 0:
+        return 32 * np_ + 16 * tp + _geometry_bytes(t) + 8 + 13 * nf
+    return 80 * np_ + 32 * tp + nf
+
+
+def mortar_alg_bytes(N: int, dense: bool) -> int:
+    """Per non-conforming coarse face: read the coarse trace and the four fine
+    traces, write four virtual-slot traces and the flux (16 B per lattice
+    value); with mid-step traces also read the coarse mid-step trace and write
+    four more virtual-slot traces."""
+    nfn = (N + 1) * (N + 2) // 2
+    return 16 * nfn * (1 + 4 + 4 + 1 + (5 if dense else 0)) + 40
 
 
 def csrc_hash() -> str:
@@ -90,14 +152,17 @@ def measured_traffic(kernel_name: str, also: str = ""):
     return None
 
 
-def cpu_baseline(n: int, N: int, stages: int):
+def cpu_baseline(n: int, N: int, stages: int, refined: bool):
+    """The FP64 oracle timed on the host cores: `stages` LSERK4 stages
+    (right-hand side + update of every element) on a smaller mesh of the same
+    construction."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
     from oracle.solver import LSERK_A, LSERK_B, Disc
     from paper_1507_02557_amd.inputs import four_slab_mesh, gaussian_pulse, pulse_centre
 
-    mesh = four_slab_mesh(n, seed=0, jitter=0.1)
+    mesh = four_slab_mesh(n, seed=0, jitter=0.1, refine_last=2 if refined else 1)
     d = Disc(mesh, N)
     c = pulse_centre(0)
     U = d.project(lambda x, y, z, t: gaussian_pulse(x, y, z, c))
@@ -112,10 +177,11 @@ def cpu_baseline(n: int, N: int, stages: int):
             U[t] = U[t] + LSERK_B[s % 5] * res[t]
     el = time.perf_counter() - t0
     threads = max([1] + [p.get("num_threads", 1) for p in threadpool_info()])
+    kind = "refined-slab " if refined else ""
     return {"value": dofs * stages / el / 1e9, "unit": "GDOF/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"FP64 oracle, {stages} LSERK4 stages on the n={n} four-slab mesh "
-                      f"({mesh.n_elem} elements, {dofs} dofs/field, N={N}); {el:.1f} s on "
-                      f"{os.cpu_count()} visible host cores"}
+            "sample": f"FP64 oracle, {stages} LSERK4 stages (every element each stage) on the n={n} "
+                      f"{kind}four-slab mesh ({mesh.n_elem} elements, {dofs} dofs/field, N={N}); "
+                      f"{el:.1f} s on {os.cpu_count()} visible host cores"}
 
 
 def copy_calibration(mib: int):
@@ -132,17 +198,271 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}))
 
 
+PREC_NAMES = {0: "fp32", 1: "fp16x2", 2: "fp16x2-k16"}
+PREC_DESC = {
+    0: "FP32 operands, FP32 accumulation (16x16x4 MFMA)",
+    1: "split FP16 operands (hi + lo, power-of-two scales), FP32 accumulation, 16x16x32 MFMA",
+    2: "split FP16 operands (hi + lo, power-of-two scales), FP32 accumulation, 16x16x16 MFMA",
+}
+TYPE_NAMES = ((0, "hex"), (1, "wedge"), (2, "pyr"), (3, "tet"))
+
+
+def _energy_rel(solver, A, B):
+    """sqrt(E(A - B) / E(B)) with the library's energy (mass-weighted; kappa =
+    rho = 1 on these meshes, so this is the rel L2 norm of all four fields).
+    A, B: per type tensors (K, 4, Np) on the device, float64.  Leaves the
+    solver's state at B."""
+    for t, a in A.items():
+        d = (a - B[t]).float()
+        solver.set_state(t, [d[:, c].contiguous() for c in range(4)])
+    num = solver.energy()
+    for t, b in B.items():
+        solver.set_state(t, [b[:, c].float().contiguous() for c in range(4)])
+    den = solver.energy()
+    return math.sqrt(max(num, 0.0) / den)
+
+
+def fp64_check(hdg, N: int, precision: int):
+    """rel L2 against the stored FP64 oracle state of the refined construction
+    on 4^3 cubes (standing mode, multi-rate AB3 on three levels); None if no
+    stored state exists for this order."""
+    import numpy as np
+    import torch
+
+    from paper_1507_02557_amd.inputs import four_slab_mesh, standing_mode_rigid
+
+    path = os.path.join(GOLDEN, f"refined_n4_standing_N{N}.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    mesh = four_slab_mesh(4, seed=0, jitter=0.1, refine_last=2)
+    s = hdg.Solver(mesh, N, precision=precision)
+    _, _, lev = s.mrab_setup(int(g["levels"]))
+    if not np.array_equal(lev, g["level"]):
+        raise RuntimeError("multi-rate levels differ from the stored oracle run")
+    s.project_function(standing_mode_rigid)
+    s.mrab_advance(0)
+    s.mrab_advance(int(g["coarse_steps"]))
+    A = {t: s.get_field(t).double() for t in s.types}
+    B = {t: torch.from_numpy(g[f"U{t}"]).to(A[t].device) for t in s.types}
+    rel = _energy_rel(s, A, B)
+    s.close()
+    return {"rel_l2": rel, "mesh": "refined four-slab n=4 (seed 0), standing mode",
+            "steps": f"start-up + {int(g['coarse_steps'])} coarse steps, t={float(g['t']):.4e}"}
+
+
+def run_refined(args, hdg, torch, np):
+    from paper_1507_02557_amd.inputs import four_slab_mesh, gaussian_pulse, pulse_centre
+
+    N, L = args.order, args.levels
+    mesh0 = four_slab_mesh(args.n, seed=0, jitter=0.1, refine_last=2)
+    # store every type's elements finest level first (levels do not depend on
+    # the element order)
+    s0 = hdg.Solver(mesh0, N)
+    _, cnt0, lev0 = s0.mrab_setup(L)
+    s0.close()
+    order = mesh0.level_order(lev0)
+    mesh = mesh0.permuted(order)
+    lev = lev0[order]
+    c = pulse_centre(0)
+    precs = [int(p) for p in args.precisions.split(",")]
+    if 0 not in precs:
+        precs = [0] + precs
+
+    results, states, keep = {}, {}, None
+    npe = {t: _np_of(t, N) for t, _ in TYPE_NAMES}
+    # active element-node dofs per coarse step: level l is active 2^(l-1) times
+    active_dofs = 0
+    for t, _ in TYPE_NAMES:
+        for l in range(1, L + 1):
+            active_dofs += int(np.sum((mesh.etype == t) & (lev == l))) * npe[t] * (2 ** (l - 1))
+    nsub = 2 ** (L - 1)
+    prof_steps = max(2, args.steps // 4)
+    for p in precs:
+        s = hdg.Solver(mesh, N, precision=p)
+        s.project_function(lambda x, y, z, t: gaussian_pulse(x, y, z, c))
+        dtmin, cnt, lv = s.mrab_setup(L)
+        assert np.array_equal(lv, lev)
+        s.mrab_advance(0)  # start-up: two coarse steps of LSERK4 at dtau_min
+        s.mrab_advance(args.warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.mrab_advance(args.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        s.profile(True)
+        s.mrab_advance(prof_steps)
+        kms, kcnt = s.profile_read()
+        s.profile(False)
+        states[p] = {t: s.get_field(t).double() for t in s.types}
+        lattice = s.get_path()[1] == 1
+        gd = active_dofs * args.steps / (ms * 1e-3) / 1e9
+        results[p] = {
+            "precision": PREC_DESC[p] + ("" if p == 0 else "; tetrahedra (other types FP32)"),
+            "value": round(gd, 4), "unit": "GDOF/s",
+            "ms_per_coarse_step": round(ms / args.steps, 4),
+            "ms_per_substep": round(ms / args.steps / nsub, 4),
+            "effective_single_rate_gdofs": round(sum(int(np.sum(mesh.etype == t)) * npe[t] for t, _ in TYPE_NAMES)
+                                                 * nsub * args.steps / (ms * 1e-3) / 1e9, 4),
+            "kernel_ms_per_coarse_step": {
+                f"{k}_{name}": round(float(kms[ki][t]) / prof_steps, 4)
+                for ki, k in enumerate(("rhs", "update", "interface")) for t, name in TYPE_NAMES if kcnt[ki][t]},
+            "energy_after": s.energy(),
+        }
+        if p == 0:
+            keep = (s, kms, kcnt, lattice, dtmin, cnt)
+        else:
+            s.close()
+            del s
+    s, kms, kcnt, lattice, dtmin, cnt = keep
+    # accuracy: every mode against the stored FP64 oracle run (small mesh), and
+    # against the FP32 path after the same steps at full size
+    for p in precs:
+        chk = fp64_check(hdg, N, p)
+        results[p]["rel_l2_vs_fp64"] = chk["rel_l2"] if chk else None
+        results[p]["fp64_reference"] = chk
+        if p != 0:
+            results[p]["rel_l2_vs_fp32_full_size"] = _energy_rel(s, states[p], states[0])
+            results[p]["speedup_vs_fp32_plain"] = round(results[p]["value"] / results[0]["value"], 4)
+
+    # roofline of each (kind, type) kernel: algorithmic bytes of all its
+    # launches in a coarse step over its event-timed duration
+    counts = {t: [int(np.sum((mesh.etype == t) & (lev == l))) for l in range(1, L + 1)] for t, _ in TYPE_NAMES}
+    act = {t: sum(counts[t][l - 1] * (2 ** (l - 1)) for l in range(1, L + 1)) for t, _ in TYPE_NAMES}
+    n_nc = int(mesh.hanging.shape[0] > 0) * 2 * args.n * args.n
+    roof = {}
+    for kind, kname in ((0, "rhs"), (1, "update")):
+        for t, name in TYPE_NAMES:
+            if not kcnt[kind][t]:
+                continue
+            ms_k = float(kms[kind][t]) / prof_steps
+            b = mrab_alg_bytes(kind, t, N, lattice) * act[t]
+            ach = b / (ms_k * 1e-3) / 1e9
+            roof[f"{kname}_{name}"] = {
+                "bound": "hbm", "ms_per_coarse_step": round(ms_k, 4), "launches_per_coarse_step": int(kcnt[kind][t]) // prof_steps,
+                "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": None, "alg_bytes_per_element": mrab_alg_bytes(kind, t, N, lattice),
+                "active_elements_per_coarse_step": act[t]}
+    if kcnt[2][3]:
+        ms_k = float(kms[2][3]) / prof_steps
+        b = mortar_alg_bytes(N, True) * n_nc * nsub
+        roof["interface_tet"] = {"bound": "hbm", "ms_per_coarse_step": round(ms_k, 4),
+                                 "achieved": round(b / (ms_k * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(b / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                                 "alg_bytes_per_face": mortar_alg_bytes(N, True), "faces": n_nc}
+    dominant = max(roof, key=lambda k: roof[k]["ms_per_coarse_step"])
+    s.close()
+
+    mixed = [p for p in precs if p != 0]
+    ok = [p for p in mixed if results[p]["rel_l2_vs_fp64"] is not None and results[p]["rel_l2_vs_fp64"] <= TOL_FP64]
+    best = max(ok, key=lambda p: results[p]["value"]) if ok else (mixed[0] if mixed else 0)
+    head = results[best]
+    workload = (f"four-slab hybrid mesh n={args.n} with the tetrahedral slab refined 2x in h (1:4 non-conforming "
+                f"face; jitter 0.1h, seed 0), N={N}, Gaussian pulse, rigid walls, MRAB3 on {L} levels, elements "
+                f"stored finest level first; {PREC_NAMES[best]}")
+    out = {
+        "metric": "GDOF/s per RK stage: mixed-precision vs FP32 plain, at rel L2 <= 1e-5 vs FP64",
+        "value": head["value"],
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_coarse_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if best == 0 else f"{PREC_NAMES[best]} operands, f32 accumulate",
+        "data": "synthetic",
+        "config": {
+            "workload": workload,
+            "precision": PREC_NAMES[best],
+            "meets_fp64_bar": best in ok,
+            "fp32_plain_value": results[0]["value"],
+            "speedup_vs_fp32_plain": head.get("speedup_vs_fp32_plain", 1.0),
+            "elements": {name: int(np.sum(mesh.etype == t)) for t, name in TYPE_NAMES},
+            "elements_per_level": [int(x) for x in cnt],
+            "dt_min": dtmin,
+            "active_dofs_per_coarse_step": int(active_dofs),
+            "substeps_per_coarse_step": nsub,
+            "precisions": {PREC_NAMES[p]: results[p] for p in precs},
+            "roofline_by_kernel": roof,
+        },
+        "roofline": dict(roof[dominant], kernel=dominant),
+    }
+    return out
+
+
+def run_four_slab(args, hdg, torch, np):
+    from paper_1507_02557_amd.inputs import four_slab_mesh, gaussian_pulse, pulse_centre
+
+    N = args.order
+    mesh = four_slab_mesh(args.n, seed=0, jitter=0.1)
+    c = pulse_centre(0)
+    T = 0.5
+    s = hdg.Solver(mesh, N, bc=hdg.BC_RIGID_WALL)
+    s.project_function(lambda x, y, z, t: gaussian_pulse(x, y, z, c))
+    _, dtmin = s.dt(0.5)
+    dt = T / math.ceil(T / dtmin)
+    s.step(dt, args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.step(dt, args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    prof_steps = max(2, args.steps // 4)
+    s.profile(True)
+    s.step(dt, prof_steps)
+    kms, kcnt = s.profile_read()
+    s.profile(False)
+    dofs = sum(s.info[t][0] * s.info[t][1] for t in s.types)
+    stages = 5 * args.steps
+    gdofs = dofs * stages / (ms * 1e-3) / 1e9
+    lattice = s.get_path()[1] == 1
+    roof = {}
+    for t, name in TYPE_NAMES:
+        if not kcnt[0][t]:
+            continue
+        ms_t = float(kms[0][t]) / kcnt[0][t]
+        b = alg_bytes(t, N, lattice) * s.info[t][0]
+        ach = b / (ms_t * 1e-3) / 1e9
+        roof[name] = {"bound": "hbm", "ms_per_launch": round(ms_t, 4), "achieved": round(ach, 1),
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                      "alg_bytes_per_launch": int(b), "alg_bytes_per_element": alg_bytes(t, N, lattice)}
+    dominant = max(roof, key=lambda k: roof[k]["ms_per_launch"])
+    out = {
+        "metric": "GDOF/s per RK stage: mixed-precision vs FP32 plain, at rel L2 <= 1e-5 vs FP64",
+        "value": round(gdofs, 4), "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"four-slab hybrid mesh n={args.n} (jitter 0.1h, seed 0), N={N}, Gaussian pulse, "
+                               f"rigid walls, single-rate LSERK4, FP32 plain",
+                   "elements": {name: int(s.info[t][0]) for t, name in TYPE_NAMES}, "dofs_per_field": int(dofs),
+                   "dt": dt, "stage_ms": round(ms / stages, 4), "roofline_by_type": roof, "energy_after": s.energy()},
+        "roofline": dict(roof[dominant], type=dominant),
+    }
+    s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10, help="timed steps (coarse multi-rate steps)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=("refined", "four-slab"), default="refined")
     ap.add_argument("--n", type=int, default=48)
     ap.add_argument("--order", type=int, default=4)
+    ap.add_argument("--levels", type=int, default=3)
+    ap.add_argument("--precisions", default="0,1,2", help="precision codes to run (0 FP32 always runs)")
     ap.add_argument("--cpu-n", type=int, default=12)
-    ap.add_argument("--cpu-stages", type=int, default=20)
+    ap.add_argument("--cpu-stages", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-mrab", action="store_true", help="skip the multi-rate (MRAB3) measurement")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -157,155 +477,13 @@ def main():
     import torch
 
     from paper_1507_02557_amd import hdg
-    from paper_1507_02557_amd.inputs import four_slab_mesh, gaussian_pulse, pulse_centre
 
-    N = args.order
-    mesh = four_slab_mesh(args.n, seed=0, jitter=0.1)
-    c = pulse_centre(0)
-    T = 0.5
-    prof_steps = max(2, args.steps // 4)
-
-    def run(precision: int, dt: float | None):
-        s = hdg.Solver(mesh, N, bc=hdg.BC_RIGID_WALL, precision=precision)
-        s.project_function(lambda x, y, z, t: gaussian_pulse(x, y, z, c))
-        if dt is None:
-            _, dtmin = s.dt(0.5)
-            dt = T / math.ceil(T / dtmin)
-        s.step(dt, args.warmup)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        s.step(dt, args.steps)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        # per-kernel durations (events on the launch stream around each launch)
-        s.profile(True)
-        s.step(dt, prof_steps)
-        kms, kcnt = s.profile_read()
-        s.profile(False)
-        state = {t: s.get_field(t).clone() for t in s.types}
-        return s, dt, ms, kms, kcnt, state
-
-    s, dt, ms, kms, kcnt, state32 = run(hdg.PREC_FP32, None)
-    dofs = sum(s.info[t][0] * s.info[t][1] for t in s.types)
-    stages = 5 * args.steps
-    gdofs = dofs * stages / (ms * 1e-3) / 1e9
-    Ktet = s.info[hdg.TET][0]
-    lattice = s.get_path()[1] == 1
-    # kernel names as rocprofv3 reports them (for the committed traffic counters)
-    kname = {3: (f"TetMfma<{N}, ", ", 0>") if lattice else (f"TetStage<{N}, ", ""),
-             2: (f"PyrMfma<{N}, ", "") if (lattice and N in (3, 4)) else (f"PyrStage<{N}, ", ""),
-             1: (f"WedgeStage<{N}, ", ""), 0: (f"HexStage<{N}, ", "")}
-    kfull = {3: "tet_mfma_kernel" if lattice else "stage_kernel",
-             2: "pyr_mfma_kernel" if (lattice and N in (3, 4)) else "stage_kernel",
-             1: "stage_kernel", 0: "stage_kernel"}
-    roof = {}
-    for t, name in ((0, "hex"), (1, "wedge"), (2, "pyr"), (3, "tet")):
-        if not kcnt[t]:
-            continue
-        ms_t = kms[t] / kcnt[t]
-        b = alg_bytes(t, N, lattice) * s.info[t][0]
-        ach = b / (ms_t * 1e-3) / 1e9
-        roof[name] = {"bound": "hbm", "kernel": f"{kfull[t]}<{kname[t][0]}...>", "ms_per_launch": round(ms_t, 4),
-                      "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "frac": round(ach / HBM_PEAK_GBS, 4),
-                      "traffic": measured_traffic(*kname[t]), "alg_bytes_per_launch": int(b),
-                      "alg_bytes_per_element": alg_bytes(t, N, lattice)}
-    dominant = max(roof, key=lambda k: roof[k]["ms_per_launch"])
-    per_type = {k: v["ms_per_launch"] for k, v in roof.items()}
-    E = s.energy()
-    info = dict(s.info)
-    types = list(s.types)
-    s.close()
-    del s
-
-    # the same workload with split-FP16 matrix-core products
-    s16, _, ms16, kms16, kcnt16, state16 = run(hdg.PREC_FP16X2, dt)
-    gdofs16 = dofs * stages / (ms16 * 1e-3) / 1e9
-    num = sum(float(((state16[t].double() - state32[t].double()) ** 2).sum()) for t in types)
-    den = sum(float((state32[t].double() ** 2).sum()) for t in types)
-    mixed = {
-        "precision": "split FP16 operands (hi + lo, power-of-two scales), FP32 accumulation, 16x16x32 MFMA, "
-                     "tetrahedra; other types FP32",
-        "value": round(gdofs16, 4),
-        "unit": "GDOF/s",
-        "speedup_vs_fp32_plain": round(gdofs16 / gdofs, 4),
-        "stage_ms": round(ms16 / stages, 4),
-        "kernel_ms_per_launch": {name: round(float(kms16[t] / max(kcnt16[t], 1)), 4)
-                                 for t, name in ((0, "hex"), (1, "wedge"), (2, "pyr"), (3, "tet")) if kcnt16[t]},
-        "rel_l2_vs_fp32_path": math.sqrt(num / den),
-        "steps_compared": args.warmup + args.steps + prof_steps,
-    }
-    s16.close()
-    del s16
-
-    # the same workload advanced by the multi-rate AB3 scheme (three levels,
-    # Section 2.4): simulated time per second against single-rate LSERK4
-    multi = None
-    if not args.no_mrab:
-        L = 3
-        smr = hdg.Solver(mesh, N, bc=hdg.BC_RIGID_WALL)
-        smr.project_function(lambda x, y, z, t: gaussian_pulse(x, y, z, c))
-        dtmin_mr, cnt, _ = smr.mrab_setup(L)
-        smr.mrab_advance(0)  # start-up (two coarse steps of LSERK4 at dt_min)
-        smr.mrab_advance(1)  # warm-up coarse step
-        torch.cuda.synchronize()
-        n_coarse = max(2, args.steps // 4)
-        m0 = torch.cuda.Event(enable_timing=True)
-        m1 = torch.cuda.Event(enable_timing=True)
-        m0.record()
-        t_adv = smr.mrab_advance(n_coarse)
-        m1.record()
-        torch.cuda.synchronize()
-        ms_mr = m0.elapsed_time(m1)
-        rate_mr = t_adv / (ms_mr * 1e-3)
-        rate_rk = dt * args.steps / (ms * 1e-3)
-        multi = {
-            "scheme": f"MRAB3, {L} levels (coarse step 2^{L - 1} dt_min), FP32",
-            "elements_per_level": [int(x) for x in cnt],
-            "dt_min": dtmin_mr,
-            "coarse_steps_timed": n_coarse,
-            "ms_per_coarse_step": round(ms_mr / n_coarse, 4),
-            "simulated_time_per_s": rate_mr,
-            "lserk4_simulated_time_per_s": rate_rk,
-            "speedup_vs_lserk4": round(rate_mr / rate_rk, 4),
-            "energy_after": smr.energy(),
-        }
-        smr.close()
-        del smr
-
-    out = {
-        "metric": "GDOF/s per RK stage: mixed-precision vs FP32 plain, at rel L2 <= 1e-5 vs FP64",
-        "value": round(gdofs, 4),
-        "unit": "GDOF/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms / args.steps, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": f"four-slab hybrid mesh n={args.n} (jitter 0.1h, seed 0), N={N}, Gaussian pulse, "
-                        f"rigid walls, single-rate LSERK4, FP32 plain",
-            "elements": {name: int(info[t][0]) for t, name in ((0, "hex"), (1, "wedge"), (2, "pyr"), (3, "tet"))},
-            "dofs_per_field": int(dofs),
-            "dt": dt,
-            "stage_ms": round(ms / stages, 4),
-            "kernel_ms_per_launch": per_type,
-            "energy_after": E,
-            "mixed_precision": mixed,
-            "multi_rate": multi,
-        },
-        "roofline": dict(roof[dominant], type=dominant),
-    }
-    out["config"]["roofline_by_type"] = roof
+    if args.workload == "refined":
+        out = run_refined(args, hdg, torch, np)
+    else:
+        out = run_four_slab(args, hdg, torch, np)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_n, N, args.cpu_stages)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.order, args.cpu_stages, args.workload == "refined")
     print(json.dumps(out))
 
 

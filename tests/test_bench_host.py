@@ -46,6 +46,25 @@ def test_alg_bytes_at_the_benchmark_order():
     assert [bench.alg_bytes(t, 4, True) for t in range(4)] == [13078, 9017, 6433, 4316]
 
 
+@pytest.mark.parametrize("N", [3, 4, 5])
+def test_multirate_bytes_split_the_stage_traffic(N):
+    """The multi-rate right-hand-side kernel moves U once and one history slot
+    (32 B/node) and reads the neighbours' traces (16 B/point); the update
+    reads U and three slots and writes U (80 B/node) and writes synchronised
+    and mid-step traces (32 B/point)."""
+    faces = {0: (6, 0), 1: (3, 2), 2: (1, 4), 3: (0, 4)}
+    geometry = {0: 8 * 24, 1: 6 * 24, 2: 5 * 24, 3: 4 * 24}
+    nq, nl = (N + 1) ** 2, (N + 1) * (N + 2) // 2
+    for t in range(4):
+        quads, tris = faces[t]
+        pts = quads * nq + tris * (nl if t in (2, 3) else nq)
+        nf = quads + tris
+        assert bench.mrab_alg_bytes(0, t, N, True) == 32 * _nodes(t, N) + 16 * pts + geometry[t] + 8 + 13 * nf
+        assert bench.mrab_alg_bytes(1, t, N, True) == 80 * _nodes(t, N) + 32 * pts + nf
+    nfn = (N + 1) * (N + 2) // 2
+    assert bench.mortar_alg_bytes(N, False) == 16 * nfn * 10 + 40
+
+
 def test_source_hash_is_stable_and_keys_the_traffic_file():
     h = bench.csrc_hash()
     assert len(h) == 16 and all(c in "0123456789abcdef" for c in h)
