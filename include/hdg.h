@@ -60,18 +60,27 @@ extern "C" {
 #define HDG_BC_RIGID_WALL 1   /* u . n = 0                     */
 
 /* Operand precision of the element-batched operator products on the matrix
- * cores (tetrahedra with lattice traces; every other product is FP32):
+ * cores (the tetrahedra's volume and lift products of Section 2.3.2,
+ * Algorithm 4, with lattice traces; every other product is FP32):
  *   HDG_PREC_FP32          FP32 operands (16x16x4 MFMA)
  *   HDG_PREC_FP16X2        split FP16 operands x = hi + lo, operators scaled
  *                          by a power of two per matrix group and element data
  *                          per element column, products hi*hi + hi*lo + lo*hi
  *                          accumulated in FP32 (16x16x32 MFMA)
  *   HDG_PREC_FP16X2_K16    the same split on 16x16x16 MFMA
+ *   HDG_PREC_BF16X2        split BF16 operands x = hi + lo (about 16
+ *                          significant bits), hi*hi + hi*lo + lo*hi in FP32
+ *                          (16x16x32 BF16 MFMA)
+ *   HDG_PREC_BF16X3        three-piece BF16 split x = hi + mid + lo (about 24
+ *                          bits), the six products with piece orders summing
+ *                          to at most 2, in FP32 (16x16x32 BF16 MFMA)
  * State, geometry (computed in FP64), fluxes and updates are FP32 in all
  * modes. */
 #define HDG_PREC_FP32 0
 #define HDG_PREC_FP16X2 1
 #define HDG_PREC_FP16X2_K16 2
+#define HDG_PREC_BF16X2 3
+#define HDG_PREC_BF16X3 4
 
 #define HDG_PATH_AUTO 0      /* lattice traces + matrix-core tetrahedra where the mesh allows */
 #define HDG_PATH_GENERIC 1   /* cubature-point traces on every face, vector kernels */
@@ -120,8 +129,8 @@ typedef struct hdg_mesh {
  * Builds the reference operators in FP64 on the host, matches faces, and
  * computes the geometric factors in FP64 on the device.  Work is enqueued on
  * hip_stream (a hipStream_t, may be NULL for the null stream); the call
- * synchronises that stream before returning.  precision: one of
- * HDG_PREC_FP32, HDG_PREC_FP16X2, HDG_PREC_FP16X2_K16 (else HDG_EINVAL).
+ * synchronises that stream before returning.  precision: one of the
+ * HDG_PREC_* codes above (else HDG_EINVAL).
  * Errors: HDG_EINVAL (N out of range, bad type id, NULL pointer),
  * HDG_EMESH (non-positive Jacobian, a face shared by more than two elements),
  * HDG_ENOMEM, HDG_EHIP.  On error *out is NULL. */

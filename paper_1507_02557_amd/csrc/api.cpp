@@ -60,6 +60,7 @@ struct TypeData {
   int* elist = nullptr;        // elements sorted by level, finest first
   bool elist_identity = false; // the sorted order is the storage order (no indirection needed)
   int8_t* elevel = nullptr;    // level per element
+  int8_t* ehalf = nullptr;     // 1: a face neighbour is on a finer level (reads the mid-step traces)
   float* H = nullptr;          // right-hand-side history [3][4][K][Np]
   int64_t n_from[10] = {};     // number of elements with level >= l
 };
@@ -228,11 +229,26 @@ int build_tables(hdg_ctx* c, int t, std::vector<float>& ops, std::vector<int>& i
   return HDG_OK;
 }
 
+// BF16 rounding (nearest, ties to even) of a finite float, as its bits.
+uint16_t bf16_bits(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+double bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+
 // MFMA A-fragments of a row-major R x C matrix, appended to out: for each
 // 16-row tile t and k-step s (K = kk per instruction), piece pc and lane l,
 // the ki entries A[16t + l%16][kk s + ki (l/16) + i] (0 outside the matrix).
-// Precision 0 stores FP32 values; otherwise x = sc A is stored as two FP16
-// pieces hi = fp16(x), lo = fp16(x - hi).
+// Precision 0 stores FP32 values; otherwise x = sc A is stored as npc pieces,
+// each the FP16 (P = 1, 2) or BF16 (P = 3, 4) rounding of what the previous
+// pieces leave: hi = r(x), lo = r(x - hi) (and, three pieces, mid, lo).
 void pack_frags(const double* A, int R, int C, int P, double sc, std::vector<float>& out) {
   int kk, ki, npc;
   tet_mfma_frag_shape(P, &kk, &ki, &npc);
@@ -253,11 +269,18 @@ void pack_frags(const double* A, int R, int C, int P, double sc, std::vector<flo
       for (int pc = 0; pc < npc; ++pc)
         for (int l = 0; l < 64; ++l)
           for (int i = 0; i < ki; ++i) {
-            const double x = at(t, s, l, i) * sc;
-            const _Float16 hi = (_Float16)x;
-            const _Float16 v = pc == 0 ? hi : (_Float16)(x - (double)hi);
-            uint16_t bits;
-            std::memcpy(&bits, &v, 2);
+            double x = at(t, s, l, i) * sc;
+            uint16_t bits = 0;
+            for (int q = 0; q <= pc; ++q) {
+              if (P == 3 || P == 4) {
+                bits = bf16_bits((float)x);
+                x -= bf16_value(bits);
+              } else {
+                const _Float16 v = (_Float16)x;
+                std::memcpy(&bits, &v, 2);
+                x -= (double)v;
+              }
+            }
             h.push_back(bits);
           }
   const size_t o = out.size();
@@ -1035,7 +1058,8 @@ int hdg_create(hdg_ctx** out, const hdg_mesh* m, int N, int precision, void* hip
   if (!m || !m->xyz || !m->type || !m->verts || !m->kappa || !m->rho)
     return fail(nullptr, HDG_EINVAL, "mesh or one of its arrays is NULL");
   if (N < 1 || N > kMaxN) return fail(nullptr, HDG_EINVAL, "order N must be in [1, 5]");
-  if (precision != HDG_PREC_FP32 && precision != HDG_PREC_FP16X2 && precision != HDG_PREC_FP16X2_K16)
+  if (precision != HDG_PREC_FP32 && precision != HDG_PREC_FP16X2 && precision != HDG_PREC_FP16X2_K16 &&
+      precision != HDG_PREC_BF16X2 && precision != HDG_PREC_BF16X3)
     return fail(nullptr, HDG_EINVAL, "unsupported precision mode");
   if (m->n_elem < 1 || m->n_vert < 1) return fail(nullptr, HDG_EINVAL, "empty mesh");
   if (m->bc != HDG_BC_FREE_SURFACE && m->bc != HDG_BC_RIGID_WALL)
@@ -1229,6 +1253,7 @@ StageArgs mr_args(hdg_ctx* c, TypeData& d, int lmin, int k, int dense) {
   // is a prefix of the storage order and tiles move as contiguous blocks
   a.elist = d.elist_identity ? nullptr : d.elist;
   a.elevel = d.elevel;
+  a.ehalf = d.ehalf;
   a.slevel = c->slevel;
   a.H = d.H;
   a.tr_half = c->trace[1 - c->cur];
@@ -1346,12 +1371,21 @@ int hdg_mrab_setup(hdg_ctx* c, int n_levels, double cfl, double* dt_min_out, int
   if (!c->slevel && (rc = dalloc(c, &c->slevel, c->nslot))) return rc;
   HIPCHK(c, hipMemcpyAsync(c->slevel, slev.data(), c->nslot, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  // elements with a finer face neighbour (through a sub-face too) write
+  // mid-step traces
+  std::vector<int8_t> half(c->n_elem, 0);
+  for (size_t s = 0; s < c->nbr_h.size(); ++s) {
+    if (c->nbr_h[s] < 0) continue;
+    const int64_t a = c->slot_elem_h[s], b = c->slot_elem_h[c->nbr_h[s]];
+    if (lev[b] > lev[a]) half[a] = 1;
+  }
   std::vector<int64_t> cnt(L + 1, 0);
   for (int t = 0; t < 4; ++t) {
     TypeData& d = c->td[t];
     if (!d.present) continue;
     std::vector<int> order(d.K);
-    std::vector<int8_t> el(d.K);
+    std::vector<int8_t> el(d.K), hf(d.K);
+    for (int64_t k = 0; k < d.K; ++k) hf[k] = half[d.elems[k]];
     for (int64_t k = 0; k < d.K; ++k) {
       order[k] = (int)k;
       el[k] = (int8_t)lev[d.elems[k]];
@@ -1363,6 +1397,8 @@ int hdg_mrab_setup(hdg_ctx* c, int n_levels, double cfl, double* dt_min_out, int
       for (int l = 1; l <= el[k]; ++l) d.n_from[l]++;
     if (!d.elist && (rc = dalloc(c, &d.elist, d.K))) return rc;
     if (!d.elevel && (rc = dalloc(c, &d.elevel, d.K))) return rc;
+    if (!d.ehalf && (rc = dalloc(c, &d.ehalf, d.K))) return rc;
+    HIPCHK(c, hipMemcpyAsync(d.ehalf, hf.data(), d.K, hipMemcpyHostToDevice, c->stream));
     if (!d.H && (rc = dalloc(c, &d.H, (size_t)3 * 4 * d.K * d.Np))) return rc;
     HIPCHK(c, hipMemcpyAsync(d.elist, order.data(), d.K * sizeof(int), hipMemcpyHostToDevice, c->stream));
     d.elist_identity = true;

@@ -39,6 +39,7 @@ struct StageArgs {
   int64_t n_items;       // elements processed by this launch
   const int* elist;      // element of each item (NULL: item i is element i)
   const int8_t* elevel;  // level per element (multi-rate)
+  const int8_t* ehalf;   // 1: a face neighbour is finer, so the element's mid-step traces are read
   const int8_t* slevel;  // level of each slot's element [nslot] (multi-rate)
   float* H;              // right-hand-side history [3][4][K][Np] (multi-rate)
   float4* tr_half;       // mid-step traces [nslot][Nfq] (multi-rate)
@@ -212,7 +213,18 @@ struct MrabUpdate {
     }
   }
 
+  // mid-step traces are written only for batches holding an element whose
+  // finer neighbour reads them
+  HD static bool any_half(const StageArgs& a, int64_t e0) {
+    for (int el = 0; el < S::kEPB; ++el) {
+      const int64_t e = item(a, e0 + el);
+      if (e >= 0 && a.ehalf[e]) return true;
+    }
+    return false;
+  }
+
   HD static void step(int st, int tid, typename S::Smem& sm, const StageArgs& a, int64_t e0) {
+    if (st >= 2 + T && !any_half(a, e0)) return;
     StageArgs b = a;
     b.mode = kModeStage;
     if (st == 0) {

@@ -32,7 +32,8 @@ constexpr bool tet_fits() {
 // lane gets at 8 wavefronts per block)
 template <int N, int P>
 constexpr int tet_waves() {
-  return (tet_fits<N, P, 8>() && (P == 0 || N <= 2)) ? 8 : (tet_fits<N, P, 4>() ? 4 : 2);
+  return (tet_fits<N, P, 8>() && (P == 0 || N <= 2)) ? 8
+                                                        : (tet_fits<N, P, 4>() ? 4 : (tet_fits<N, P, 2>() ? 2 : 1));
 }
 template <int N, int P>
 using TetM = TetMfma<N, tet_waves<N, P>(), P>;
@@ -82,6 +83,8 @@ int launch_tet_mfma(int N, int P, const StageArgs& a, hipStream_t s, int max_blo
     case 0: return launch_p<0>(N, a, s, max_blocks);
     case 1: return launch_p<1>(N, a, s, max_blocks);
     case 2: return launch_p<2>(N, a, s, max_blocks);
+    case 3: return launch_p<3>(N, a, s, max_blocks);
+    case 4: return launch_p<4>(N, a, s, max_blocks);
   }
   return -1;
 }
@@ -97,16 +100,31 @@ static void sizes_p(int N, int* nf, int* ni) {
   }
 }
 
+template <int P>
+static void shape_p(int* kk, int* ki, int* npc) {
+  *kk = Prec<P>::KK;
+  *ki = Prec<P>::KI;
+  *npc = Prec<P>::NPC;
+}
+
 void tet_mfma_frag_shape(int P, int* kk, int* ki, int* npc) {
-  if (P == 1) { *kk = Prec<1>::KK; *ki = Prec<1>::KI; *npc = Prec<1>::NPC; }
-  else if (P == 2) { *kk = Prec<2>::KK; *ki = Prec<2>::KI; *npc = Prec<2>::NPC; }
-  else { *kk = Prec<0>::KK; *ki = Prec<0>::KI; *npc = Prec<0>::NPC; }
+  switch (P) {
+    case 1: shape_p<1>(kk, ki, npc); break;
+    case 2: shape_p<2>(kk, ki, npc); break;
+    case 3: shape_p<3>(kk, ki, npc); break;
+    case 4: shape_p<4>(kk, ki, npc); break;
+    default: shape_p<0>(kk, ki, npc); break;
+  }
 }
 
 void tet_mfma_table_sizes(int N, int P, int* nf, int* ni) {
-  if (P == 1) sizes_p<1>(N, nf, ni);
-  else if (P == 2) sizes_p<2>(N, nf, ni);
-  else sizes_p<0>(N, nf, ni);
+  switch (P) {
+    case 1: sizes_p<1>(N, nf, ni); break;
+    case 2: sizes_p<2>(N, nf, ni); break;
+    case 3: sizes_p<3>(N, nf, ni); break;
+    case 4: sizes_p<4>(N, nf, ni); break;
+    default: sizes_p<0>(N, nf, ni); break;
+  }
 }
 
 }  // namespace hdg

@@ -198,13 +198,13 @@ struct TetMfma {
   // face-node values of the tile's state, canonical lattice order
   template <class SM, class WV>
   __device__ static void write_traces(const SM& sm, const WV& W, const StageArgs& a, int64_t e0, int lane,
-                                      const FaceRec& rec, float4* tr) {
+                                      const FaceRec& rec, float4* tr, bool col_active = true) {
     const int n = lane & 15, g = lane >> 4;
     const int64_t e = item(a, e0 + n);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
       const int o = __shfl(rec.ori, n + 16 * f);
-      if (e < 0) continue;
+      if (e < 0 || !col_active) continue;
       const int64_t slot = a.slot0 + e * 4 + f;
 #pragma unroll
       for (int j = 0; j < JF; ++j) {
@@ -282,7 +282,8 @@ struct TetMfma {
         dd[c][j] = d1 - dh;
       }
     wave_sync();
-    write_traces(sm, W, a, e0, lane, rec, a.tr_half);
+    // mid-step traces of the elements whose finer neighbours read them
+    write_traces(sm, W, a, e0, lane, rec, a.tr_half, e >= 0 && a.ehalf[e]);
     wave_sync();
 #pragma unroll
     for (int c = 0; c < 4; ++c)
@@ -314,9 +315,9 @@ struct TetMfma {
       update_tile(sm, W, a, t * 16, lane);
   }
 
-  // acc += L_f F (one field) with split FP16 operands and a column scale.
-  __device__ static void lift_f16(const Smem& sm, const Wave& W, int f, int n, int g, int lane,
-                                  const float (*Fc)[SF], f32x4 (&acc)[Mt]) {
+  // acc += L_f F (one field) with split operands and a column scale.
+  __device__ static void lift_split(const Smem& sm, const Wave& W, int f, int n, int g, int lane,
+                                    const float (*Fc)[SF], f32x4 (&acc)[Mt]) {
     float mf = 0.f;
 #pragma unroll
     for (int j = 0; j < JF; ++j) {
@@ -335,14 +336,14 @@ struct TetMfma {
         const int k = KK * s + KI * g + i;
         v[i] = k < Nfn ? Fc[n][k < Nfn ? k : 0] : 0.f;
       }
-      V bh, bl;
-      split_f16<V, KI>(v, sf, bh, bl);
+      V b[NPC];
+      split_pieces<PR>(v, sf, b);
 #pragma unroll
       for (int t = 0; t < Mt; ++t) {
-        const V ah = sm.L[f][t][s][0][lane], al = sm.L[f][t][s][1][lane];
-        tmp[t] = mma_f16(ah, bh, tmp[t]);
-        tmp[t] = mma_f16(ah, bl, tmp[t]);
-        tmp[t] = mma_f16(al, bh, tmp[t]);
+        V a[NPC];
+#pragma unroll
+        for (int q = 0; q < NPC; ++q) a[q] = sm.L[f][t][s][q][lane];
+        tmp[t] = mma_split<PR>(a, b, tmp[t]);
       }
     }
     const float gs = sm.inv_sL / sf;
@@ -397,10 +398,10 @@ struct TetMfma {
         }
       }
     } else {
-      lift_f16(sm, W, f, n, g, lane, W.F[0], accP);
-      lift_f16(sm, W, f, n, g, lane, W.F[1], accL[0]);
-      lift_f16(sm, W, f, n, g, lane, W.F[2], accL[1]);
-      lift_f16(sm, W, f, n, g, lane, W.F[3], accL[2]);
+      lift_split(sm, W, f, n, g, lane, W.F[0], accP);
+      lift_split(sm, W, f, n, g, lane, W.F[1], accL[0]);
+      lift_split(sm, W, f, n, g, lane, W.F[2], accL[1]);
+      lift_split(sm, W, f, n, g, lane, W.F[3], accL[2]);
     }
     wave_sync();
   }
@@ -542,21 +543,19 @@ struct TetMfma {
 #pragma unroll
           for (int r = 0; r < 3; ++r) uv[r][i] = in ? -(G[3 * r] * u1 + G[3 * r + 1] * u2 + G[3 * r + 2] * u3) : 0.f;
         }
-        V ph, pl, uh[3], ul[3];
-        split_f16<V, KI>(pv, sp, ph, pl);
+        V pb[NPC], ub[3][NPC];
+        split_pieces<PR>(pv, sp, pb);
 #pragma unroll
-        for (int r = 0; r < 3; ++r) split_f16<V, KI>(uv[r], su, uh[r], ul[r]);
+        for (int r = 0; r < 3; ++r) split_pieces<PR>(uv[r], su, ub[r]);
 #pragma unroll
         for (int t = 0; t < Mt; ++t)
 #pragma unroll
           for (int r = 0; r < 3; ++r) {
-            const V ah = sm.D[r][t][s][0][lane], al = sm.D[r][t][s][1][lane];
-            accG[r][t] = mma_f16(ah, ph, accG[r][t]);
-            accG[r][t] = mma_f16(ah, pl, accG[r][t]);
-            accG[r][t] = mma_f16(al, ph, accG[r][t]);
-            accP[t] = mma_f16(ah, uh[r], accP[t]);
-            accP[t] = mma_f16(ah, ul[r], accP[t]);
-            accP[t] = mma_f16(al, uh[r], accP[t]);
+            V a[NPC];
+#pragma unroll
+            for (int q = 0; q < NPC; ++q) a[q] = sm.D[r][t][s][q][lane];
+            accG[r][t] = mma_split<PR>(a, pb, accG[r][t]);
+            accP[t] = mma_split<PR>(a, ub[r], accP[t]);
           }
       }
       const float gp = sm.inv_sD / sp, gu = sm.inv_sD / su;

@@ -15,7 +15,7 @@ import torch
 
 HEX, WEDGE, PYR, TET = 0, 1, 2, 3
 BC_FREE_SURFACE, BC_RIGID_WALL = 0, 1
-PREC_FP32, PREC_FP16X2, PREC_FP16X2_K16 = 0, 1, 2
+PREC_FP32, PREC_FP16X2, PREC_FP16X2_K16, PREC_BF16X2, PREC_BF16X3 = 0, 1, 2, 3, 4
 PATH_AUTO, PATH_GENERIC = 0, 1
 STEPPER_LSERK4, STEPPER_MRAB3 = 0, 1
 PROJECT_SCRATCH_BYTES = 16 * 1024 * 1024  # HDG_PROJECT_SCRATCH_BYTES
