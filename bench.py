@@ -198,11 +198,13 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}))
 
 
-PREC_NAMES = {0: "fp32", 1: "fp16x2", 2: "fp16x2-k16"}
+PREC_NAMES = {0: "fp32", 1: "fp16x2", 2: "fp16x2-k16", 3: "bf16x2", 4: "bf16x3"}
 PREC_DESC = {
     0: "FP32 operands, FP32 accumulation (16x16x4 MFMA)",
     1: "split FP16 operands (hi + lo, power-of-two scales), FP32 accumulation, 16x16x32 MFMA",
     2: "split FP16 operands (hi + lo, power-of-two scales), FP32 accumulation, 16x16x16 MFMA",
+    3: "split BF16 operands (hi + lo, 3 products), FP32 accumulation, 16x16x32 BF16 MFMA",
+    4: "three-piece BF16 operands (hi + mid + lo, 6 products), FP32 accumulation, 16x16x32 BF16 MFMA",
 }
 TYPE_NAMES = ((0, "hex"), (1, "wedge"), (2, "pyr"), (3, "tet"))
 
@@ -459,7 +461,7 @@ def main():
     ap.add_argument("--n", type=int, default=48)
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--levels", type=int, default=3)
-    ap.add_argument("--precisions", default="0,1,2", help="precision codes to run (0 FP32 always runs)")
+    ap.add_argument("--precisions", default="0,1,3,4", help="precision codes to run (0 FP32 always runs)")
     ap.add_argument("--cpu-n", type=int, default=12)
     ap.add_argument("--cpu-stages", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")

@@ -127,7 +127,7 @@ def test_refined_mrab_matches_oracle(refined_mesh):
     assert rel < 1e-5
 
 
-@pytest.mark.parametrize("prec", [hdg.PREC_FP16X2, hdg.PREC_FP16X2_K16])
+@pytest.mark.parametrize("prec", [hdg.PREC_FP16X2, hdg.PREC_FP16X2_K16, hdg.PREC_BF16X3])
 def test_refined_split_precision_rhs(refined_mesh, prec):
     N = 4
     d = Disc(refined_mesh, N)

@@ -64,7 +64,7 @@ def test_create_rejects_unsupported_order(N):
     assert rc == -1 and not h.value and "order" in msg
 
 
-@pytest.mark.parametrize("precision", [-1, 3, 7])
+@pytest.mark.parametrize("precision", [-1, 5, 7])
 def test_create_rejects_unknown_precision(precision):
     rc, h, msg = _create(_tets([[0, 1, 2, 3]], XYZ), precision=precision)
     assert rc == -1 and not h.value and "precision" in msg
