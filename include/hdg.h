@@ -99,7 +99,16 @@ typedef struct hdg_ctx hdg_ctx;
  *     pyramid: (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1) apex (-1,-1,1)
  *     tet:     (-1,-1,-1) (1,-1,-1) (-1,1,-1) (-1,-1,1)
  *   kappa,rho [n_elem]    bulk modulus and density (> 0)
- *   bc                    boundary condition on every boundary face
+ *   bc                    boundary condition on every boundary face (the
+ *                         mirror states of Section 2.2's flux: free surface
+ *                         p = 0, rigid wall u . n = 0)
+ *   bc_face   [6*n_elem]  optional per element and local face (the face order
+ *                         of the element's type: hex (r=-1, r=1, s=-1, s=1,
+ *                         t=-1, t=1), wedge (s=-1, s=1, t=-1, r=-1, r+t=0),
+ *                         pyramid (base, r=-1, s=-1, r+t=0, s+t=0), tet
+ *                         (t=-1, s=-1, r+s+t=-1, r=-1)): -1 uses bc, 0 / 1
+ *                         choose the condition of that face when it lies on
+ *                         the boundary; may be NULL
  *   n_hanging, hanging    [3*n_hanging] rows (v, a, b): vertex v is the
  *                         midpoint of the edge (a, b) (may be 0 / NULL).
  * 1:4 non-conforming faces (an extension: the paper's meshes are
@@ -121,6 +130,7 @@ typedef struct hdg_mesh {
   const double* kappa;
   const double* rho;
   int32_t bc;
+  const int8_t* bc_face;
   int64_t n_hanging;
   const int64_t* hanging;
 } hdg_mesh;
@@ -131,8 +141,9 @@ typedef struct hdg_mesh {
  * hip_stream (a hipStream_t, may be NULL for the null stream); the call
  * synchronises that stream before returning.  precision: one of the
  * HDG_PREC_* codes above (else HDG_EINVAL).
- * Errors: HDG_EINVAL (N out of range, bad type id, NULL pointer),
- * HDG_EMESH (non-positive Jacobian, a face shared by more than two elements),
+ * Errors: HDG_EINVAL (N out of range, bad type id, NULL pointer, a bc_face
+ * entry other than -1, 0, 1), HDG_EMESH (non-positive Jacobian, a face shared
+ * by more than two elements, a malformed non-conforming face),
  * HDG_ENOMEM, HDG_EHIP.  On error *out is NULL. */
 int hdg_create(hdg_ctx** out, const hdg_mesh* m, int N, int precision, void* hip_stream);
 

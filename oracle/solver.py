@@ -83,6 +83,13 @@ class Disc:
         slot_elem, slot_face, nbr = OM.match_faces(types, mesh.everts, self.refs)
         self.nslot = slot_elem.shape[0]
         self.slot_elem, self.slot_face, self.nbr = slot_elem, slot_face, nbr
+        # boundary condition per face slot: the mesh's per-face choice where it
+        # makes one (bc_face[element, local face] >= 0), else bc
+        self.slot_bc = np.full(self.nslot, bc, dtype=np.int64)
+        bcf = getattr(mesh, "bc_face", None)
+        if bcf is not None:
+            v = np.asarray(bcf, dtype=np.int64)[slot_elem, slot_face]
+            self.slot_bc = np.where(v >= 0, v, bc)
         first = np.zeros(types.shape[0] + 1, dtype=np.int64)
         nfaces = np.array([self.refs[t].nfaces if t in self.refs else 0 for t in range(4)])
         first[1:] = np.cumsum(nfaces[types])
@@ -201,6 +208,7 @@ class Disc:
         self.fx, self.Js, self.Js_ref = ext(self.fx), ext(self.Js), ext(self.Js_ref)
         self.nrm, self.wq, self.fJ = ext(self.nrm), ext(self.wq), ext(self.fJ, 1.0)
         self.is_parent = ext(self.is_parent, False)
+        self.slot_bc = ext(self.slot_bc, self.bc)
         eta, _ = self.face_rule[3]
         S, _ = R.face_shape(3, eta)
         local = {}
@@ -274,16 +282,16 @@ class Disc:
         inner = self.nbr >= 0
         nb[inner] = TR[self.nbr[inner]]
         n = self.nrm
-        bnd = ~inner
-        pm, um = own[bnd, :, 0], own[bnd, :, 1:]
-        nbn = n[bnd]
-        if self.bc == BC_RIGID_WALL:
-            un = np.einsum("kqd,kqd->kq", um, nbn)
-            nb[bnd, :, 0] = pm
-            nb[bnd, :, 1:] = um - 2.0 * un[:, :, None] * nbn
-        else:
-            nb[bnd, :, 0] = -pm
-            nb[bnd, :, 1:] = um
+        # boundary mirror states: rigid wall p+ = p-, u+ = u- - 2 (n.u-) n;
+        # free surface p+ = -p-, u+ = u-
+        rig = ~inner & (self.slot_bc == BC_RIGID_WALL)
+        fre = ~inner & (self.slot_bc != BC_RIGID_WALL)
+        pm, um = own[rig, :, 0], own[rig, :, 1:]
+        un = np.einsum("kqd,kqd->kq", um, n[rig])
+        nb[rig, :, 0] = pm
+        nb[rig, :, 1:] = um - 2.0 * un[:, :, None] * n[rig]
+        nb[fre, :, 0] = -own[fre, :, 0]
+        nb[fre, :, 1:] = own[fre, :, 1:]
         rc_own = self.rhoc[self.slot_elem]
         rc_nb = rc_own.copy()
         rc_nb[inner] = self.rhoc[self.slot_elem[self.nbr[inner]]]

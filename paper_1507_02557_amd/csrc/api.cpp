@@ -820,7 +820,21 @@ int create_impl(hdg_ctx* c, const hdg_mesh* m, int N) {
   std::vector<int64_t> order(ns);
   std::iota(order.begin(), order.end(), 0);
   std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return keys[x] < keys[y]; });
+  // boundary faces: -(1 + bc), bc per face where the mesh gives one
   std::vector<int> nbr(ns, -1 - m->bc);
+  if (m->bc_face) {
+    for (int t = 0; t < 4; ++t) {
+      const TypeData& d = c->td[t];
+      const int nf = elem_desc(t).nf;
+      for (int64_t k = 0; k < d.K; ++k)
+        for (int f = 0; f < nf; ++f) {
+          const int b = m->bc_face[6 * d.elems[k] + f];
+          if (b != -1 && b != HDG_BC_FREE_SURFACE && b != HDG_BC_RIGID_WALL)
+            return fail(c, HDG_EINVAL, "element " + std::to_string(d.elems[k]) + " has a bad face boundary condition");
+          if (b >= 0) nbr[d.slot0 + k * nf + f] = -1 - b;
+        }
+    }
+  }
   for (int64_t i = 0; i < ns;) {
     int64_t j = i + 1;
     while (j < ns && keys[order[j]] == keys[order[i]]) ++j;

@@ -17,7 +17,7 @@ __global__ __launch_bounds__(S::NT) void tet_mfma_kernel(StageArgs a) {
 
 // multi-rate AB3 update of the tetrahedra (kModeMrab)
 template <class S>
-__global__ __launch_bounds__(64 * S::NWU) void tet_mrab_update_kernel(StageArgs a) {
+__global__ __launch_bounds__(64 * S::NWU, S::kUpdateWaves) void tet_mrab_update_kernel(StageArgs a) {
   __shared__ typename S::USmem sm;
   S::run_update(sm, a);
 }

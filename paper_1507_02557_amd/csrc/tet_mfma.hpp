@@ -196,9 +196,9 @@ struct TetMfma {
   }
 
   // face-node values of the tile's state, canonical lattice order
-  template <class SM, class WV>
-  __device__ static void write_traces(const SM& sm, const WV& W, const StageArgs& a, int64_t e0, int lane,
-                                      const FaceRec& rec, float4* tr, bool col_active = true) {
+  template <class SM>
+  __device__ static void write_traces(const SM& sm, const float (&X)[4][16][SX], const StageArgs& a, int64_t e0,
+                                      int lane, const FaceRec& rec, float4* tr, bool col_active = true) {
     const int n = lane & 15, g = lane >> 4;
     const int64_t e = item(a, e0 + n);
 #pragma unroll
@@ -211,7 +211,7 @@ struct TetMfma {
         const int m = g + 4 * j;
         if (m >= Nfn) continue;
         const int node = sm.fnode[f][sm.tperm[o][m]];
-        tr[slot * Nfq + m] = make_float4(W.X[0][n][node], W.X[1][n][node], W.X[2][n][node], W.X[3][n][node]);
+        tr[slot * Nfq + m] = make_float4(X[0][n][node], X[1][n][node], X[2][n][node], X[3][n][node]);
       }
     }
   }
@@ -225,9 +225,12 @@ struct TetMfma {
   // u_new - u_half stays in registers; the mid-step traces are written, then
   // the tile becomes u_new, which is stored with its traces.
   static constexpr int NWU = 4;  // wavefronts per block of the update kernel
+  // wavefronts per SIMD the update kernel's register allocation must allow
+  static constexpr int kUpdateWaves = N <= 4 ? 3 : 2;
   static constexpr int JN = (16 * Np + 63) / 64;  // flat tile entries per lane
   struct alignas(16) UWave {
-    float X[4][16][SX];
+    float X[4][16][SX];  // state tile (u_half in the one-level path)
+    float Y[4][16][SX];  // u_new in the one-level path
   };
   struct USmem {
     MrabParams mr;  // per-level weights and history slots (indexed by the element's level)
@@ -239,13 +242,52 @@ struct TetMfma {
   __device__ static void update_tile(const USmem& sm, UWave& W, const StageArgs& a, int64_t e0, int lane) {
     const int64_t K = a.K;
     const int64_t hstr = 4 * K * Np;
+    const int64_t fs = K * Np;
     const int n = lane & 15, g = lane >> 4;
     const int64_t e = item(a, e0 + n);
     const bool contig = contiguous(a, e0);
     wave_sync();
-    const FaceRec rec = load_rec(a, e, g);
+    // only the orientation codes of the face records are needed here
+    FaceRec rec{-1, 0, 0, make_float4(0.f, 0.f, 0.f, 0.f), make_float2(0.f, 0.f)};
+    if (e >= 0) rec.ori = a.ori[a.slot0 + e * 4 + g];
+    const bool half = e >= 0 && a.ehalf[e];
+    const MrabParams& mr = sm.mr;
+    // a tile of consecutive elements of one level (the common case with the
+    // elements stored finest level first) moves as flat float4 vectors
+    const int lv0 = contig ? a.elevel[e0] : 0;
+    if (contig && a.elevel[e0 + 15] == lv0) {
+      const float dl = mr.dtl[lv0];
+      const float w1[3] = {dl * mr.b1[lv0][0], dl * mr.b1[lv0][1], dl * mr.b1[lv0][2]};
+      const float wh[3] = {dl * mr.bh[lv0][0], dl * mr.bh[lv0][1], dl * mr.bh[lv0][2]};
+      const float* h0 = a.H + mr.hs[lv0][0] * hstr;
+      const float* h1 = a.H + mr.hs[lv0][1] * hstr;
+      const float* h2 = a.H + mr.hs[lv0][2] * hstr;
+#pragma unroll 1
+      for (int c = 0; c < 4; ++c) {
+        float4 u[JQ], x0[JQ], x1[JQ], x2[JQ], un[JQ], uh[JQ];
+        load_field(u, a.U + c * fs, e0, lane);
+        load_field(x0, h0 + c * fs, e0, lane);
+        load_field(x1, h1 + c * fs, e0, lane);
+        load_field(x2, h2 + c * fs, e0, lane);
+#pragma unroll
+        for (int j = 0; j < JQ; ++j) {
+          un[j] = u[j] + w1[0] * x0[j] + w1[1] * x1[j] + w1[2] * x2[j];
+          uh[j] = u[j] + wh[0] * x0[j] + wh[1] * x1[j] + wh[2] * x2[j];
+        }
+        float4* U4 = reinterpret_cast<float4*>(a.U + c * fs + e0 * Np);
+#pragma unroll
+        for (int j = 0; j < JQ; ++j)
+          if (lane + 64 * j < Q4) U4[lane + 64 * j] = un[j];
+        put_field<SX>(W.X[c], uh, lane);
+        put_field<SX>(W.Y[c], un, lane);
+      }
+      wave_sync();
+      // mid-step traces of the elements whose finer neighbours read them
+      write_traces(sm, W.X, a, e0, lane, rec, a.tr_half, half);
+      write_traces(sm, W.Y, a, e0, lane, rec, a.tr_out);
+      return;
+    }
     if (contig) {
-      const int64_t fs = K * Np;
       float4 v0[JQ], v1[JQ], v2[JQ], v3[JQ];
       load_field(v0, a.U, e0, lane);
       load_field(v1, a.U + fs, e0, lane);
@@ -271,19 +313,17 @@ struct TetMfma {
         const int64_t ee = item(a, e0 + nn);
         if (ee < 0) continue;
         const int lv = a.elevel[ee];
-        const MrabParams& mr = sm.mr;
         const int64_t gi = (int64_t)c * K * Np + ee * Np + k;
-        const float h0 = a.H[mr.hs[lv][0] * hstr + gi], h1 = a.H[mr.hs[lv][1] * hstr + gi],
-                    h2 = a.H[mr.hs[lv][2] * hstr + gi];
+        const float x0 = a.H[mr.hs[lv][0] * hstr + gi], x1 = a.H[mr.hs[lv][1] * hstr + gi],
+                    x2 = a.H[mr.hs[lv][2] * hstr + gi];
         const float dl = mr.dtl[lv];
-        const float d1 = dl * (mr.b1[lv][0] * h0 + mr.b1[lv][1] * h1 + mr.b1[lv][2] * h2);
-        const float dh = dl * (mr.bh[lv][0] * h0 + mr.bh[lv][1] * h1 + mr.bh[lv][2] * h2);
+        const float d1 = dl * (mr.b1[lv][0] * x0 + mr.b1[lv][1] * x1 + mr.b1[lv][2] * x2);
+        const float dh = dl * (mr.bh[lv][0] * x0 + mr.bh[lv][1] * x1 + mr.bh[lv][2] * x2);
         W.X[c][nn][k] += dh;
         dd[c][j] = d1 - dh;
       }
     wave_sync();
-    // mid-step traces of the elements whose finer neighbours read them
-    write_traces(sm, W, a, e0, lane, rec, a.tr_half, e >= 0 && a.ehalf[e]);
+    write_traces(sm, W.X, a, e0, lane, rec, a.tr_half, half);
     wave_sync();
 #pragma unroll
     for (int c = 0; c < 4; ++c)
@@ -297,7 +337,7 @@ struct TetMfma {
     wave_sync();
 #pragma unroll
     for (int c = 0; c < 4; ++c) store_tile<SX>(a.U + (int64_t)c * K * Np, W.X[c], a, e0, lane, contig);
-    write_traces(sm, W, a, e0, lane, rec, a.tr_out);
+    write_traces(sm, W.X, a, e0, lane, rec, a.tr_out);
   }
 
   __device__ static void run_update(USmem& sm, const StageArgs& a) {
@@ -484,7 +524,7 @@ struct TetMfma {
     }
     wave_sync();
     if (a.mode == kModeTrace) {
-      write_traces(sm, W, a, e0, lane, rec, a.tr_out);
+      write_traces(sm, W.X, a, e0, lane, rec, a.tr_out);
       return;
     }
     const float iJ = G[9];
@@ -612,7 +652,7 @@ struct TetMfma {
     emit<1>(W, a, e0, lane, contig, rv1, accL[0], irho);
     emit<2>(W, a, e0, lane, contig, rv2, accL[1], irho);
     emit<3>(W, a, e0, lane, contig, rv3, accL[2], irho);
-    if (stage) write_traces(sm, W, a, e0, lane, rec, a.tr_out);
+    if (stage) write_traces(sm, W.X, a, e0, lane, rec, a.tr_out);
   }
 
   __device__ static void run(Smem& sm, const StageArgs& a) {

@@ -61,7 +61,7 @@ EXPORTS = [s[0] for s in _SIGS]
 
 class HdgMesh(ctypes.Structure):
     _fields_ = [("n_vert", ctypes.c_int64), ("xyz", _P), ("n_elem", ctypes.c_int64), ("type", _P),
-                ("verts", _P), ("kappa", _P), ("rho", _P), ("bc", ctypes.c_int32),
+                ("verts", _P), ("kappa", _P), ("rho", _P), ("bc", ctypes.c_int32), ("bc_face", _P),
                 ("n_hanging", ctypes.c_int64), ("hanging", _P)]
 
 
@@ -115,8 +115,11 @@ class Solver:
         ka = np.ascontiguousarray(mesh.kappa, dtype=np.float64)
         rh = np.ascontiguousarray(mesh.rho, dtype=np.float64)
         hg = np.ascontiguousarray(getattr(mesh, "hanging", np.zeros((0, 3))), dtype=np.int64).reshape(-1, 3)
+        bf = getattr(mesh, "bc_face", None)
+        bf = None if bf is None else np.ascontiguousarray(bf, dtype=np.int8).reshape(et.shape[0], 6)
         m = HdgMesh(xyz.shape[0], xyz.ctypes.data, et.shape[0], et.ctypes.data, ev.ctypes.data,
-                    ka.ctypes.data, rh.ctypes.data, bc, hg.shape[0], hg.ctypes.data if hg.shape[0] else None)
+                    ka.ctypes.data, rh.ctypes.data, bc, None if bf is None else bf.ctypes.data,
+                    hg.shape[0], hg.ctypes.data if hg.shape[0] else None)
         h = _P()
         rc = self._lib.hdg_create(ctypes.byref(h), ctypes.byref(m), N, precision, self._stream())
         if rc != 0:

@@ -92,6 +92,10 @@ class Mesh:
     n: int = 0
     info: dict = field(default_factory=dict)
     hanging: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), dtype=np.int64))
+    # optional boundary condition per element and local face ([n_elem, 6],
+    # -1: the solver's default, else 0 free surface / 1 rigid wall); only
+    # boundary faces use it
+    bc_face: np.ndarray | None = None
 
     @property
     def n_elem(self) -> int:
@@ -106,7 +110,8 @@ class Mesh:
         if order.shape != (self.n_elem,) or not np.array_equal(np.sort(order), np.arange(self.n_elem)):
             raise ValueError("order must be a permutation of the elements")
         return Mesh(xyz=self.xyz, etype=self.etype[order], everts=self.everts[order], kappa=self.kappa[order],
-                    rho=self.rho[order], n=self.n, info=dict(self.info), hanging=self.hanging)
+                    rho=self.rho[order], n=self.n, info=dict(self.info), hanging=self.hanging,
+                    bc_face=None if self.bc_face is None else np.asarray(self.bc_face)[order])
 
     def level_order(self, level) -> np.ndarray:
         """Element order that stores every type's elements finest level first

@@ -78,6 +78,25 @@ def test_rhs_free_surface_and_materials(path):
 
 
 @pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("N", [2, 4])
+def test_rhs_per_face_boundary_conditions(N, path):
+    """Free-surface and rigid-wall faces mixed at random on the boundary
+    (per element and local face), random materials."""
+    m = four_slab_mesh(4, seed=3, jitter=0.1)
+    rng = np.random.default_rng(9)
+    m.kappa = rng.uniform(0.5, 2.0, m.n_elem)
+    m.rho = rng.uniform(0.5, 2.0, m.n_elem)
+    m.bc_face = rng.integers(-1, 2, size=(m.n_elem, 6)).astype(np.int8)
+    d = Disc(m, N, bc=BC_FREE_SURFACE)
+    s = hdg.Solver(m, N, bc=hdg.BC_FREE_SURFACE, path=path)
+    U = random_state(d, seed=30 + N)
+    set_lib_state(s, U)
+    Rl = {t: v.double().cpu().numpy() for t, v in s.rhs().items()}
+    err = type_rel_err(Rl, d.rhs(U))
+    assert max(err.values()) < TOL_RHS, err
+
+
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("slabs,n", [(("hex",), 1), (("tet",), 1), (("pyr6",), 2), (("wedge",), 2), (("pyrtet",), 2)])
 def test_single_type_meshes(slabs, n, path):
     """Single-element and single-type meshes (all faces on the boundary for n=1)."""

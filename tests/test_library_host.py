@@ -39,8 +39,11 @@ def _create(mesh, N=2, bc=1, precision=0, hanging=None):
     ka = np.ascontiguousarray(mesh.kappa, dtype=np.float64)
     rh = np.ascontiguousarray(mesh.rho, dtype=np.float64)
     hg = np.ascontiguousarray(np.zeros((0, 3)) if hanging is None else hanging, dtype=np.int64).reshape(-1, 3)
+    bf = getattr(mesh, "bc_face", None)
+    bf = None if bf is None else np.ascontiguousarray(bf, dtype=np.int8)
     m = hdg.HdgMesh(xyz.shape[0], xyz.ctypes.data, et.shape[0], et.ctypes.data, ev.ctypes.data,
-                    ka.ctypes.data, rh.ctypes.data, bc, hg.shape[0], hg.ctypes.data if hg.shape[0] else None)
+                    ka.ctypes.data, rh.ctypes.data, bc, None if bf is None else bf.ctypes.data,
+                    hg.shape[0], hg.ctypes.data if hg.shape[0] else None)
     h = ctypes.c_void_p()
     rc = lib.hdg_create(ctypes.byref(h), ctypes.byref(m), N, precision, None)
     return rc, h, lib.hdg_last_error(None).decode()
@@ -88,6 +91,14 @@ def test_create_rejects_bad_material_and_bc():
     assert rc == -1 and "rho" in msg
     rc, _, msg = _create(_tets([[0, 1, 2, 3]], XYZ), bc=7)
     assert rc == -1 and "boundary" in msg
+
+
+def test_create_rejects_bad_face_boundary_condition():
+    m = _tets([[0, 1, 2, 3]], XYZ)
+    m.bc_face = np.full((1, 6), -1, dtype=np.int8)
+    m.bc_face[0, 2] = 3
+    rc, h, msg = _create(m)
+    assert rc == hdg.EINVAL and not h.value and "boundary condition" in msg
 
 
 def test_binding_fails_loudly_without_a_gpu():

@@ -267,6 +267,43 @@ def test_energy_identity(bc, jitter):
     assert abs(lhs - (e_int + e_bnd)) < 1e-11 * abs(e_int + e_bnd)
 
 
+def test_energy_identity_with_per_face_boundary_conditions():
+    """Free-surface and rigid-wall faces mixed at random on one boundary: the
+    identity holds with each boundary face's own mirror term (rigid: the
+    normal velocity, free: the pressure), so a face given the wrong mirror
+    state breaks it."""
+    m = four_slab_mesh(4, seed=3, jitter=0.1)
+    rng = np.random.default_rng(8)
+    m.kappa = rng.uniform(0.5, 2.0, m.n_elem)
+    m.rho = rng.uniform(0.5, 2.0, m.n_elem)
+    m.bc_face = rng.integers(-1, 2, size=(m.n_elem, 6)).astype(np.int8)
+    d = Disc(m, 2, bc=BC_FREE_SURFACE)
+    bnd = d.nbr < 0
+    assert np.any(bnd & (d.slot_bc == BC_RIGID_WALL)) and np.any(bnd & (d.slot_bc == BC_FREE_SURFACE))
+    U = {t: rng.standard_normal(d.zeros()[t].shape) for t in d.types}
+    Rr = d.rhs(U)
+    lhs = 0.0
+    for t in d.types:
+        MR = d.mass_apply(t, Rr[t])
+        lhs += float(np.sum(U[t][:, 0] * MR[:, 0] / d.kappa[d.els[t]][:, None]))
+        lhs += float(np.sum(d.rho[d.els[t]][:, None, None] * U[t][:, 1:] * MR[:, 1:]))
+    TR = d.traces(U)
+    inner = ~bnd
+    nb = TR[np.maximum(d.nbr, 0)]
+    rc_o = d.rhoc[d.slot_elem]
+    rc_n = np.where(inner, d.rhoc[d.slot_elem[np.maximum(d.nbr, 0)]], rc_o)
+    avg = 0.5 * (rc_o + rc_n)
+    jp = nb[..., 0] - TR[..., 0]
+    un_o = np.einsum("kqd,kqd->kq", TR[..., 1:], d.nrm)
+    un_n = np.einsum("kqd,kqd->kq", nb[..., 1:], d.nrm)
+    w = d.wq * d.Js
+    e_int = -0.25 * np.sum((w * (jp ** 2 / avg[:, None] + avg[:, None] * (un_n - un_o) ** 2))[inner])
+    rig = bnd & (d.slot_bc == BC_RIGID_WALL)
+    fre = bnd & (d.slot_bc == BC_FREE_SURFACE)
+    e_bnd = -np.sum((w * avg[:, None] * un_o ** 2)[rig]) - np.sum((w * TR[..., 0] ** 2 / avg[:, None])[fre])
+    assert abs(lhs - (e_int + e_bnd)) < 1e-11 * abs(e_int + e_bnd)
+
+
 def test_constant_state_is_steady():
     """p = const, u = 0 with rigid walls gives dU/dt = 0 (affine mesh)."""
     d = Disc(four_slab_mesh(4, seed=0, jitter=0.0), 3)
