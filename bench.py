@@ -253,19 +253,51 @@ def fp64_check(hdg, N: int, precision: int):
             "steps": f"start-up + {int(g['coarse_steps'])} coarse steps, t={float(g['t']):.4e}"}
 
 
-def run_refined(args, hdg, torch, np):
-    from paper_1507_02557_amd.inputs import four_slab_mesh, gaussian_pulse, pulse_centre
+def refined_workload(args, hdg):
+    """The refined four-slab mesh with every type's elements stored finest
+    level first (levels do not depend on the element order), and the levels."""
+    from paper_1507_02557_amd.inputs import four_slab_mesh
 
-    N, L = args.order, args.levels
     mesh0 = four_slab_mesh(args.n, seed=0, jitter=0.1, refine_last=2)
-    # store every type's elements finest level first (levels do not depend on
-    # the element order)
-    s0 = hdg.Solver(mesh0, N)
-    _, cnt0, lev0 = s0.mrab_setup(L)
+    s0 = hdg.Solver(mesh0, args.order)
+    _, _, lev0 = s0.mrab_setup(args.levels)
     s0.close()
     order = mesh0.level_order(lev0)
-    mesh = mesh0.permuted(order)
-    lev = lev0[order]
+    return mesh0.permuted(order), lev0[order]
+
+
+def kernels_only(args, hdg, torch, np):
+    """The refined workload's kernels and nothing else (for profiler runs):
+    set-up, start-up, `warmup` + `steps` coarse steps at the first precision
+    given.  Two runs with different `steps` give per-coarse-step counter
+    totals by difference."""
+    from paper_1507_02557_amd.inputs import gaussian_pulse, pulse_centre
+
+    mesh, lev = refined_workload(args, hdg)
+    c = pulse_centre(0)
+    p = int(args.precisions.split(",")[0])
+    s = hdg.Solver(mesh, args.order, precision=p)
+    s.project_function(lambda x, y, z, t: gaussian_pulse(x, y, z, c))
+    s.mrab_setup(args.levels)
+    s.mrab_advance(0)
+    s.mrab_advance(args.warmup + args.steps)
+    torch.cuda.synchronize()
+    N, L = args.order, args.levels
+    act = {name: sum(int(np.sum((mesh.etype == t) & (lev == l))) * (2 ** (l - 1)) for l in range(1, L + 1))
+           for t, name in TYPE_NAMES}
+    print(json.dumps({"kernels_only": True, "coarse_steps": args.warmup + args.steps, "precision": PREC_NAMES[p],
+                      "active_elements_per_coarse_step": act,
+                      "alg_bytes_per_element": {f"{k}_{name}": mrab_alg_bytes(ki, t, N, True)
+                                                for ki, k in ((0, "rhs"), (1, "update")) for t, name in TYPE_NAMES},
+                      "energy": s.energy()}))
+    s.close()
+
+
+def run_refined(args, hdg, torch, np):
+    from paper_1507_02557_amd.inputs import gaussian_pulse, pulse_centre
+
+    N, L = args.order, args.levels
+    mesh, lev = refined_workload(args, hdg)
     c = pulse_centre(0)
     precs = [int(p) for p in args.precisions.split(",")]
     if 0 not in precs:
@@ -467,6 +499,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="refined workload: only set-up, start-up and warmup + steps coarse steps (profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}))
@@ -480,6 +514,9 @@ def main():
 
     from paper_1507_02557_amd import hdg
 
+    if args.kernels_only:
+        kernels_only(args, hdg, torch, np)
+        return
     if args.workload == "refined":
         out = run_refined(args, hdg, torch, np)
     else:
