@@ -96,20 +96,34 @@ def tet_alg_bytes(N: int, lattice: bool) -> int:
     return alg_bytes(3, N, lattice)
 
 
-def mrab_alg_bytes(kind: int, t: int, N: int, lattice: bool) -> int:
+def mrab_alg_bytes(kind: int, t: int, N: int, lattice: bool, mid: bool = True) -> int:
     """Algorithmic HBM bytes per active element of one multi-rate kernel.
 
     kind 0, right-hand side into the history: read U and write one history
     slot (32 B per node), read the neighbours' traces (16 B per trace point),
     geometry, material, face records as in alg_bytes.
     kind 1, AB3 update: read U and three history slots, write U (80 B per
-    node), write the synchronised and the mid-step traces (32 B per trace
-    point), orientation codes (1 B per face).
+    node), write the synchronised traces (16 B per trace point) and, for an
+    element with a finer face neighbour (mid=True), the mid-step traces that
+    neighbour reads (16 B per trace point), orientation codes (1 B per face).
     """
     np_, tp, nf = _np_of(t, N), _trace_points(t, N, lattice), _faces(t)
     if kind == 0:
         return 32 * np_ + 16 * tp + _geometry_bytes(t) + 8 + 13 * nf
-    return 80 * np_ + 32 * tp + nf
+    return 80 * np_ + 16 * tp + (16 * tp if mid else 0) + nf
+
+
+def mrab_step_bytes(kind: int, t: int, N: int, lattice: bool, info) -> int:
+    """Algorithmic bytes of one (kind, type) kernel over a coarse step: level l
+    is active 2^(l-1) times; `info` is Solver.mrab_level_info (elements and
+    mid-step trace writers per type and level)."""
+    L = info.shape[1]
+    w = [2 ** l for l in range(L)]
+    act = sum(int(info[t, l, 0]) * w[l] for l in range(L))
+    if kind == 0:
+        return mrab_alg_bytes(0, t, N, lattice) * act
+    writers = sum(int(info[t, l, 1]) * w[l] for l in range(L))
+    return mrab_alg_bytes(1, t, N, lattice, mid=False) * act + 16 * _trace_points(t, N, lattice) * writers
 
 
 def mortar_alg_bytes(N: int, dense: bool) -> int:
@@ -122,23 +136,25 @@ def mortar_alg_bytes(N: int, dense: bool) -> int:
 
 
 def csrc_hash() -> str:
-    """sha256 (first 16 hex) over the library's native sources, in name order."""
+    """sha256 (first 16 hex) over the library's device sources (.hip, .hpp),
+    in name order: the key of the committed traffic counters."""
     import hashlib
 
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1507_02557_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+        if f.endswith((".hip", ".hpp")):
             h.update(f.encode())
             with open(os.path.join(d, f), "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_name: str, also: str = ""):
-    """HBM bytes per launch of a kernel from the committed rocprofv3 --pmc
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings),
-    or None when the sources have changed since the counters were taken."""
+def measured_traffic(kernel_name: str, also: str = "", section: str = "bytes_per_launch"):
+    """HBM bytes of a kernel from the committed rocprofv3 --pmc summaries
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings): per launch
+    for the single-rate stage kernels, per coarse step for the multi-rate
+    kernels; None when the sources have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -146,10 +162,19 @@ def measured_traffic(kernel_name: str, also: str = ""):
         data = json.load(fh)
     if data.get("source_hash") != csrc_hash():
         return None
-    for name, b in data.get("bytes_per_launch", {}).items():
+    for name, b in data.get(section, {}).items():
         if kernel_name in name and also in name:
             return float(b)
     return None
+
+
+# multi-rate kernels of the refined workload at N = 4, FP32, by (kind, type, N)
+MRAB_KERNELS = {
+    (0, 0, 4): "stage_kernel<hdg::HexStage<4, 4> >", (1, 0, 4): "mrab_update_kernel<hdg::HexStage<4, 4> >",
+    (0, 1, 4): "stage_kernel<hdg::WedgeStage<4, 2> >", (1, 1, 4): "mrab_update_kernel<hdg::WedgeStage<4, 2> >",
+    (0, 2, 4): "stage_kernel<hdg::PyrStage<4, 4> >", (1, 2, 4): "mrab_update_kernel<hdg::PyrStage<4, 4> >",
+    (0, 3, 4): "tet_mfma_kernel<hdg::TetMfma<4, 8, 0> >", (1, 3, 4): "tet_mrab_update_kernel<hdg::TetMfma<4, 8, 0> >",
+}
 
 
 def cpu_baseline(n: int, N: int, stages: int, refined: bool):
@@ -283,12 +308,12 @@ def kernels_only(args, hdg, torch, np):
     s.mrab_advance(args.warmup + args.steps)
     torch.cuda.synchronize()
     N, L = args.order, args.levels
-    act = {name: sum(int(np.sum((mesh.etype == t) & (lev == l))) * (2 ** (l - 1)) for l in range(1, L + 1))
-           for t, name in TYPE_NAMES}
+    info = s.mrab_level_info(L)
+    act = {name: sum(int(info[t, l, 0]) * 2 ** l for l in range(L)) for t, name in TYPE_NAMES}
     print(json.dumps({"kernels_only": True, "coarse_steps": args.warmup + args.steps, "precision": PREC_NAMES[p],
                       "active_elements_per_coarse_step": act,
-                      "alg_bytes_per_element": {f"{k}_{name}": mrab_alg_bytes(ki, t, N, True)
-                                                for ki, k in ((0, "rhs"), (1, "update")) for t, name in TYPE_NAMES},
+                      "alg_bytes_per_coarse_step": {f"{k}_{name}": mrab_step_bytes(ki, t, N, True, info)
+                                                    for ki, k in ((0, "rhs"), (1, "update")) for t, name in TYPE_NAMES},
                       "energy": s.energy()}))
     s.close()
 
@@ -364,8 +389,8 @@ def run_refined(args, hdg, torch, np):
 
     # roofline of each (kind, type) kernel: algorithmic bytes of all its
     # launches in a coarse step over its event-timed duration
-    counts = {t: [int(np.sum((mesh.etype == t) & (lev == l))) for l in range(1, L + 1)] for t, _ in TYPE_NAMES}
-    act = {t: sum(counts[t][l - 1] * (2 ** (l - 1)) for l in range(1, L + 1)) for t, _ in TYPE_NAMES}
+    info = s.mrab_level_info(L)
+    act = {t: sum(int(info[t, l, 0]) * 2 ** l for l in range(L)) for t, _ in TYPE_NAMES}
     n_nc = int(mesh.hanging.shape[0] > 0) * 2 * args.n * args.n
     roof = {}
     for kind, kname in ((0, "rhs"), (1, "update")):
@@ -373,19 +398,24 @@ def run_refined(args, hdg, torch, np):
             if not kcnt[kind][t]:
                 continue
             ms_k = float(kms[kind][t]) / prof_steps
-            b = mrab_alg_bytes(kind, t, N, lattice) * act[t]
+            b = mrab_step_bytes(kind, t, N, lattice, info)
             ach = b / (ms_k * 1e-3) / 1e9
+            tr = measured_traffic(MRAB_KERNELS[(kind, t, N)], section="bytes_per_coarse_step") \
+                if (kind, t, N) in MRAB_KERNELS else None
             roof[f"{kname}_{name}"] = {
                 "bound": "hbm", "ms_per_coarse_step": round(ms_k, 4), "launches_per_coarse_step": int(kcnt[kind][t]) // prof_steps,
                 "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": None, "alg_bytes_per_element": mrab_alg_bytes(kind, t, N, lattice),
+                "traffic": None if tr is None else int(tr), "alg_bytes_per_coarse_step": int(b),
                 "active_elements_per_coarse_step": act[t]}
     if kcnt[2][3]:
         ms_k = float(kms[2][3]) / prof_steps
         b = mortar_alg_bytes(N, True) * n_nc * nsub
         roof["interface_tet"] = {"bound": "hbm", "ms_per_coarse_step": round(ms_k, 4),
                                  "achieved": round(b / (ms_k * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                 "frac": round(b / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                                 "frac": round(b / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "traffic": (lambda v: None if v is None else int(v))(
+                                     measured_traffic("mortar_kernel", section="bytes_per_coarse_step")
+                                     if N == 4 else None),
                                  "alg_bytes_per_face": mortar_alg_bytes(N, True), "faces": n_nc}
     dominant = max(roof, key=lambda k: roof[k]["ms_per_coarse_step"])
     s.close()

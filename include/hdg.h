@@ -247,6 +247,15 @@ int hdg_mrab_setup(hdg_ctx* ctx, int n_levels, double cfl, double* dt_min_out, i
  * Errors: HDG_ESTATE if hdg_mrab_setup was not called. */
 int hdg_mrab_advance(hdg_ctx* ctx, int64_t n_coarse, double* t_advanced);
 
+/* Level census of the multi-rate set-up (Section 2.4), for cost accounting:
+ * out (host, int64 [4][L][2], L = n_levels of the last hdg_mrab_setup) receives
+ * per element type t and level l = 1..L the number of elements, at
+ * out[(t L + l - 1) 2], and the number of those that have a face neighbour
+ * (across a sub-face too) on a finer level and so write the mid-step traces
+ * that neighbour reads, at out[(t L + l - 1) 2 + 1].  Errors: HDG_EINVAL
+ * (NULL), HDG_ESTATE (hdg_mrab_setup not called). */
+int hdg_mrab_level_info(const hdg_ctx* ctx, int64_t* out);
+
 /* Energy E = 1/2 sum_K (p^T M p / kappa + rho u^T M u) of the current state
  * (Section 3.1: the quantity eq. sym shows the upwind flux cannot increase),
  * with the element mass matrices of Section 2.1, accumulated in FP64 on the

@@ -110,6 +110,7 @@ struct hdg_ctx {
   double time = 0.0;           // simulated time of the state
   double mr_dtmin0 = 0.0;      // dtau_min of hdg_mrab_setup (hdg_advance may scale it down)
   std::vector<int8_t> level_h; // multi-rate level per element (mesh order)
+  std::vector<int8_t> half_h;  // 1: the element writes mid-step traces (mesh order)
   double* pscratch = nullptr;  // fixed work buffer of hdg_project_noalloc on this context's GPU
   // 1:4 non-conforming faces: slots [nslot0, nslot0 + 4 n_nc) are the
   // virtual slots (the coarse trace at a sub-face, read by the fine
@@ -1393,6 +1394,7 @@ int hdg_mrab_setup(hdg_ctx* c, int n_levels, double cfl, double* dt_min_out, int
     const int64_t a = c->slot_elem_h[s], b = c->slot_elem_h[c->nbr_h[s]];
     if (lev[b] > lev[a]) half[a] = 1;
   }
+  c->half_h = half;
   std::vector<int64_t> cnt(L + 1, 0);
   for (int t = 0; t < 4; ++t) {
     TypeData& d = c->td[t];
@@ -1427,6 +1429,24 @@ int hdg_mrab_setup(hdg_ctx* c, int n_levels, double cfl, double* dt_min_out, int
   if (level_out)
     for (int64_t e = 0; e < c->n_elem; ++e) level_out[e] = (int8_t)lev[e];
   c->mr_ready = false;
+  return HDG_OK;
+}
+
+int hdg_mrab_level_info(const hdg_ctx* c, int64_t* out) {
+  if (!c || !out) return HDG_EINVAL;
+  if (c->level_h.empty() || c->half_h.size() != c->level_h.size()) return HDG_ESTATE;
+  const int L = c->L;
+  for (int i = 0; i < 4 * L * 2; ++i) out[i] = 0;
+  for (int t = 0; t < 4; ++t) {
+    const TypeData& d = c->td[t];
+    if (!d.present) continue;
+    for (int64_t k = 0; k < d.K; ++k) {
+      const int64_t e = d.elems[k];
+      const int l = c->level_h[e];
+      out[(t * L + l - 1) * 2] += 1;
+      out[(t * L + l - 1) * 2 + 1] += c->half_h[e];
+    }
+  }
   return HDG_OK;
 }
 

@@ -51,6 +51,7 @@ _SIGS = [
     ("hdg_checkpoint_load", ctypes.c_int, [_P, _P, ctypes.c_int64]),
     ("hdg_mrab_setup", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _P, _P]),
     ("hdg_mrab_advance", ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
+    ("hdg_mrab_level_info", ctypes.c_int, [_P, _P]),
     ("hdg_profile", ctypes.c_int, [_P, ctypes.c_int]),
     ("hdg_profile_read", ctypes.c_int, [_P, _P, _P]),
     ("hdg_set_path", ctypes.c_int, [_P, ctypes.c_int]),
@@ -251,6 +252,13 @@ class Solver:
         self._check(self._lib.hdg_mrab_setup(self._h, n_levels, cfl, ctypes.byref(mn), cnt.ctypes.data,
                                              lev.ctypes.data))
         return mn.value, cnt, lev
+
+    def mrab_level_info(self, n_levels: int):
+        """(4, n_levels, 2) int64: per type and level, the element count and the
+        number of those that write mid-step traces."""
+        out = np.zeros((4, n_levels, 2), dtype=np.int64)
+        self._check(self._lib.hdg_mrab_level_info(self._h, out.ctypes.data))
+        return out
 
     def mrab_advance(self, n_coarse: int) -> float:
         t = ctypes.c_double()

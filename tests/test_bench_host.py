@@ -61,8 +61,24 @@ def test_multirate_bytes_split_the_stage_traffic(N):
         nf = quads + tris
         assert bench.mrab_alg_bytes(0, t, N, True) == 32 * _nodes(t, N) + 16 * pts + geometry[t] + 8 + 13 * nf
         assert bench.mrab_alg_bytes(1, t, N, True) == 80 * _nodes(t, N) + 32 * pts + nf
+        assert bench.mrab_alg_bytes(1, t, N, True, mid=False) == 80 * _nodes(t, N) + 16 * pts + nf
     nfn = (N + 1) * (N + 2) // 2
     assert bench.mortar_alg_bytes(N, False) == 16 * nfn * 10 + 40
+
+
+def test_coarse_step_bytes_weight_levels_and_mid_step_writers():
+    """Level l is active 2^(l-1) times per coarse step; only the elements that
+    write mid-step traces pay their 16 B per trace point."""
+    import numpy as np
+
+    info = np.zeros((4, 3, 2), dtype=np.int64)
+    info[3] = [[5, 1], [7, 0], [11, 3]]          # tets per level, writers
+    act = 5 + 2 * 7 + 4 * 11
+    writers = 1 + 0 + 4 * 3
+    tp = 4 * 15
+    assert bench.mrab_step_bytes(0, 3, 4, True, info) == act * bench.mrab_alg_bytes(0, 3, 4, True)
+    assert bench.mrab_step_bytes(1, 3, 4, True, info) == act * (80 * 35 + 16 * tp + 4) + writers * 16 * tp
+    assert bench.mrab_step_bytes(1, 0, 4, True, info) == 0
 
 
 def test_source_hash_is_stable_and_keys_the_traffic_file():
@@ -75,7 +91,8 @@ def test_source_hash_is_stable_and_keys_the_traffic_file():
     assert len(data["source_hash"]) == 16
     assert data["fetch_scale"] > 0 and data["write_scale"] > 0
     if data["source_hash"] == h:
-        assert bench.measured_traffic("TetMfma<4, ", ", 0>") is not None
+        for name in bench.MRAB_KERNELS.values():
+            assert bench.measured_traffic(name, section="bytes_per_coarse_step") > 0, name
 
 
 def test_more_than_one_gpu_is_refused():

@@ -58,6 +58,19 @@ def test_refined_dt_and_levels_match_oracle(refined_mesh):
         g[d.els[t]] = mr.level[t]
     assert np.array_equal(g, lev.astype(np.int64))
     assert abs(dtmin - mr.dtmin) < 1e-12 * dtmin
+    # level census: elements per type and level, and those with a face
+    # neighbour (across a sub-face too) on a finer level
+    writer = np.zeros(refined_mesh.n_elem, dtype=bool)
+    inner = d.nbr >= 0
+    a, b = d.slot_elem[inner], d.slot_elem[d.nbr[inner]]
+    writer[a[g[b] > g[a]]] = True
+    info = s.mrab_level_info(3)
+    for t in range(4):
+        for l in range(1, 4):
+            on = (refined_mesh.etype == t) & (g == l)
+            assert info[t, l - 1, 0] == np.sum(on), (t, l)
+            assert info[t, l - 1, 1] == np.sum(on & writer), (t, l)
+    assert info[3, :, 1].sum() > 0
 
 
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 5])

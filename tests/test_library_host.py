@@ -123,6 +123,7 @@ def test_calls_on_a_null_context_are_rejected():
     assert lib.hdg_checkpoint_load(None, buf, 64) == hdg.EINVAL
     assert lib.hdg_project_noalloc(None, 0, None, None, None, None) == hdg.EINVAL
     assert lib.hdg_project(None, 0, None, None, None, None) == hdg.EINVAL
+    assert lib.hdg_mrab_level_info(None, buf) == hdg.EINVAL
 
 
 def test_header_scratch_size_matches_binding():
