@@ -70,10 +70,10 @@ extern "C" {
  *   HDG_PREC_FP16X2_K16    the same split on 16x16x16 MFMA
  *   HDG_PREC_BF16X2        split BF16 operands x = hi + lo (about 16
  *                          significant bits), hi*hi + hi*lo + lo*hi in FP32
- *                          (16x16x32 BF16 MFMA)
+ *                          (16x16x16 BF16 MFMA)
  *   HDG_PREC_BF16X3        three-piece BF16 split x = hi + mid + lo (about 24
  *                          bits), the six products with piece orders summing
- *                          to at most 2, in FP32 (16x16x32 BF16 MFMA)
+ *                          to at most 2, in FP32 (16x16x16 BF16 MFMA)
  * State, geometry (computed in FP64), fluxes and updates are FP32 in all
  * modes. */
 #define HDG_PREC_FP32 0

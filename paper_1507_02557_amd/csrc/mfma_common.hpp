@@ -9,7 +9,8 @@ namespace hdg {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
 
 // D = A B + C for 16x16 tiles, K = 4: lane l passes A[l%16][l/16] and
 // B[l/16][l%16] and holds D[4(l/16)+i][l%16] in component i.
@@ -26,9 +27,12 @@ __device__ __forceinline__ f32x4 mma_f16(f16x4 a, f16x4 b, f32x4 c) {
 __device__ __forceinline__ f32x4 mma_f16(f16x8 a, f16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
-// BF16 operands, FP32 accumulation, 16x16x32 (lane layout of the FP16 one).
-__device__ __forceinline__ f32x4 mma_f16(bf16x8 a, bf16x8 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+// BF16 operands, FP32 accumulation, 16x16x16 (lane layout of the FP16
+// 16x16x16 one; the instruction takes the BF16 bit patterns as 16-bit
+// integers).
+__device__ __forceinline__ f32x4 mma_f16(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, a), __builtin_bit_cast(s16x4, b), c, 0,
+                                                   0, 0);
 }
 
 // Operand precision of the element-batched operator products.
@@ -38,10 +42,10 @@ __device__ __forceinline__ f32x4 mma_f16(bf16x8 a, bf16x8 b, f32x4 c) {
 //      each operand carries about 22 significant bits; A B is formed as
 //      hi hi + hi lo + lo hi with FP32 accumulation.
 //   2: the same split with 16x16x16 instructions (less padding of K).
-//   3: split BF16, 16x16x32: x = hi + lo, hi = bf16(x), lo = bf16(x - hi)
+//   3: split BF16, 16x16x16: x = hi + lo, hi = bf16(x), lo = bf16(x - hi)
 //      (about 16 significant bits; BF16 keeps FP32's exponent range), A B as
 //      hi hi + hi lo + lo hi.
-//   4: three-piece BF16, 16x16x32: x = hi + mid + lo, each the BF16 rounding
+//   4: three-piece BF16, 16x16x16: x = hi + mid + lo, each the BF16 rounding
 //      of what the previous pieces leave (about 24 significant bits), A B as
 //      the six products whose piece orders add up to at most 2:
 //      hi hi + hi mid + mid hi + hi lo + lo hi + mid mid.
@@ -66,14 +70,14 @@ struct Prec<2> {
 };
 template <>
 struct Prec<3> {
-  static constexpr int KI = 8, KK = 32, NPC = 2;
-  typedef bf16x8 V;
+  static constexpr int KI = 4, KK = 16, NPC = 2;
+  typedef bf16x4 V;
   typedef __bf16 E;
 };
 template <>
 struct Prec<4> {
-  static constexpr int KI = 8, KK = 32, NPC = 3;
-  typedef bf16x8 V;
+  static constexpr int KI = 4, KK = 16, NPC = 3;
+  typedef bf16x4 V;
   typedef __bf16 E;
 };
 

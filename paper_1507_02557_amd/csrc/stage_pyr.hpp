@@ -17,12 +17,12 @@
 
 namespace hdg {
 
-template <int N, int EPB>
+template <int N, int EPB, int NTH = 256>
 struct PyrStage {
   static constexpr int Np = (N + 1) * (N + 2) * (2 * N + 3) / 6;
   static constexpr int Nfn = (N + 1) * (N + 2) / 2;
   static constexpr int Nfq = (N + 1) * (N + 1);
-  static constexpr int NT = 256;
+  static constexpr int NT = NTH;
   static constexpr int kEPB = EPB;
   static constexpr int nphase = 7;
   static constexpr int kTraceBegin = 5;  // first phase that writes traces

@@ -101,7 +101,7 @@ static int launch_n(int type, const StageArgs& a, hipStream_t s, bool mrab) {
   switch (type) {
     case 0: return go<HexStage<N, epb(0, N)>>(a, s, mrab);
     case 1: return go<WedgeStage<N, epb(1, N)>>(a, s, mrab);
-    case 2: return go<PyrStage<N, epb(2, N)>>(a, s, mrab);
+    case 2: return go<PyrStage<N, epb(2, N), pyr_threads(N)>>(a, s, mrab);
     case 3: return go<TetStage<N, epb(3, N)>>(a, s, mrab);
   }
   return -1;
@@ -112,7 +112,7 @@ static void sizes_n(int type, int* nf, int* ni) {
   switch (type) {
     case 0: sizes<HexStage<N, epb(0, N)>>(nf, ni); break;
     case 1: sizes<WedgeStage<N, epb(1, N)>>(nf, ni); break;
-    case 2: sizes<PyrStage<N, epb(2, N)>>(nf, ni); break;
+    case 2: sizes<PyrStage<N, epb(2, N), pyr_threads(N)>>(nf, ni); break;
     default: sizes<TetStage<N, epb(3, N)>>(nf, ni); break;
   }
 }

@@ -24,19 +24,20 @@ __global__ __launch_bounds__(64 * S::NWU, S::kUpdateWaves) void tet_mrab_update_
 
 // wavefronts per block: as many as fit the LDS (operator fragments are held
 // once per block)
-template <int N, int P, int NW>
+template <int N, int P, int NW, bool ST>
 constexpr bool tet_fits() {
-  return sizeof(typename TetMfma<N, NW, P>::Smem) <= 160 * 1024;
+  return sizeof(typename TetMfma<N, NW, P, ST>::Smem) <= 160 * 1024;
 }
-// (split-precision kernels above N = 2 need more than the 256 registers a
-// lane gets at 8 wavefronts per block)
-template <int N, int P>
+// (split-precision stage kernels above N = 2 need more than the 256
+// registers a lane gets at 8 wavefronts per block)
+template <int N, int P, bool ST>
 constexpr int tet_waves() {
-  return (tet_fits<N, P, 8>() && (P == 0 || N <= 2)) ? 8
-                                                        : (tet_fits<N, P, 4>() ? 4 : (tet_fits<N, P, 2>() ? 2 : 1));
+  return (tet_fits<N, P, 8, ST>() && (P == 0 || N <= 2 || !ST))
+             ? 8
+             : (tet_fits<N, P, 4, ST>() ? 4 : (tet_fits<N, P, 2, ST>() ? 2 : 1));
 }
-template <int N, int P>
-using TetM = TetMfma<N, tet_waves<N, P>(), P>;
+template <int N, int P, bool ST = true>
+using TetM = TetMfma<N, tet_waves<N, P, ST>(), P, ST>;
 
 template <class S>
 static int go_mfma(const StageArgs& a, hipStream_t s, int max_blocks) {
@@ -65,14 +66,20 @@ static int go_mfma(const StageArgs& a, hipStream_t s, int max_blocks) {
   return 0;
 }
 
+template <int N, int P>
+static int go_n(const StageArgs& a, hipStream_t s, int max_blocks) {
+  if (a.mode == kModeRhs || a.mode == kModeRhsHist) return go_mfma<TetM<N, P, false>>(a, s, max_blocks);
+  return go_mfma<TetM<N, P>>(a, s, max_blocks);
+}
+
 template <int P>
 static int launch_p(int N, const StageArgs& a, hipStream_t s, int max_blocks) {
   switch (N) {
-    case 1: return go_mfma<TetM<1, P>>(a, s, max_blocks);
-    case 2: return go_mfma<TetM<2, P>>(a, s, max_blocks);
-    case 3: return go_mfma<TetM<3, P>>(a, s, max_blocks);
-    case 4: return go_mfma<TetM<4, P>>(a, s, max_blocks);
-    case 5: return go_mfma<TetM<5, P>>(a, s, max_blocks);
+    case 1: return go_n<1, P>(a, s, max_blocks);
+    case 2: return go_n<2, P>(a, s, max_blocks);
+    case 3: return go_n<3, P>(a, s, max_blocks);
+    case 4: return go_n<4, P>(a, s, max_blocks);
+    case 5: return go_n<5, P>(a, s, max_blocks);
   }
   return -1;
 }

@@ -31,7 +31,9 @@
 
 namespace hdg {
 
-template <int N, int NW, int P>
+// ST = false: a kernel for the right-hand-side modes only (no residual
+// registers, no stage update).
+template <int N, int NW, int P, bool ST = true>
 struct TetMfma {
   typedef Prec<P> PR;
   typedef typename PR::V V;
@@ -253,7 +255,9 @@ struct TetMfma {
     const bool half = e >= 0 && a.ehalf[e];
     const MrabParams& mr = sm.mr;
     // a tile of consecutive elements of one level (the common case with the
-    // elements stored finest level first) moves as flat float4 vectors
+    // elements stored finest level first) moves as flat float4 vectors;
+    // without an item list the storage is in that order, so equal levels at
+    // both ends of the tile mean one level throughout
     const int lv0 = contig ? a.elevel[e0] : 0;
     if (contig && a.elevel[e0 + 15] == lv0) {
       const float dl = mr.dtl[lv0];
@@ -448,12 +452,14 @@ struct TetMfma {
 
   // Output of field C: rhs = sc * acc at rows 16 t + 4 g + i of column n,
   // then the stage update (res = a res + dt rhs, u += b res) or the rhs store.
+  // hist: the history slot of a tile of consecutive elements of one level
+  // (multi-rate right-hand side), else null
   template <int C>
   __device__ static void emit(Wave& W, const StageArgs& a, int64_t e0, int lane, bool contig, const float4 (&rv)[JQ],
-                              const f32x4 (&acc)[Mt], float sc) {
+                              const f32x4 (&acc)[Mt], float sc, float* hist) {
     const int64_t K = a.K;
     const int n = lane & 15, g = lane >> 4;
-    const bool stage = a.mode == kModeStage;
+    const bool stage = ST && a.mode == kModeStage;
     float(*RB)[SX] = reinterpret_cast<float(*)[SX]>(&W.F[0][0][0]);
     if (stage) {
       if (contig) {
@@ -479,7 +485,9 @@ struct TetMfma {
         }
       }
     wave_sync();
-    if (a.mode == kModeRhsHist) {
+    if (hist) {
+      store_tile<SX>(hist + (int64_t)C * K * Np, RB, a, e0, lane, true);
+    } else if (a.mode == kModeRhsHist) {
       for (int it = lane; it < 16 * Np; it += 64) {
         const int nn = it / Np, k = it - nn * Np;
         const int64_t ee = item(a, e0 + nn);
@@ -612,7 +620,7 @@ struct TetMfma {
     for (int t = 0; t < Mt; ++t)
 #pragma unroll
       for (int d = 0; d < 3; ++d) accL[d][t] = -(G[d] * accG[0][t] + G[3 + d] * accG[1][t] + G[6 + d] * accG[2][t]);
-    const bool stage = a.mode == kModeStage;
+    const bool stage = ST && a.mode == kModeStage;
     float4 rv0[JQ], rv1[JQ], rv2[JQ], rv3[JQ];
     // faces: flux at the lattice nodes, then the lift products
     if constexpr (P == 0) {
@@ -648,10 +656,17 @@ struct TetMfma {
       }
     }
     // rhs at rows 16 t + 4 g + i of column n; stage update or rhs output
-    emit<0>(W, a, e0, lane, contig, rv0, accP, kap);
-    emit<1>(W, a, e0, lane, contig, rv1, accL[0], irho);
-    emit<2>(W, a, e0, lane, contig, rv2, accL[1], irho);
-    emit<3>(W, a, e0, lane, contig, rv3, accL[2], irho);
+    // (a multi-rate launch without an item list has its elements stored
+    // finest level first, so equal levels at both ends mean one level)
+    float* hist = nullptr;
+    if (a.mode == kModeRhsHist && contig) {
+      const int lv = a.elevel[e0];
+      if (a.elevel[e0 + 15] == lv) hist = a.H + (int64_t)a.mr.hs[lv][0] * 4 * K * Np;
+    }
+    emit<0>(W, a, e0, lane, contig, rv0, accP, kap, hist);
+    emit<1>(W, a, e0, lane, contig, rv1, accL[0], irho, hist);
+    emit<2>(W, a, e0, lane, contig, rv2, accL[1], irho, hist);
+    emit<3>(W, a, e0, lane, contig, rv3, accL[2], irho, hist);
     if (stage) write_traces(sm, W.X, a, e0, lane, rec, a.tr_out);
   }
 
