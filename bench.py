@@ -172,7 +172,8 @@ def measured_traffic(kernel_name: str, also: str = "", section: str = "bytes_per
 MRAB_KERNELS = {
     (0, 0, 4): "stage_kernel<hdg::HexStage<4, 4> >", (1, 0, 4): "mrab_update_kernel<hdg::HexStage<4, 4> >",
     (0, 1, 4): "stage_kernel<hdg::WedgeStage<4, 2> >", (1, 1, 4): "mrab_update_kernel<hdg::WedgeStage<4, 2> >",
-    (0, 2, 4): "stage_kernel<hdg::PyrStage<4, 16, 1024> >", (1, 2, 4): "mrab_update_kernel<hdg::PyrStage<4, 16, 1024> >",
+    (0, 2, 4): "wave_stage_kernel<hdg::PyrStage<4, 1, 64>, 12>",
+    (1, 2, 4): "wave_mrab_update_kernel<hdg::PyrStage<4, 1, 64>, 12>",
     (0, 3, 4): "tet_mfma_kernel<hdg::TetMfma<4, 8, 0, false> >",
     (1, 3, 4): "tet_mrab_update_kernel<hdg::TetMfma<4, 8, 0, true> >",
 }
@@ -210,6 +211,27 @@ def cpu_baseline(n: int, N: int, stages: int, refined: bool):
                       f"{el:.1f} s on {os.cpu_count()} visible host cores"}
 
 
+def copy_bandwidth(torch, mib: int = 1024, reps: int = 10) -> float:
+    """GB/s (read + written bytes) of a plain device-to-device copy of `mib`
+    MiB, HIP-event timed over `reps` copies: what a streaming kernel reaches
+    on this device, the practical ceiling beside the 8 TB/s peak."""
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    return round(gbs, 1)
+
+
 def copy_calibration(mib: int):
     """One plain device-to-device copy of known size: under rocprofv3 --pmc its
     FETCH_SIZE / WRITE_SIZE give the counter scale for HBM traffic."""
@@ -229,8 +251,8 @@ PREC_DESC = {
     0: "FP32 operands, FP32 accumulation (16x16x4 MFMA)",
     1: "split FP16 operands (hi + lo, power-of-two scales), FP32 accumulation, 16x16x32 MFMA",
     2: "split FP16 operands (hi + lo, power-of-two scales), FP32 accumulation, 16x16x16 MFMA",
-    3: "split BF16 operands (hi + lo, 3 products), FP32 accumulation, 16x16x32 BF16 MFMA",
-    4: "three-piece BF16 operands (hi + mid + lo, 6 products), FP32 accumulation, 16x16x32 BF16 MFMA",
+    3: "split BF16 operands (hi + lo, 3 products), FP32 accumulation, 16x16x16 BF16 MFMA",
+    4: "three-piece BF16 operands (hi + mid + lo, 6 products), FP32 accumulation, 16x16x16 BF16 MFMA",
 }
 TYPE_NAMES = ((0, "hex"), (1, "wedge"), (2, "pyr"), (3, "tet"))
 
@@ -454,6 +476,7 @@ def run_refined(args, hdg, torch, np):
             "substeps_per_coarse_step": nsub,
             "precisions": {PREC_NAMES[p]: results[p] for p in precs},
             "roofline_by_kernel": roof,
+            "copy_gbs": copy_bandwidth(torch),
         },
         "roofline": dict(roof[dominant], kernel=dominant),
     }

@@ -125,15 +125,6 @@ __device__ __forceinline__ f32x4 mma_split(const typename PR::V (&a)[PR::NPC], c
   return acc;
 }
 
-// LDS writes of this wavefront become visible to its later LDS reads (LDS
-// operations of one wavefront complete in order; this stops the compiler
-// from moving memory operations across the point).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Neighbour state on a lattice face at canonical lattice node m (boundary:
 // mirror of the own state).  A coarser neighbour that is mid-step supplies
 // its dense-output trace.

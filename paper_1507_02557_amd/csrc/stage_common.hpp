@@ -74,6 +74,15 @@ enum { kModeStage = 0, kModeTrace = 1, kModeRhs = 2, kModeRhsHist = 3, kModeMrab
 // neighbour trace.  Boundary codes -(1 + bc) stay above -kNcBase.
 constexpr int kNcBase = 16;
 
+// LDS writes of this wavefront become visible to its later LDS reads (LDS
+// operations of one wavefront complete in order; this stops the compiler
+// from moving memory operations across the point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Element processed by item i, or -1 past the end of the launch.
 HD inline int64_t item(const StageArgs& a, int64_t i) {
   if (i >= a.n_items) return -1;
@@ -193,8 +202,10 @@ struct MrabUpdate {
   static constexpr int T = S::nphase - S::kTraceBegin;
   static constexpr int nstep = 3 + 2 * T;
 
-  HD static void combine(int tid, typename S::Smem& sm, const StageArgs& a, int64_t e0, bool half) {
+  template <class SM>
+  HD static void combine(int tid, SM& smem, const StageArgs& a, int64_t e0, bool half) {
     constexpr int EPB = S::kEPB, Np = S::Np;
+    auto& sm = S::batch(smem);
     const int64_t K = a.K;
     const int64_t hstr = 4 * K * Np;
     for (int it = tid; it < 4 * EPB * Np; it += S::NT) {
@@ -223,7 +234,8 @@ struct MrabUpdate {
     return false;
   }
 
-  HD static void step(int st, int tid, typename S::Smem& sm, const StageArgs& a, int64_t e0) {
+  template <class SM>
+  HD static void step(int st, int tid, SM& sm, const StageArgs& a, int64_t e0) {
     if (st >= 2 + T && !any_half(a, e0)) return;
     StageArgs b = a;
     b.mode = kModeStage;

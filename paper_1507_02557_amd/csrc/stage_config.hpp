@@ -10,14 +10,13 @@ namespace hdg {
 constexpr int epb(int type, int N) {
   if (type == 0) return N <= 2 ? 16 : (N <= 3 ? 8 : 4);
   if (type == 1) return N <= 3 ? 8 : 2;
-  if (type == 2) return N <= 2 ? 8 : (N <= 4 ? 16 : 2);
+  if (type == 2) return 2;  // N = 5 (N <= 4: the wavefront-batched kernels)
   return N == 1 ? 32 : (N == 2 ? 16 : (N == 3 ? 12 : (N == 4 ? 8 : 4)));
 }
 
-// Threads per block of the vector pyramid kernel: one block per compute unit
-// holds the operator tables once, so the batch and the block grow together
-// (16 elements: 16 wavefronts per compute unit at N = 4; 8 at N = 3, whose
-// stage kernel needs more than the 128 registers a lane gets at 16).
-constexpr int pyr_threads(int N) { return N == 4 ? 1024 : (N == 3 ? 512 : 256); }
+// Wavefronts per block of the wavefront-batched pyramid kernels (N <= 4): the
+// tables plus one element's data per wavefront fit the LDS, and each
+// wavefront's registers fit without spilling (N = 3 needs more than 168).
+constexpr int pyr_waves(int N) { return N == 4 ? 12 : (N == 3 ? 8 : 16); }
 
 }  // namespace hdg

@@ -45,6 +45,8 @@ struct HexStage {
     return true;
   }
 
+  HD static Smem& batch(Smem& sm) { return sm; }
+
   HD static void load_ops(int tid, Smem& sm, const StageArgs& a) {
     for (int i = tid; i < n1 * n1; i += NT) (&sm.D1[0][0])[i] = a.ops[i];
     for (int i = tid; i < 2 * n1; i += NT) (&sm.Lf[0][0])[i] = a.ops[n1 * n1 + i];

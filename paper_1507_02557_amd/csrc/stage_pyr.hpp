@@ -31,13 +31,16 @@ struct PyrStage {
   static constexpr int kOpsInts = 8 * Nfq + 6 * Nfn;
   static constexpr int kDl = kDInLds ? Np : 1;
 
-  struct Smem {
+  // operator tables (shared by all batches of a block) and one batch's data
+  struct Ops {
     float D[3][kDl][kDl];
     float Fq[Nfq][Np];
     float Ft[4][Nfn][Np];
     float Ican[Nfq][Nfn];
     int qperm[8][Nfq];
     int tperm[6][Nfn];
+  };
+  struct Batch {
     float u[4][EPB][Np];
     float un[4][EPB][Np];
     float ur[3][EPB][Np];
@@ -47,6 +50,17 @@ struct PyrStage {
     float s[EPB][Np][4];
     float mat[EPB][2];
   };
+  struct Smem {
+    Ops o;
+    Batch b;
+  };
+  // a wavefront's view: the block's tables and the wavefront's own batch
+  struct WaveRef {
+    const Ops& o;
+    Batch& b;
+  };
+  HD static Batch& batch(Smem& sm) { return sm.b; }
+  HD static Batch& batch(WaveRef& r) { return r.b; }
 
   HD static bool active(int ph, int mode) {
     if (mode == kModeTrace) return ph == 0 || ph >= 5;
@@ -54,23 +68,28 @@ struct PyrStage {
     return true;
   }
 
-  HD static float Dop(const Smem& sm, const StageArgs& a, int r, int i, int j) {
-    if (kDInLds) return sm.D[r][i % kDl][j % kDl];
+  HD static float Dop(const Ops& o, const StageArgs& a, int r, int i, int j) {
+    if (kDInLds) return o.D[r][i % kDl][j % kDl];
     return a.ops[(r * Np + i) * Np + j];
   }
 
-  HD static void load_ops(int tid, Smem& sm, const StageArgs& a) {
+  // tables into LDS by nthr threads
+  HD static void load_ops(int tid, int nthr, Ops& o, const StageArgs& a) {
     if (kDInLds)
-      for (int i = tid; i < 3 * Np * Np; i += NT) (&sm.D[0][0][0])[i] = a.ops[i];
+      for (int i = tid; i < 3 * Np * Np; i += nthr) (&o.D[0][0][0])[i] = a.ops[i];
     const int o1 = 3 * Np * Np, o2 = o1 + Nfq * Np, o3 = o2 + 4 * Nfn * Np;
-    for (int i = tid; i < Nfq * Np; i += NT) (&sm.Fq[0][0])[i] = a.ops[o1 + i];
-    for (int i = tid; i < 4 * Nfn * Np; i += NT) (&sm.Ft[0][0][0])[i] = a.ops[o2 + i];
-    for (int i = tid; i < Nfq * Nfn; i += NT) (&sm.Ican[0][0])[i] = a.ops[o3 + i];
-    for (int i = tid; i < 8 * Nfq; i += NT) (&sm.qperm[0][0])[i] = a.iops[i];
-    for (int i = tid; i < 6 * Nfn; i += NT) (&sm.tperm[0][0])[i] = a.iops[8 * Nfq + i];
+    for (int i = tid; i < Nfq * Np; i += nthr) (&o.Fq[0][0])[i] = a.ops[o1 + i];
+    for (int i = tid; i < 4 * Nfn * Np; i += nthr) (&o.Ft[0][0][0])[i] = a.ops[o2 + i];
+    for (int i = tid; i < Nfq * Nfn; i += nthr) (&o.Ican[0][0])[i] = a.ops[o3 + i];
+    for (int i = tid; i < 8 * Nfq; i += nthr) (&o.qperm[0][0])[i] = a.iops[i];
+    for (int i = tid; i < 6 * Nfn; i += nthr) (&o.tperm[0][0])[i] = a.iops[8 * Nfq + i];
   }
+  HD static void load_ops(int tid, Smem& sm, const StageArgs& a) { load_ops(tid, NT, sm.o, a); }
 
-  HD static void phase(int ph, int tid, Smem& sm, const StageArgs& a, int64_t e0) {
+  HD static void phase(int ph, int tid, Smem& sm, const StageArgs& a, int64_t e0) { phase(ph, tid, sm.o, sm.b, a, e0); }
+  HD static void phase(int ph, int tid, WaveRef& r, const StageArgs& a, int64_t e0) { phase(ph, tid, r.o, r.b, a, e0); }
+
+  HD static void phase(int ph, int tid, const Ops& o, Batch& sm, const StageArgs& a, int64_t e0) {
     const int64_t K = a.K;
     if (ph == 0) {
       for (int it = tid; it < 4 * EPB * Np; it += NT) {
@@ -110,11 +129,11 @@ struct PyrStage {
         const int64_t slot = a.slot0 + e * 5 + f;
         const float4 g = a.fgeo[(e * 5 + f) * Nfq + q];
         float4 m, p;
-        if (a.lat && f > 0) face_states_lattice(a, slot, Nfq, Nfn, q, &sm.Ican[0][0], g, m, p);
+        if (a.lat && f > 0) face_states_lattice(a, slot, Nfq, Nfn, q, &o.Ican[0][0], g, m, p);
         else face_states(a, slot, Nfq, q, g, m, p);
         float out[4];
         upwind_flux(m, p, g, a.tau[slot], true, out);
-        const int l = (f == 0) ? sm.qperm[a.ori[slot]][q] : q;
+        const int l = (f == 0) ? o.qperm[a.ori[slot]][q] : q;
         for (int c = 0; c < 4; ++c) sm.g[el][f][l][c] = out[c];
       }
     } else if (ph == 2) {
@@ -123,13 +142,13 @@ struct PyrStage {
         const int tf = rr / Nfn, m = rr % Nfn;
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
-        const int o = a.ori[a.slot0 + e * 5 + 1 + tf];
+        const int ori = a.ori[a.slot0 + e * 5 + 1 + tf];
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int q = 0; q < Nfq; ++q) {
-          const float w = sm.Ican[q][m];
+          const float w = o.Ican[q][m];
           for (int c = 0; c < 4; ++c) acc[c] += w * sm.g[el][1 + tf][q][c];
         }
-        const int l = sm.tperm[o][m];
+        const int l = o.tperm[ori][m];
         for (int c = 0; c < 4; ++c) sm.c[el][tf][l][c] = acc[c];
       }
     } else if (ph == 3) {
@@ -138,12 +157,12 @@ struct PyrStage {
         if (item(a, e0 + el) < 0) continue;
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int l = 0; l < Nfq; ++l) {
-          const float w = sm.Fq[l][i];
+          const float w = o.Fq[l][i];
           for (int c = 0; c < 4; ++c) acc[c] += w * sm.g[el][0][l][c];
         }
         for (int tf = 0; tf < 4; ++tf)
           for (int l = 0; l < Nfn; ++l) {
-            const float w = sm.Ft[tf][l][i];
+            const float w = o.Ft[tf][l][i];
             for (int c = 0; c < 4; ++c) acc[c] += w * sm.c[el][tf][l][c];
           }
         for (int c = 0; c < 4; ++c) sm.s[el][i][c] = acc[c];
@@ -160,8 +179,8 @@ struct PyrStage {
         for (int j = 0; j < Np; ++j) {
           const float pj = sm.u[0][el][j];
           for (int r = 0; r < 3; ++r) {
-            Dp[r] += Dop(sm, a, r, i, j) * pj;
-            volp += Dop(sm, a, r, j, i) * sm.ur[r][el][j];
+            Dp[r] += Dop(o, a, r, i, j) * pj;
+            volp += Dop(o, a, r, j, i) * sm.ur[r][el][j];
           }
         }
         const float* gp = a.geo + e * 10 * Np + i;
@@ -184,10 +203,10 @@ struct PyrStage {
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
         const int64_t slot = a.slot0 + e * 5;
-        const int l = sm.qperm[a.ori[slot]][q];
+        const int l = o.qperm[a.ori[slot]][q];
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int j = 0; j < Np; ++j) {
-          const float w = sm.Fq[l][j];
+          const float w = o.Fq[l][j];
           for (int c = 0; c < 4; ++c) acc[c] += w * src[c][el][j];
         }
         a.tr_out[slot * Nfq + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
@@ -197,7 +216,7 @@ struct PyrStage {
         const int tf = rr / Nfn, l = rr % Nfn;
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int j = 0; j < Np; ++j) {
-          const float w = sm.Ft[tf][l][j];
+          const float w = o.Ft[tf][l][j];
           for (int c = 0; c < 4; ++c) acc[c] += w * src[c][el][j];
         }
         for (int c = 0; c < 4; ++c) sm.c[el][tf][l][c] = acc[c];
@@ -210,7 +229,7 @@ struct PyrStage {
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
         const int64_t slot = a.slot0 + e * 5 + 1 + tf;
-        const int l = sm.tperm[a.ori[slot]][m];
+        const int l = o.tperm[a.ori[slot]][m];
         a.tr_out[slot * Nfq + m] = make_float4(sm.c[el][tf][l][0], sm.c[el][tf][l][1], sm.c[el][tf][l][2], sm.c[el][tf][l][3]);
       }
     } else if (ph == 6) {
@@ -220,11 +239,11 @@ struct PyrStage {
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
         const int64_t slot = a.slot0 + e * 5 + 1 + tf;
-        const int o = a.ori[slot];
+        const int ori = a.ori[slot];
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int m = 0; m < Nfn; ++m) {
-          const float w = sm.Ican[q][m];
-          const int l = sm.tperm[o][m];
+          const float w = o.Ican[q][m];
+          const int l = o.tperm[ori][m];
           for (int c = 0; c < 4; ++c) acc[c] += w * sm.c[el][tf][l][c];
         }
         a.tr_out[slot * Nfq + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);

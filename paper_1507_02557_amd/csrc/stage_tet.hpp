@@ -53,6 +53,8 @@ struct TetStage {
     return true;
   }
 
+  HD static Smem& batch(Smem& sm) { return sm; }
+
   HD static void load_ops(int tid, Smem& sm, const StageArgs& a) {
     float* D = &sm.D[0][0][0];
     for (int i = tid; i < 3 * Np * Np; i += NT) D[i] = a.ops[i];

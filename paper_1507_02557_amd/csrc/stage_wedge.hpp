@@ -72,6 +72,8 @@ struct WedgeStage {
     return true;
   }
 
+  HD static Smem& batch(Smem& sm) { return sm; }
+
   HD static void load_ops(int tid, Smem& sm, const StageArgs& a) {
     for (int i = tid; i < kOpsFloats; i += NT) sm.ops[i] = a.ops[i];
     for (int i = tid; i < 8 * Nfq; i += NT) (&sm.qperm[0][0])[i] = a.iops[i];

@@ -59,6 +59,50 @@ __global__ __launch_bounds__(S::NT) void mrab_update_kernel(StageArgs a) {
   }
 }
 
+// Wavefront-batched form (vector pyramids at N <= 4): the block holds the
+// operator tables once; each of its W wavefronts runs the same phases on a
+// batch of its own (one element), separated by wavefront syncs instead of
+// block barriers, so the wavefronts of a compute unit proceed independently
+// and hide one another's memory latency.
+template <class S, int W>
+__global__ __launch_bounds__(64 * W) void wave_stage_kernel(StageArgs a) {
+  __shared__ typename S::Ops o;
+  __shared__ typename S::Batch bt[W];
+  S::load_ops(threadIdx.x, 64 * W, o, a);
+  __syncthreads();
+  typename S::WaveRef r{o, bt[threadIdx.x >> 6]};
+  constexpr int EPB = S::kEPB;
+  const int64_t nb = (a.n_items + EPB - 1) / EPB;
+  for (int64_t b = (int64_t)blockIdx.x * W + (threadIdx.x >> 6); b < nb; b += (int64_t)gridDim.x * W) {
+    for (int ph = 0; ph < S::nphase; ++ph) {
+      if (!S::active(ph, a.mode)) continue;
+      int t = threadIdx.x & 63;
+      __asm__ volatile("" : "+v"(t));
+      S::phase(ph, t, r, a, b * EPB);
+      wave_sync();
+    }
+  }
+}
+
+template <class S, int W>
+__global__ __launch_bounds__(64 * W) void wave_mrab_update_kernel(StageArgs a) {
+  __shared__ typename S::Ops o;
+  __shared__ typename S::Batch bt[W];
+  S::load_ops(threadIdx.x, 64 * W, o, a);
+  __syncthreads();
+  typename S::WaveRef r{o, bt[threadIdx.x >> 6]};
+  constexpr int EPB = S::kEPB;
+  const int64_t nb = (a.n_items + EPB - 1) / EPB;
+  for (int64_t b = (int64_t)blockIdx.x * W + (threadIdx.x >> 6); b < nb; b += (int64_t)gridDim.x * W) {
+    for (int st = 0; st < MrabUpdate<S>::nstep; ++st) {
+      int t = threadIdx.x & 63;
+      __asm__ volatile("" : "+v"(t));
+      MrabUpdate<S>::step(st, t, r, a, b * EPB);
+      wave_sync();
+    }
+  }
+}
+
 // Blocks of a kernel that the whole device holds at once.  The persistent
 // grid is never larger: blocks beyond that number would start only when the
 // first ones finish, and the last of them would run alone.
@@ -90,6 +134,27 @@ static int go(const StageArgs& a, hipStream_t s, bool mrab) {
   return 0;
 }
 
+template <class S, int W>
+static int go_wave(const StageArgs& a, hipStream_t s, bool mrab) {
+  static_assert(S::NT == 64, "one wavefront per batch");
+  static_assert(sizeof(typename S::Ops) + W * sizeof(typename S::Batch) <= 160 * 1024, "LDS budget exceeded");
+  if (a.n_items == 0) return 0;
+  const int64_t nb = (a.n_items + S::kEPB - 1) / S::kEPB;
+  const int64_t nblk = (nb + W - 1) / W;
+  int64_t cap;
+  if (mrab) {
+    static const int64_t c = resident_blocks(reinterpret_cast<const void*>(&wave_mrab_update_kernel<S, W>), 64 * W);
+    cap = c;
+  } else {
+    static const int64_t c = resident_blocks(reinterpret_cast<const void*>(&wave_stage_kernel<S, W>), 64 * W);
+    cap = c;
+  }
+  const unsigned grid = (unsigned)(nblk < cap ? nblk : cap);
+  if (mrab) hipLaunchKernelGGL((wave_mrab_update_kernel<S, W>), dim3(grid), dim3(64 * W), 0, s, a);
+  else hipLaunchKernelGGL((wave_stage_kernel<S, W>), dim3(grid), dim3(64 * W), 0, s, a);
+  return 0;
+}
+
 template <class S>
 static void sizes(int* nf, int* ni) {
   *nf = S::kOpsFloats;
@@ -101,7 +166,9 @@ static int launch_n(int type, const StageArgs& a, hipStream_t s, bool mrab) {
   switch (type) {
     case 0: return go<HexStage<N, epb(0, N)>>(a, s, mrab);
     case 1: return go<WedgeStage<N, epb(1, N)>>(a, s, mrab);
-    case 2: return go<PyrStage<N, epb(2, N), pyr_threads(N)>>(a, s, mrab);
+    case 2:
+      if constexpr (N <= 4) return go_wave<PyrStage<N, 1, 64>, pyr_waves(N)>(a, s, mrab);
+      else return go<PyrStage<N, epb(2, N)>>(a, s, mrab);
     case 3: return go<TetStage<N, epb(3, N)>>(a, s, mrab);
   }
   return -1;
@@ -112,7 +179,7 @@ static void sizes_n(int type, int* nf, int* ni) {
   switch (type) {
     case 0: sizes<HexStage<N, epb(0, N)>>(nf, ni); break;
     case 1: sizes<WedgeStage<N, epb(1, N)>>(nf, ni); break;
-    case 2: sizes<PyrStage<N, epb(2, N), pyr_threads(N)>>(nf, ni); break;
+    case 2: sizes<PyrStage<N, epb(2, N)>>(nf, ni); break;
     default: sizes<TetStage<N, epb(3, N)>>(nf, ni); break;
   }
 }

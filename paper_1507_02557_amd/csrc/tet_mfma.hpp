@@ -197,24 +197,32 @@ struct TetMfma {
     }
   }
 
-  // face-node values of the tile's state, canonical lattice order
-  template <class SM>
+  // face-node values of the tile's state, canonical lattice order (LEAN:
+  // one face at a time, for callers with many registers in use)
+  template <bool LEAN = false, class SM>
   __device__ static void write_traces(const SM& sm, const float (&X)[4][16][SX], const StageArgs& a, int64_t e0,
                                       int lane, const FaceRec& rec, float4* tr, bool col_active = true) {
     const int n = lane & 15, g = lane >> 4;
     const int64_t e = item(a, e0 + n);
+    if constexpr (LEAN) {
+#pragma unroll 1
+      for (int f = 0; f < 4; ++f) trace_face(sm, X, a, e, n, g, f, __shfl(rec.ori, n + 16 * f), tr, col_active);
+    } else {
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const int o = __shfl(rec.ori, n + 16 * f);
-      if (e < 0 || !col_active) continue;
-      const int64_t slot = a.slot0 + e * 4 + f;
+      for (int f = 0; f < 4; ++f) trace_face(sm, X, a, e, n, g, f, __shfl(rec.ori, n + 16 * f), tr, col_active);
+    }
+  }
+  template <class SM>
+  __device__ static void trace_face(const SM& sm, const float (&X)[4][16][SX], const StageArgs& a, int64_t e, int n,
+                                    int g, int f, int o, float4* tr, bool col_active) {
+    if (e < 0 || !col_active) return;
+    const int64_t slot = a.slot0 + e * 4 + f;
 #pragma unroll
-      for (int j = 0; j < JF; ++j) {
-        const int m = g + 4 * j;
-        if (m >= Nfn) continue;
-        const int node = sm.fnode[f][sm.tperm[o][m]];
-        tr[slot * Nfq + m] = make_float4(X[0][n][node], X[1][n][node], X[2][n][node], X[3][n][node]);
-      }
+    for (int j = 0; j < JF; ++j) {
+      const int m = g + 4 * j;
+      if (m >= Nfn) continue;
+      const int node = sm.fnode[f][sm.tperm[o][m]];
+      tr[slot * Nfq + m] = make_float4(X[0][n][node], X[1][n][node], X[2][n][node], X[3][n][node]);
     }
   }
 
@@ -222,17 +230,17 @@ struct TetMfma {
   // state tile per wavefront, its own register budget)
   //   u_half = u + dtau_l sum_j beta_j(1/2) r_{s-j}   (dense output at mid-step)
   //   u_new  = u + dtau_l sum_j beta_j(1)   r_{s-j}
-  // The history is read once, in the tile's flat node order (consecutive
-  // lanes, consecutive addresses): the tile becomes u_half while
-  // u_new - u_half stays in registers; the mid-step traces are written, then
-  // the tile becomes u_new, which is stored with its traces.
+  // One LDS tile per wavefront (12 wavefronts per compute unit at N <= 4,
+  // set by the registers): it holds u_half while the mid-step traces are
+  // written (tiles with an element whose finer neighbour reads them), then
+  // u_new, which is stored with its traces; in the one-level tiles u_new waits
+  // in registers and the history is read once.
   static constexpr int NWU = 4;  // wavefronts per block of the update kernel
   // wavefronts per SIMD the update kernel's register allocation must allow
   static constexpr int kUpdateWaves = N <= 4 ? 3 : 2;
   static constexpr int JN = (16 * Np + 63) / 64;  // flat tile entries per lane
   struct alignas(16) UWave {
-    float X[4][16][SX];  // state tile (u_half in the one-level path)
-    float Y[4][16][SX];  // u_new in the one-level path
+    float X[4][16][SX];  // state tile
   };
   struct USmem {
     MrabParams mr;  // per-level weights and history slots (indexed by the element's level)
@@ -253,6 +261,7 @@ struct TetMfma {
     FaceRec rec{-1, 0, 0, make_float4(0.f, 0.f, 0.f, 0.f), make_float2(0.f, 0.f)};
     if (e >= 0) rec.ori = a.ori[a.slot0 + e * 4 + g];
     const bool half = e >= 0 && a.ehalf[e];
+    const bool any_half = __any(half);
     const MrabParams& mr = sm.mr;
     // a tile of consecutive elements of one level (the common case with the
     // elements stored finest level first) moves as flat float4 vectors;
@@ -266,51 +275,78 @@ struct TetMfma {
       const float* h0 = a.H + mr.hs[lv0][0] * hstr;
       const float* h1 = a.H + mr.hs[lv0][1] * hstr;
       const float* h2 = a.H + mr.hs[lv0][2] * hstr;
-#pragma unroll 1
+      float4 un[4][JQ];
+#pragma unroll
       for (int c = 0; c < 4; ++c) {
-        float4 u[JQ], x0[JQ], x1[JQ], x2[JQ], un[JQ], uh[JQ];
+        float4 u[JQ], x0[JQ], x1[JQ], x2[JQ];
         load_field(u, a.U + c * fs, e0, lane);
         load_field(x0, h0 + c * fs, e0, lane);
         load_field(x1, h1 + c * fs, e0, lane);
         load_field(x2, h2 + c * fs, e0, lane);
-#pragma unroll
-        for (int j = 0; j < JQ; ++j) {
-          un[j] = u[j] + w1[0] * x0[j] + w1[1] * x1[j] + w1[2] * x2[j];
-          uh[j] = u[j] + wh[0] * x0[j] + wh[1] * x1[j] + wh[2] * x2[j];
-        }
         float4* U4 = reinterpret_cast<float4*>(a.U + c * fs + e0 * Np);
 #pragma unroll
-        for (int j = 0; j < JQ; ++j)
-          if (lane + 64 * j < Q4) U4[lane + 64 * j] = un[j];
-        put_field<SX>(W.X[c], uh, lane);
-        put_field<SX>(W.Y[c], un, lane);
+        for (int j = 0; j < JQ; ++j) {
+          if (lane + 64 * j >= Q4) continue;
+          un[c][j] = u[j] + w1[0] * x0[j] + w1[1] * x1[j] + w1[2] * x2[j];
+          const float4 uh = u[j] + wh[0] * x0[j] + wh[1] * x1[j] + wh[2] * x2[j];
+          U4[lane + 64 * j] = un[c][j];
+          put4<SX>(W.X[c], 4 * (lane + 64 * j), any_half ? uh : un[c][j]);
+        }
+        // the next field's loads are issued after this field's stores (all
+        // four fields' loads in flight at once would not fit the registers)
+        __builtin_amdgcn_sched_barrier(0);
       }
       wave_sync();
-      // mid-step traces of the elements whose finer neighbours read them
-      write_traces(sm, W.X, a, e0, lane, rec, a.tr_half, half);
-      write_traces(sm, W.Y, a, e0, lane, rec, a.tr_out);
+      if (any_half) {
+        // mid-step traces of the elements whose finer neighbours read them
+        write_traces<true>(sm, W.X, a, e0, lane, rec, a.tr_half, half);
+        wave_sync();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) put_field<SX>(W.X[c], un[c], lane);
+        wave_sync();
+      }
+      write_traces(sm, W.X, a, e0, lane, rec, a.tr_out);
       return;
     }
     if (contig) {
-      float4 v0[JQ], v1[JQ], v2[JQ], v3[JQ];
-      load_field(v0, a.U, e0, lane);
-      load_field(v1, a.U + fs, e0, lane);
-      load_field(v2, a.U + 2 * fs, e0, lane);
-      load_field(v3, a.U + 3 * fs, e0, lane);
-      put_field<SX>(W.X[0], v0, lane);
-      put_field<SX>(W.X[1], v1, lane);
-      put_field<SX>(W.X[2], v2, lane);
-      put_field<SX>(W.X[3], v3, lane);
+#pragma unroll 1
+      for (int c = 0; c < 4; ++c) {
+        float4 v[JQ];
+        load_field(v, a.U + c * fs, e0, lane);
+        put_field<SX>(W.X[c], v, lane);
+      }
     } else {
       for (int c = 0; c < 4; ++c) load_rows<SX>(W.X[c], a.U + (int64_t)c * K * Np, a, e0, lane);
     }
     wave_sync();
-    float dd[4][JN];
-#pragma unroll
+    // general tiles (an item list, or two levels in one tile): per-entry
+    // history reads, one field at a time; with mid-step traces to write the
+    // history is read twice (u_half, then u_new - u_half)
+    if (any_half) {
+      hist_pass(sm, W, a, e0, lane, 0);
+      wave_sync();
+      write_traces<true>(sm, W.X, a, e0, lane, rec, a.tr_half, half);
+      wave_sync();
+      hist_pass(sm, W, a, e0, lane, 1);
+    } else {
+      hist_pass(sm, W, a, e0, lane, 2);
+    }
+    wave_sync();
+#pragma unroll 1
+    for (int c = 0; c < 4; ++c) store_tile<SX>(a.U + (int64_t)c * K * Np, W.X[c], a, e0, lane, contig);
+    write_traces<true>(sm, W.X, a, e0, lane, rec, a.tr_out);
+  }
+
+  // X += dtau_l sum_j w_j r_{s-j} over the tile, per entry at the entry's
+  // element level: w = beta(1/2) (which 0), beta(1) - beta(1/2) (1), beta(1) (2)
+  __device__ static void hist_pass(const USmem& sm, UWave& W, const StageArgs& a, int64_t e0, int lane, int which) {
+    const int64_t K = a.K;
+    const int64_t hstr = 4 * K * Np;
+    const MrabParams& mr = sm.mr;
+#pragma unroll 1
     for (int c = 0; c < 4; ++c)
-#pragma unroll
+#pragma unroll 1
       for (int j = 0; j < JN; ++j) {
-        dd[c][j] = 0.f;
         const int it = lane + 64 * j;
         if (it >= 16 * Np) continue;
         const int nn = it / Np, k = it - nn * Np;
@@ -320,28 +356,12 @@ struct TetMfma {
         const int64_t gi = (int64_t)c * K * Np + ee * Np + k;
         const float x0 = a.H[mr.hs[lv][0] * hstr + gi], x1 = a.H[mr.hs[lv][1] * hstr + gi],
                     x2 = a.H[mr.hs[lv][2] * hstr + gi];
-        const float dl = mr.dtl[lv];
-        const float d1 = dl * (mr.b1[lv][0] * x0 + mr.b1[lv][1] * x1 + mr.b1[lv][2] * x2);
-        const float dh = dl * (mr.bh[lv][0] * x0 + mr.bh[lv][1] * x1 + mr.bh[lv][2] * x2);
-        W.X[c][nn][k] += dh;
-        dd[c][j] = d1 - dh;
+        float w[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          w[q] = which == 0 ? mr.bh[lv][q] : (which == 1 ? mr.b1[lv][q] - mr.bh[lv][q] : mr.b1[lv][q]);
+        W.X[c][nn][k] += mr.dtl[lv] * (w[0] * x0 + w[1] * x1 + w[2] * x2);
       }
-    wave_sync();
-    write_traces(sm, W.X, a, e0, lane, rec, a.tr_half, half);
-    wave_sync();
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int j = 0; j < JN; ++j) {
-        const int it = lane + 64 * j;
-        if (it >= 16 * Np) continue;
-        const int nn = it / Np, k = it - nn * Np;
-        W.X[c][nn][k] += dd[c][j];
-      }
-    wave_sync();
-#pragma unroll
-    for (int c = 0; c < 4; ++c) store_tile<SX>(a.U + (int64_t)c * K * Np, W.X[c], a, e0, lane, contig);
-    write_traces(sm, W.X, a, e0, lane, rec, a.tr_out);
   }
 
   __device__ static void run_update(USmem& sm, const StageArgs& a) {
