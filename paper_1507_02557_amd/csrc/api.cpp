@@ -510,7 +510,7 @@ int run_mortar(hdg_ctx* c, float4* tr, float4* tr_half, int ksub, int dense) {
   m.rec = c->ncrec;
   m.vslot0 = c->nslot0;
   m.nfn = c->ft.Nfn;
-  m.nfq = c->ft.Nfq;
+  m.ts = trace_stride(c->N);
   m.I = c->ncI;
   m.P = c->ncP;
   m.cgeo = c->td[kTet].fgeo;
@@ -1049,8 +1049,8 @@ int create_impl(hdg_ctx* c, const hdg_mesh* m, int N) {
     HIPCHK(c, hipMemsetAsync(d.U, 0, nstate * sizeof(float), c->stream));
     HIPCHK(c, hipMemsetAsync(d.R, 0, nstate * sizeof(float), c->stream));
   }
-  if ((rc = dalloc(c, &c->trace[0], (size_t)nsall * ft.Nfq))) return rc;
-  if ((rc = dalloc(c, &c->trace[1], (size_t)nsall * ft.Nfq))) return rc;
+  if ((rc = dalloc(c, &c->trace[0], (size_t)nsall * trace_stride(c->N)))) return rc;
+  if ((rc = dalloc(c, &c->trace[1], (size_t)nsall * trace_stride(c->N)))) return rc;
   if ((rc = dalloc(c, &c->partial, (size_t)(ne / 256 + 8)))) return rc;
   if ((rc = dalloc(c, &c->flag, 1))) return rc;
   HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -46,7 +46,7 @@ struct MortarArgs {
   int64_t n;              // non-conforming coarse faces
   const int* rec;         // [n][kNcRec]
   int64_t vslot0;
-  int nfn, nfq;
+  int nfn, ts;            // face lattice nodes; trace stride (float4 per slot)
   const float* I;         // [nvar][nfn][nfn] coarse lattice -> sub-face lattice (canonical frames)
   const float* P;         // [nvar][nfn][nfn] sub-face lattice flux -> equivalent coarse lattice flux
   const float4* cgeo;     // coarse type's face factors [K][4] (n, J^s)

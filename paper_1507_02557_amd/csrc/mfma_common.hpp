@@ -125,14 +125,4 @@ __device__ __forceinline__ f32x4 mma_split(const typename PR::V (&a)[PR::NPC], c
   return acc;
 }
 
-// Neighbour state on a lattice face at canonical lattice node m (boundary:
-// mirror of the own state).  A coarser neighbour that is mid-step supplies
-// its dense-output trace.
-__device__ __forceinline__ float4 lattice_neighbour(const StageArgs& a, int64_t slot, int nfq, int m, float4 g,
-                                                    float4 own) {
-  const int nb = a.nbr[slot];
-  if (nb < 0) return mirror_state(own, -nb - 1, g.x, g.y, g.z);
-  return neighbour_src(a, slot, nb)[(int64_t)nb * nfq + m];
-}
-
 }  // namespace hdg

@@ -54,16 +54,18 @@ __global__ __launch_bounds__(kFacesPerBlock* kLanes) void mortar_kernel(MortarAr
   const int64_t i = (int64_t)blockIdx.x * kFacesPerBlock + lf;
   const bool face = i < a.n;
   const bool act = face && m < a.nfn;
+  // written slots are padded with zeros to whole lines
+  const bool pad = face && m >= a.nfn && m < (a.nfn + 7) / 8 * 8;
   const int nfn = a.nfn;
-  const int64_t nfq = a.nfq;
+  const int64_t ts = a.ts;
   if (face && m < kNcRec) R[lf][m] = a.rec[i * kNcRec + m];
   __syncthreads();
   const int parent = face ? R[lf][0] : 0, flux = face ? R[lf][1] : 0;
   const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
   if (act) {
-    C[lf][m] = a.tr[(int64_t)parent * nfq + m];
+    C[lf][m] = a.tr[(int64_t)parent * ts + m];
     float4 h = z;
-    if (a.tr_half) h = a.tr_half[(int64_t)parent * nfq + m];
+    if (a.tr_half) h = a.tr_half[(int64_t)parent * ts + m];
     Ch[lf][m] = h;
   }
   __syncthreads();
@@ -81,8 +83,8 @@ __global__ __launch_bounds__(kFacesPerBlock* kLanes) void mortar_kernel(MortarAr
         x = fma4(w, C[lf][j], x);
         xh = fma4(w, Ch[lf][j], xh);
       }
-      a.tr[vs * nfq + m] = x;
-      if (a.tr_half) a.tr_half[vs * nfq + m] = xh;
+      a.tr[vs * ts + m] = x;
+      if (a.tr_half) a.tr_half[vs * ts + m] = xh;
       // the fine side: its mid-step trace when it is one level coarser and
       // between its step boundaries
       const float4* src = a.tr;
@@ -90,7 +92,7 @@ __global__ __launch_bounds__(kFacesPerBlock* kLanes) void mortar_kernel(MortarAr
         const int ln = a.slevel[fine];
         if (ln < a.slevel[parent] && (a.ksub & ((1 << (a.L - ln)) - 1)) != 0) src = a.tr_half;
       }
-      const float4 p = src[(int64_t)fine * nfq + m];
+      const float4 p = src[(int64_t)fine * ts + m];
       float out[4];
       upwind_flux(x, p, gs, a.tau[vs], false, out);
       Fl[lf][s][m] = make_float4(out[0], out[1], out[2], out[3]);
@@ -104,7 +106,16 @@ __global__ __launch_bounds__(kFacesPerBlock* kLanes) void mortar_kernel(MortarAr
       const float* Ps = a.P + ((int64_t)R[lf][6 + s] * nfn + m) * nfn;
       for (int j = 0; j < nfn; ++j) gsum = fma4(Ps[j], Fl[lf][s][j], gsum);
     }
-    a.tr[(int64_t)flux * nfq + m] = gsum;
+    a.tr[(int64_t)flux * ts + m] = gsum;
+  }
+  if (pad) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t vs = a.vslot0 + 4 * i + s;
+      a.tr[vs * ts + m] = z;
+      if (a.tr_half) a.tr_half[vs * ts + m] = z;
+    }
+    a.tr[(int64_t)R[lf][1] * ts + m] = z;
   }
 }
 

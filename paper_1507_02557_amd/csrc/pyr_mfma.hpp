@@ -71,6 +71,7 @@ struct PyrMfma {
   static constexpr int Np = (N + 1) * (N + 2) * (2 * N + 3) / 6;
   static constexpr int Nfn = (N + 1) * (N + 2) / 2;
   static constexpr int Nfq = (N + 1) * (N + 1);
+  static constexpr int TS = trace_stride(N), LW = lattice_width(N);
   static constexpr int Mt = (Np + 15) / 16;   // row tiles over element nodes
   static constexpr int Ks = (Np + 3) / 4;     // k-steps over element nodes
   static constexpr int Mq = (Nfq + 15) / 16;  // row tiles over base-face points
@@ -228,7 +229,7 @@ struct PyrMfma {
         for (int i = 0; i < 4; ++i) {
           const int l = 16 * t + 4 * g + i;
           if (e >= 0 && l < Nfq)
-            tr[slot * Nfq + sm.iqperm[o][l]] = make_float4(acc[0][t][i], acc[1][t][i], acc[2][t][i], acc[3][t][i]);
+            tr[slot * TS + sm.iqperm[o][l]] = make_float4(acc[0][t][i], acc[1][t][i], acc[2][t][i], acc[3][t][i]);
         }
     }
     // triangular faces: lattice values Ft_f u (rows = local lattice nodes)
@@ -251,7 +252,9 @@ struct PyrMfma {
       for (int i = 0; i < 4; ++i) {
         const int l = 4 * g + i;
         if (e >= 0 && l < Nfn)
-          tr[(slot + 1 + tf) * Nfq + sm.itperm[o][l]] = make_float4(acc[0][i], acc[1][i], acc[2][i], acc[3][i]);
+          tr[(slot + 1 + tf) * TS + sm.itperm[o][l]] = make_float4(acc[0][i], acc[1][i], acc[2][i], acc[3][i]);
+        else if (e >= 0 && l < LW)  // padding to whole lines
+          tr[(slot + 1 + tf) * TS + l] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
     }
   }
@@ -442,9 +445,9 @@ struct PyrMfma {
         for (int jj = 0; jj < 2; ++jj) {
           const int q = g + 4 * (j0 + jj);
           if (e >= 0 && j0 + jj < JB && q < Nfq) {
-            own[jj] = a.tr_in[slot0 * Nfq + q];
+            own[jj] = a.tr_in[slot0 * TS + q];
             gq[jj] = a.fgeo[(slot0 - a.slot0) * Nfq + q];
-            if (nb >= 0) pv[jj] = nsrc[(int64_t)nb * Nfq + q];
+            if (nb >= 0) pv[jj] = nsrc[(int64_t)nb * TS + q];
           }
         }
 #pragma unroll
@@ -503,8 +506,8 @@ struct PyrMfma {
         float out[4] = {0.f, 0.f, 0.f, 0.f};
         int l = m;
         if (e >= 0) {
-          const float4 own = a.tr_in[slot * Nfq + m];
-          const float4 p = nb >= 0 ? nsrc[(int64_t)nb * Nfq + m] : mirror_state(own, -nb - 1, gf.x, gf.y, gf.z);
+          const float4 own = a.tr_in[slot * TS + m];
+          const float4 p = nb >= 0 ? nsrc[(int64_t)nb * TS + m] : mirror_state(own, -nb - 1, gf.x, gf.y, gf.z);
           l = sm.tperm[o][m];
           upwind_flux(own, p, gf, tau, true, out);
         }

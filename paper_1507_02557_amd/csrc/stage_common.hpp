@@ -74,6 +74,15 @@ enum { kModeStage = 0, kModeTrace = 1, kModeRhs = 2, kModeRhsHist = 3, kModeMrab
 // neighbour trace.  Boundary codes -(1 + bc) stay above -kNcBase.
 constexpr int kNcBase = 16;
 
+// Float4 entries per trace slot: the face's cubature points rounded up to
+// whole 128-byte lines, so every slot starts on a line boundary.  A lattice
+// trace (triangular face between tetrahedra or pyramids) is written as
+// lattice_width values, its lattice padded with zeros to whole lines: full
+// lines go to memory as plain writes, where a partly written line costs a
+// read-modify-write.
+HD constexpr int trace_stride(int N) { return ((N + 1) * (N + 1) + 7) / 8 * 8; }
+HD constexpr int lattice_width(int N) { return ((N + 1) * (N + 2) / 2 + 7) / 8 * 8; }
+
 // LDS writes of this wavefront become visible to its later LDS reads (LDS
 // operations of one wavefront complete in order; this stops the compiler
 // from moving memory operations across the point).
@@ -164,12 +173,12 @@ HD inline const float4* neighbour_src(const StageArgs& a, int64_t slot, int nb) 
   return a.tr_in;
 }
 
-// Own and neighbour traces at canonical point q of a slot.
-HD inline void face_states(const StageArgs& a, int64_t slot, int nfq, int q, float4 g, float4& m, float4& p) {
-  m = a.tr_in[slot * nfq + q];
+// Own and neighbour traces at canonical point q of a slot (ts: trace stride).
+HD inline void face_states(const StageArgs& a, int64_t slot, int ts, int q, float4 g, float4& m, float4& p) {
+  m = a.tr_in[slot * ts + q];
   const int nb = a.nbr[slot];
   if (nb >= 0) {
-    p = neighbour_src(a, slot, nb)[(int64_t)nb * nfq + q];
+    p = neighbour_src(a, slot, nb)[(int64_t)nb * ts + q];
   } else {
     p = mirror_state(m, -nb - 1, g.x, g.y, g.z);
   }
@@ -177,11 +186,11 @@ HD inline void face_states(const StageArgs& a, int64_t slot, int nfq, int q, flo
 
 // Same from lattice traces: values at canonical cubature point q are
 // interpolated from the canonical lattice values (Ican [nfq][nfn]).
-HD inline void face_states_lattice(const StageArgs& a, int64_t slot, int nfq, int nfn, int q, const float* Ican,
+HD inline void face_states_lattice(const StageArgs& a, int64_t slot, int ts, int nfn, int q, const float* Ican,
                                    float4 g, float4& m, float4& p) {
-  const float4* own = a.tr_in + slot * nfq;
+  const float4* own = a.tr_in + slot * ts;
   const int nb = a.nbr[slot];
-  const float4* nbv = nb >= 0 ? neighbour_src(a, slot, nb) + (int64_t)nb * nfq : own;
+  const float4* nbv = nb >= 0 ? neighbour_src(a, slot, nb) + (int64_t)nb * ts : own;
   float4 sm = make_float4(0.f, 0.f, 0.f, 0.f), sp = sm;
   for (int j = 0; j < nfn; ++j) {
     const float w = Ican[q * nfn + j];

@@ -22,6 +22,7 @@ struct HexStage {
   static constexpr int n1 = N + 1;
   static constexpr int Np = n1 * n1 * n1;
   static constexpr int Nfq = n1 * n1;
+  static constexpr int TS = trace_stride(N);
   static constexpr int NT = 256;
   static constexpr int kEPB = EPB;
   static constexpr int nphase = 4;
@@ -117,7 +118,7 @@ struct HexStage {
         const int64_t e0v = item(a, e0 + el);
         const int64_t e = e0v >= 0 ? e0v : e_any;
         const int64_t slot = a.slot0 + e * 6 + f;
-        if (fnb[r] >= 0) fp[r] = neighbour_src(a, slot, fnb[r])[(int64_t)fnb[r] * Nfq + q];
+        if (fnb[r] >= 0) fp[r] = neighbour_src(a, slot, fnb[r])[(int64_t)fnb[r] * TS + q];
       }
 #pragma unroll
       for (int r = 0; r < RF; ++r) {
@@ -226,7 +227,7 @@ struct HexStage {
           const int nd = line_node(f, m, l1, l2);
           for (int c = 0; c < 4; ++c) acc[c] += L[m] * src[c][el][nd];
         }
-        a.tr_out[slot * Nfq + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        a.tr_out[slot * TS + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
       }
     }
   }

@@ -22,6 +22,7 @@ struct PyrStage {
   static constexpr int Np = (N + 1) * (N + 2) * (2 * N + 3) / 6;
   static constexpr int Nfn = (N + 1) * (N + 2) / 2;
   static constexpr int Nfq = (N + 1) * (N + 1);
+  static constexpr int TS = trace_stride(N), LW = lattice_width(N);
   static constexpr int NT = NTH;
   static constexpr int kEPB = EPB;
   static constexpr int nphase = 7;
@@ -129,8 +130,8 @@ struct PyrStage {
         const int64_t slot = a.slot0 + e * 5 + f;
         const float4 g = a.fgeo[(e * 5 + f) * Nfq + q];
         float4 m, p;
-        if (a.lat && f > 0) face_states_lattice(a, slot, Nfq, Nfn, q, &o.Ican[0][0], g, m, p);
-        else face_states(a, slot, Nfq, q, g, m, p);
+        if (a.lat && f > 0) face_states_lattice(a, slot, TS, Nfn, q, &o.Ican[0][0], g, m, p);
+        else face_states(a, slot, TS, q, g, m, p);
         float out[4];
         upwind_flux(m, p, g, a.tau[slot], true, out);
         const int l = (f == 0) ? o.qperm[a.ori[slot]][q] : q;
@@ -209,7 +210,7 @@ struct PyrStage {
           const float w = o.Fq[l][j];
           for (int c = 0; c < 4; ++c) acc[c] += w * src[c][el][j];
         }
-        a.tr_out[slot * Nfq + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        a.tr_out[slot * TS + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
       }
       for (int it = tid; it < EPB * 4 * Nfn; it += NT) {
         const int el = it / (4 * Nfn), rr = it % (4 * Nfn);
@@ -222,15 +223,20 @@ struct PyrStage {
         for (int c = 0; c < 4; ++c) sm.c[el][tf][l][c] = acc[c];
       }
     } else if (ph == 6 && a.lat) {
-      // lattice traces: the face-lattice values in the canonical order
-      for (int it = tid; it < EPB * 4 * Nfn; it += NT) {
-        const int el = it / (4 * Nfn), rr = it % (4 * Nfn);
-        const int tf = rr / Nfn, m = rr % Nfn;
+      // lattice traces: the face-lattice values in the canonical order,
+      // padded with zeros to whole lines
+      for (int it = tid; it < EPB * 4 * LW; it += NT) {
+        const int el = it / (4 * LW), rr = it % (4 * LW);
+        const int tf = rr / LW, m = rr % LW;
         const int64_t e = item(a, e0 + el);
         if (e < 0) continue;
         const int64_t slot = a.slot0 + e * 5 + 1 + tf;
-        const int l = o.tperm[a.ori[slot]][m];
-        a.tr_out[slot * Nfq + m] = make_float4(sm.c[el][tf][l][0], sm.c[el][tf][l][1], sm.c[el][tf][l][2], sm.c[el][tf][l][3]);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (m < Nfn) {
+          const int l = o.tperm[a.ori[slot]][m];
+          v = make_float4(sm.c[el][tf][l][0], sm.c[el][tf][l][1], sm.c[el][tf][l][2], sm.c[el][tf][l][3]);
+        }
+        a.tr_out[slot * TS + m] = v;
       }
     } else if (ph == 6) {
       for (int it = tid; it < EPB * 4 * Nfq; it += NT) {
@@ -246,7 +252,7 @@ struct PyrStage {
           const int l = o.tperm[ori][m];
           for (int c = 0; c < 4; ++c) acc[c] += w * sm.c[el][tf][l][c];
         }
-        a.tr_out[slot * Nfq + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        a.tr_out[slot * TS + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
       }
     }
   }

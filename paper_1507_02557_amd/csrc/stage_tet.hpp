@@ -22,6 +22,7 @@ struct TetStage {
   static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
   static constexpr int Nfn = (N + 1) * (N + 2) / 2;
   static constexpr int Nfq = (N + 1) * (N + 1);
+  static constexpr int TS = trace_stride(N);
   static constexpr int NT = 256;
   static constexpr int kEPB = EPB;
   static constexpr int nphase = 6;
@@ -104,7 +105,7 @@ struct TetStage {
           float4 g = a.fgeo[e * 4 + f];
           g.w *= sm.w[q];
           float4 m, p;
-          face_states(a, slot, Nfq, q, g, m, p);
+          face_states(a, slot, TS, q, g, m, p);
           upwind_flux(m, p, g, a.tau[slot], false, out);
         }
         for (int c = 0; c < 4; ++c) sm.g[el][f][q][c] = out[c];
@@ -177,7 +178,7 @@ struct TetStage {
           const int node = sm.fnode[f][sm.tperm[o][m]];
           for (int c = 0; c < 4; ++c) acc[c] += w * src[c][el][node];
         }
-        a.tr_out[slot * Nfq + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        a.tr_out[slot * TS + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
       }
     }
   }

@@ -26,6 +26,7 @@ struct WedgeStage {
   static constexpr int Nct = n1 * n1;
   static constexpr int Nq = n1 * Nct;
   static constexpr int Nfq = n1 * n1;
+  static constexpr int TS = trace_stride(N);
   static constexpr int Nfn = Ntri;
   static constexpr int NT = 256;
   static constexpr int kEPB = EPB;
@@ -131,7 +132,7 @@ struct WedgeStage {
         fdst[r] = (it < NF && e0v >= 0) ? el * 5 + f : -1;
         if (!flux) continue;
         fg[r] = a.fgeo[(e * 5 + f) * Nfq + q];
-        face_states(a, slot, Nfq, q, fg[r], fm[r], fp[r]);
+        face_states(a, slot, TS, q, fg[r], fm[r], fp[r]);
         ftau[r] = a.tau[slot];
       }
 #pragma unroll
@@ -370,7 +371,7 @@ struct WedgeStage {
           for (int c = 0; c < 4; ++c) acc[c] += w * sm.W[el][ef][l1][js][c];
         }
         const float isj = sm.isj[el][f][q];
-        a.tr_out[slot * Nfq + q] = make_float4(acc[0] * isj, acc[1] * isj, acc[2] * isj, acc[3] * isj);
+        a.tr_out[slot * TS + q] = make_float4(acc[0] * isj, acc[1] * isj, acc[2] * isj, acc[3] * isj);
       }
     } else if (ph == 5) {
       for (int it = tid; it < EPB * 2 * Nfq; it += NT) {
@@ -387,7 +388,7 @@ struct WedgeStage {
           for (int c = 0; c < 4; ++c) acc[c] += w * sm.c[el][tf][l][c];
         }
         const float isj = sm.isj[el][tf][q];
-        a.tr_out[slot * Nfq + q] = make_float4(acc[0] * isj, acc[1] * isj, acc[2] * isj, acc[3] * isj);
+        a.tr_out[slot * TS + q] = make_float4(acc[0] * isj, acc[1] * isj, acc[2] * isj, acc[3] * isj);
       }
     }
   }

@@ -42,6 +42,7 @@ struct TetMfma {
   static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
   static constexpr int Nfn = (N + 1) * (N + 2) / 2;
   static constexpr int Nfq = (N + 1) * (N + 1);
+  static constexpr int TS = trace_stride(N), LW = lattice_width(N);
   static constexpr int Mt = (Np + 15) / 16;  // 16-row tiles of the element operators
   static constexpr int Ks = (Np + 3) / 4;    // k-steps over element nodes
   static constexpr int Kf = (Nfn + 3) / 4;   // k-steps over one face's lattice
@@ -188,7 +189,7 @@ struct TetMfma {
     const int src = n + 16 * f;
     const int nb = __shfl(rec.nb, src);
     const float4* nsrc = __shfl(rec.half, src) ? a.tr_half : a.tr_in;
-    const int64_t base = nb >= 0 ? (int64_t)nb * Nfq : (int64_t)(-nb - kNcBase) * Nfq;
+    const int64_t base = nb >= 0 ? (int64_t)nb * TS : (int64_t)(-nb - kNcBase) * TS;
     const bool fetch = nb >= 0 || nb <= -kNcBase;
 #pragma unroll
     for (int j = 0; j < JF; ++j) {
@@ -197,32 +198,47 @@ struct TetMfma {
     }
   }
 
-  // face-node values of the tile's state, canonical lattice order (LEAN:
-  // one face at a time, for callers with many registers in use)
+  // face-node values of the tile's state, canonical lattice order, padded
+  // with zeros to whole lines: lane (q, m) = (lane >> 4, lane & 15) writes
+  // entry m of element 4 k + q, so one store instruction covers the whole
+  // face traces of four elements (LEAN: one face at a time, for callers with
+  // many registers in use)
+  static constexpr int MJ = (LW + 15) / 16;  // entries m = (lane & 15) + 16 j per lane
   template <bool LEAN = false, class SM>
   __device__ static void write_traces(const SM& sm, const float (&X)[4][16][SX], const StageArgs& a, int64_t e0,
                                       int lane, const FaceRec& rec, float4* tr, bool col_active = true) {
-    const int n = lane & 15, g = lane >> 4;
-    const int64_t e = item(a, e0 + n);
     if constexpr (LEAN) {
 #pragma unroll 1
-      for (int f = 0; f < 4; ++f) trace_face(sm, X, a, e, n, g, f, __shfl(rec.ori, n + 16 * f), tr, col_active);
+      for (int f = 0; f < 4; ++f) trace_face(sm, X, a, e0, lane, f, rec, tr, col_active);
     } else {
 #pragma unroll
-      for (int f = 0; f < 4; ++f) trace_face(sm, X, a, e, n, g, f, __shfl(rec.ori, n + 16 * f), tr, col_active);
+      for (int f = 0; f < 4; ++f) trace_face(sm, X, a, e0, lane, f, rec, tr, col_active);
     }
   }
   template <class SM>
-  __device__ static void trace_face(const SM& sm, const float (&X)[4][16][SX], const StageArgs& a, int64_t e, int n,
-                                    int g, int f, int o, float4* tr, bool col_active) {
-    if (e < 0 || !col_active) return;
-    const int64_t slot = a.slot0 + e * 4 + f;
+  __device__ static void trace_face(const SM& sm, const float (&X)[4][16][SX], const StageArgs& a, int64_t e0,
+                                    int lane, int f, const FaceRec& rec, float4* tr, bool col_active) {
+    const int q = lane >> 4;
 #pragma unroll
-    for (int j = 0; j < JF; ++j) {
-      const int m = g + 4 * j;
-      if (m >= Nfn) continue;
-      const int node = sm.fnode[f][sm.tperm[o][m]];
-      tr[slot * Nfq + m] = make_float4(X[0][n][node], X[1][n][node], X[2][n][node], X[3][n][node]);
+    for (int k = 0; k < 4; ++k) {
+      const int n = 4 * k + q;
+      // orientation of face f of element n, and whether element n writes
+      const int o = __shfl(rec.ori, n + 16 * f);
+      const int act = __shfl((int)col_active, n);
+      const int64_t e = item(a, e0 + n);
+      if (e < 0 || !act) continue;
+      const int64_t base = (a.slot0 + e * 4 + f) * TS;
+#pragma unroll
+      for (int j = 0; j < MJ; ++j) {
+        const int m = (lane & 15) + 16 * j;
+        if (m >= LW) continue;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (m < Nfn) {
+          const int node = sm.fnode[f][sm.tperm[o][m]];
+          v = make_float4(X[0][n][node], X[1][n][node], X[2][n][node], X[3][n][node]);
+        }
+        tr[base + m] = v;
+      }
     }
   }
 
