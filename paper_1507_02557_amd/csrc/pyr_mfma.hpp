@@ -230,6 +230,8 @@ struct PyrMfma {
           const int l = 16 * t + 4 * g + i;
           if (e >= 0 && l < Nfq)
             tr[slot * TS + sm.iqperm[o][l]] = make_float4(acc[0][t][i], acc[1][t][i], acc[2][t][i], acc[3][t][i]);
+          else if (e >= 0 && l < TS)  // padding to whole lines
+            tr[slot * TS + l] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
     }
     // triangular faces: lattice values Ft_f u (rows = local lattice nodes)

@@ -98,6 +98,20 @@ HD inline int64_t item(const StageArgs& a, int64_t i) {
   return a.elist ? (int64_t)a.elist[i] : i;
 }
 
+// Zero padding of the trace slots written at cubature points: entries
+// [nfq, ts) of faces f0 .. f0 + nfaces - 1 of the batch's elements (nf faces
+// per element), so each slot goes to memory in whole lines.
+HD inline void pad_traces(const StageArgs& a, float4* tr, int tid, int nt, int64_t e0, int epb, int nf, int f0,
+                          int nfaces, int nfq, int ts) {
+  const int w = ts - nfq;
+  for (int it = tid; it < epb * nfaces * w; it += nt) {
+    const int el = it / (nfaces * w), r = it % (nfaces * w);
+    const int64_t e = item(a, e0 + el);
+    if (e < 0) continue;
+    tr[(a.slot0 + e * nf + f0 + r / w) * ts + nfq + r % w] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
 // Where a right-hand side goes: the rhs buffer, or the history slot of the
 // element's level.
 HD inline float* rhs_dst(const StageArgs& a, int64_t e, int Np) {

@@ -212,6 +212,7 @@ struct PyrStage {
         }
         a.tr_out[slot * TS + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
       }
+      pad_traces(a, a.tr_out, tid, NT, e0, EPB, 5, 0, 1, Nfq, TS);
       for (int it = tid; it < EPB * 4 * Nfn; it += NT) {
         const int el = it / (4 * Nfn), rr = it % (4 * Nfn);
         const int tf = rr / Nfn, l = rr % Nfn;
@@ -254,6 +255,7 @@ struct PyrStage {
         }
         a.tr_out[slot * TS + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
       }
+      pad_traces(a, a.tr_out, tid, NT, e0, EPB, 5, 1, 4, Nfq, TS);
     }
   }
 };

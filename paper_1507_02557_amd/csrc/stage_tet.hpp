@@ -180,6 +180,7 @@ struct TetStage {
         }
         a.tr_out[slot * TS + q] = make_float4(acc[0], acc[1], acc[2], acc[3]);
       }
+      pad_traces(a, a.tr_out, tid, NT, e0, EPB, 4, 0, 4, Nfq, TS);
     }
   }
 };

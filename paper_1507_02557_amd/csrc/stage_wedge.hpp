@@ -373,6 +373,7 @@ struct WedgeStage {
         const float isj = sm.isj[el][f][q];
         a.tr_out[slot * TS + q] = make_float4(acc[0] * isj, acc[1] * isj, acc[2] * isj, acc[3] * isj);
       }
+      pad_traces(a, a.tr_out, tid, NT, e0, EPB, 5, 2, 3, Nfq, TS);
     } else if (ph == 5) {
       for (int it = tid; it < EPB * 2 * Nfq; it += NT) {
         const int el = it / (2 * Nfq), rr = it % (2 * Nfq);
@@ -390,6 +391,7 @@ struct WedgeStage {
         const float isj = sm.isj[el][tf][q];
         a.tr_out[slot * TS + q] = make_float4(acc[0] * isj, acc[1] * isj, acc[2] * isj, acc[3] * isj);
       }
+      pad_traces(a, a.tr_out, tid, NT, e0, EPB, 5, 0, 2, Nfq, TS);
     }
   }
 };
