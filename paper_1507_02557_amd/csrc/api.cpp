@@ -199,6 +199,14 @@ int build_tables(hdg_ctx* c, int t, std::vector<float>& ops, std::vector<int>& i
     append(ops, P.Fquad);
     append(ops, P.Ftri);
     append(ops, ft.Ican);
+    // face-lattice mass matrix M_f = Ican^T W Ican over the weight of
+    // cubature point 0 (the kernels' face factor carries w_0 J^s)
+    for (int x = 0; x < ft.Nfn; ++x)
+      for (int y = 0; y < ft.Nfn; ++y) {
+        double v = 0.0;
+        for (int q = 0; q < ft.Nfq; ++q) v += ft.Ican[q * ft.Nfn + x] * ft.tri_w[q] * ft.Ican[q * ft.Nfn + y];
+        ops.push_back((float)(v / ft.tri_w[0]));
+      }
     iops.insert(iops.end(), ft.quad_perm.begin(), ft.quad_perm.end());
     iops.insert(iops.end(), ft.tri_perm.begin(), ft.tri_perm.end());
   } else {

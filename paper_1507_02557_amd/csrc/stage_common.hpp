@@ -177,14 +177,21 @@ HD inline void upwind_flux(float4 m, float4 p, float4 g, float2 tau, bool skew, 
   out[3] = fu * nz;
 }
 
-// Trace buffer holding the neighbour slot nb's current trace: a coarser
-// neighbour that is mid-step supplies its dense-output (mid-step) trace.
+// Whether the neighbour slot nb supplies its dense-output (mid-step) trace:
+// a coarser neighbour between its step boundaries.  Kernels that keep this
+// as a flag take it from here, never by comparing the buffer pointer that
+// neighbour_src returns (a pointer chosen in divergent control flow and then
+// compared has been compiled wrongly for gfx950: the tr_in branch's value
+// was lost).
+HD inline bool neighbour_mid(const StageArgs& a, int64_t slot, int nb) {
+  if (!a.mr.dense) return false;
+  const int ln = a.slevel[nb];
+  return ln < a.slevel[slot] && (a.mr.ksub & ((1 << (a.mr.L - ln)) - 1)) != 0;
+}
+
+// Trace buffer holding the neighbour slot nb's current trace.
 HD inline const float4* neighbour_src(const StageArgs& a, int64_t slot, int nb) {
-  if (a.mr.dense) {
-    const int ln = a.slevel[nb];
-    if (ln < a.slevel[slot] && (a.mr.ksub & ((1 << (a.mr.L - ln)) - 1)) != 0) return a.tr_half;
-  }
-  return a.tr_in;
+  return neighbour_mid(a, slot, nb) ? a.tr_half : a.tr_in;
 }
 
 // Own and neighbour traces at canonical point q of a slot (ts: trace stride).
@@ -196,24 +203,6 @@ HD inline void face_states(const StageArgs& a, int64_t slot, int ts, int q, floa
   } else {
     p = mirror_state(m, -nb - 1, g.x, g.y, g.z);
   }
-}
-
-// Same from lattice traces: values at canonical cubature point q are
-// interpolated from the canonical lattice values (Ican [nfq][nfn]).
-HD inline void face_states_lattice(const StageArgs& a, int64_t slot, int ts, int nfn, int q, const float* Ican,
-                                   float4 g, float4& m, float4& p) {
-  const float4* own = a.tr_in + slot * ts;
-  const int nb = a.nbr[slot];
-  const float4* nbv = nb >= 0 ? neighbour_src(a, slot, nb) + (int64_t)nb * ts : own;
-  float4 sm = make_float4(0.f, 0.f, 0.f, 0.f), sp = sm;
-  for (int j = 0; j < nfn; ++j) {
-    const float w = Ican[q * nfn + j];
-    const float4 x = own[j], y = nbv[j];
-    sm.x += w * x.x; sm.y += w * x.y; sm.z += w * x.z; sm.w += w * x.w;
-    sp.x += w * y.x; sp.y += w * y.y; sp.z += w * y.z; sp.w += w * y.w;
-  }
-  m = sm;
-  p = nb >= 0 ? sp : mirror_state(sm, -nb - 1, g.x, g.y, g.z);
 }
 
 // Multi-rate update of one batch, as a sequence of barrier-separated steps:

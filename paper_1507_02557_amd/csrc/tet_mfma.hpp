@@ -168,7 +168,7 @@ struct TetMfma {
     r.ori = a.ori[slot];
     r.g = a.fgeo[e * 4 + f];
     r.tau = a.tau[slot];
-    if (r.nb >= 0 && a.mr.dense) r.half = neighbour_src(a, slot, r.nb) == a.tr_half;
+    if (r.nb >= 0) r.half = neighbour_mid(a, slot, r.nb);
     return r;
   }
   __device__ static FaceRec shfl_rec(const FaceRec& r, int src) {
