@@ -427,11 +427,10 @@ bool use_lattice(const hdg_ctx* c) { return c->path == HDG_PATH_AUTO && c->latti
 int launch_type(hdg_ctx* c, int t, StageArgs a, bool mrab) {
   a.lat = use_lattice(c) ? 1 : 0;
   a.V = c->td[t].V;
-  // The matrix-core pyramid kernel serves the single-rate modes at N = 3, 4
-  // only: the multi-rate modes and N <= 2 stay on the vector kernel (a GPU
-  // memory fault was seen in a multi-rate run at N = 2 with it; cause not
-  // found).
-  const bool pyr_mfma = t == kPyr && a.lat && c->td[t].mops && !mrab && a.mode != kModeRhsHist && c->N >= 3;
+  // The matrix-core pyramid kernel serves the stage and right-hand-side
+  // modes at N = 3, 4 (the multi-rate right-hand side included); the
+  // multi-rate update and N <= 2 use the wavefront-batched vector kernels.
+  const bool pyr_mfma = t == kPyr && a.lat && c->td[t].mops && !mrab && c->N >= 3;
   if (pyr_mfma) {
     a.ops = c->td[t].mops;
     a.iops = c->td[t].miops;
