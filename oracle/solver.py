@@ -490,34 +490,40 @@ class Disc:
         _, _, Jv, _ = OM.vertex_map(E, corners, self.V[t])
         return np.minimum(np.min(J, axis=1), np.min(Jv, axis=1))
 
-    def dt_elements(self, cfl: float = 0.5):
-        """Local stable steps dtau_K = C / (C_rhokappa C_T(N) C_J^K) (Section 3, eq. dtK)."""
-        out = {}
+    def c_rhokappa(self):
+        """C_rhokappa^K = max(tau_p,K kappa_K, tau_u,K / rho_K) per element
+        (Section 3.4), with tau_p,K, tau_u,K the maxima over the element's faces
+        (sub-faces for a coarse non-conforming face, whose own slot is left out)."""
         rc_own = self.rhoc[self.slot_elem]
         rc_nb = rc_own.copy()
         inner = self.nbr >= 0
         rc_nb[inner] = self.rhoc[self.slot_elem[self.nbr[inner]]]
         avg = 0.5 * (rc_own + rc_nb)
-        # penalty maxima over each element's faces (sub-faces for a coarse
-        # non-conforming face, whose own slot is left out)
         ne = self.kappa.shape[0]
         use = ~self.is_parent
         taup_e = np.zeros(ne)
         tauu_e = np.zeros(ne)
         np.maximum.at(taup_e, self.slot_elem[use], 1.0 / avg[use])
         np.maximum.at(tauu_e, self.slot_elem[use], avg[use])
+        out = {}
+        for t in self.types:
+            e = self.els[t]
+            out[t] = np.maximum(taup_e[e] * self.kappa[e], tauu_e[e] / self.rho[e])
+        return out
+
+    def dt_elements(self, cfl: float = 0.5):
+        """Local stable steps dtau_K = C / (C_rhokappa C_T(N) C_J^K) (Section 3, eq. dtK)."""
+        out = {}
+        crk = self.c_rhokappa()
         for t in self.types:
             sl = self.slot[t]
             e = self.els[t]
-            tau_p = taup_e[e]
-            tau_u = tauu_e[e]
-            c_rk = np.maximum(tau_p * self.kappa[e], tau_u / self.rho[e])
             jsr = self.Js_ref[sl]                      # (K, nf, Nfq)
             if t == R.WEDGE:
                 cj = np.max((jsr / self.fJ[sl]).reshape(e.size, -1), axis=1)
             else:
                 cj = np.max(jsr.reshape(e.size, -1), axis=1) / self.min_jacobian(t)
-            out[t] = cfl / (c_rk * trace_constant(t, self.N) * cj)
+            out[t] = cfl / (crk[t] * trace_constant(t, self.N) * cj)
         return out
 
     def dt_min(self, cfl: float = 0.5):
