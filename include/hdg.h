@@ -227,6 +227,34 @@ int hdg_rhs(hdg_ctx* ctx);
  * type and stage.  Asynchronous on the context's stream. */
 int hdg_step(hdg_ctx* ctx, double dt, int64_t n_steps);
 
+/* Time-step constants (Section 3.4).  HDG_DT_REFERENCE: the local step of
+ * eq. dtK with the reference element's computed C_T(N) (Appendix B, Table
+ * computedTrace) times C_J^K.  HDG_DT_ELEMENT: the mapped element's own
+ * trace constant, dtau_K = C / (C_rhokappa^K C_T(N, K)), which Section 3.4
+ * (Table bounds) shows to be the tighter bound; it never gives a shorter
+ * step, since C_T(N, K) <= C_T(N) C_J^K. */
+#define HDG_DT_REFERENCE 0
+#define HDG_DT_ELEMENT 1
+
+/* Per-element trace-inequality constants C_T(N, K) (Section 3.2; Section 3.4,
+ * the "computed C_T(N,K)" row of Table bounds): the largest eigenvalue of
+ * M_s,K v = lambda M_K v, with M_K the element's mass matrix of the method and
+ * M_s,K = sum over its faces of sum_q w_q J^s_q phi_i(x_q) phi_j(x_q) on the
+ * faces' canonical cubature rules (wedges: the LSC basis phi / sqrt(J); a
+ * coarse non-conforming face with its own rule, exact for the degree-2N
+ * integrand).  Computed on the device in FP64 (Lanczos per element on
+ * M^-1/2 M_s M^-1/2, largest Ritz value by Sturm multisection) from the
+ * stored FP32 geometric factors (relative accuracy about 1e-7), once per
+ * context and cached.  out (host, double [n_elem], mesh order) receives them.
+ * Synchronises the stream.  Errors: HDG_EINVAL (NULL), HDG_ENOMEM, HDG_EHIP. */
+int hdg_trace_constants(hdg_ctx* ctx, double* out);
+
+/* Select the constants hdg_dt, hdg_mrab_setup and hdg_advance use
+ * (HDG_DT_REFERENCE, the default, or HDG_DT_ELEMENT, which computes the
+ * per-element constants if needed).  Errors: HDG_EINVAL (NULL, unknown mode),
+ * those of hdg_trace_constants. */
+int hdg_set_dt_mode(hdg_ctx* ctx, int mode);
+
 /* Multi-rate set-up (Section 2.4).  Levels l = 1 (coarsest) .. L = n_levels
  * (1 <= L <= 8) with dtau_l = 2^(L-l) dtau_min, dtau_min the smallest local
  * step of hdg_dt(cfl).  Each element takes the coarsest level whose step does

@@ -39,9 +39,11 @@ def ab3_beta(theta: float) -> np.ndarray:
     return np.array([t + 0.75 * t * t + t ** 3 / 6.0, -(t * t + t ** 3 / 3.0), 0.25 * t * t + t ** 3 / 6.0])
 
 
-def bin_levels(disc: Disc, L: int, cfl: float = 0.5):
-    """Level per element (dict type -> int array) and dtau_min."""
-    dte = disc.dt_elements(cfl)
+def bin_levels(disc: Disc, L: int, cfl: float = 0.5, dte=None):
+    """Level per element (dict type -> int array) and dtau_min, from the local
+    steps dte (dict type -> array; default: Disc.dt_elements)."""
+    if dte is None:
+        dte = disc.dt_elements(cfl)
     dtmin = min(float(np.min(v)) for v in dte.values())
     ne = sum(disc.els[t].size for t in disc.types)
     lev = np.zeros(ne, dtype=np.int64)
@@ -73,10 +75,10 @@ def bin_levels(disc: Disc, L: int, cfl: float = 0.5):
 class MRAB3:
     """Multi-rate AB3 integrator over a Disc."""
 
-    def __init__(self, disc: Disc, L: int, cfl: float = 0.5):
+    def __init__(self, disc: Disc, L: int, cfl: float = 0.5, dte=None):
         self.d = disc
         self.L = L
-        self.level, self.dtmin = bin_levels(disc, L, cfl)
+        self.level, self.dtmin = bin_levels(disc, L, cfl, dte)
         self.dtl = {l: (2 ** (L - l)) * self.dtmin for l in range(1, L + 1)}
         self.hist = {t: np.zeros((3,) + disc.zeros()[t].shape) for t in disc.types}
         self.count = {l: 0 for l in range(1, L + 1)}  # right-hand sides pushed per level

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhdg.so")
 SOURCES = ["refel.cpp", "api.cpp", "setup_kernels.hip", "stages.hip", "tet_mfma.hip", "pyr_mfma.hip",
-           "mortar.hip"]
+           "mortar.hip", "trace_const.hip"]
 # Packed FP32 instructions are disabled for all device code.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

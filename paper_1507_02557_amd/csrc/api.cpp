@@ -56,6 +56,7 @@ struct TypeData {
   double* gpts = nullptr;      // pyramid geometry points [Np][3]
   double* Mhat = nullptr;      // tet reference mass
   std::vector<double> cJ, minJ, crk;
+  std::vector<double> ctk;      // computed trace constant C_T(N, K) per element (empty until computed)
   // multi-rate
   int* elist = nullptr;        // elements sorted by level, finest first
   bool elist_identity = false; // the sorted order is the storage order (no indirection needed)
@@ -111,6 +112,7 @@ struct hdg_ctx {
   double mr_dtmin0 = 0.0;      // dtau_min of hdg_mrab_setup (hdg_advance may scale it down)
   std::vector<int8_t> level_h; // multi-rate level per element (mesh order)
   std::vector<int8_t> half_h;  // 1: the element writes mid-step traces (mesh order)
+  int dt_mode = HDG_DT_REFERENCE;  // local steps from the reference or the per-element trace constants
   double* pscratch = nullptr;  // fixed work buffer of hdg_project_noalloc on this context's GPU
   // 1:4 non-conforming faces: slots [nslot0, nslot0 + 4 n_nc) are the
   // virtual slots (the coarse trace at a sub-face, read by the fine
@@ -1130,6 +1132,174 @@ int hdg_type_info(const hdg_ctx* c, int t, int64_t* n_elem, int32_t* np, int32_t
   return HDG_OK;
 }
 
+namespace {
+
+// Element basis of type t at the canonical cubature points of every face and
+// orientation: V [nf][8][Nfq][Np] (FP64), built from the same reference
+// tables and local-point conventions as the stage kernels' trace
+// evaluation (hexahedra: 1D extrapolation along the lines through the face
+// points; wedges: triangle basis at the edge points times the 1D basis in s,
+// or at the lattice times the 1D basis at s = -1, +1; pyramids: the base
+// basis at its GL points, the triangle faces through the lattice;
+// tetrahedra: the face nodes through the lattice).
+void build_face_bases(const hdg_ctx* c, int t, std::vector<double>& V) {
+  const FaceTables& ft = c->ft;
+  const int Nfq = ft.Nfq, Nfn = ft.Nfn, n1 = ft.n1;
+  const int Np = np_of(t, c->N);
+  const ElemDesc& E = elem_desc(t);
+  V.assign((size_t)E.nf * 8 * Nfq * Np, 0.0);
+  for (int f = 0; f < E.nf; ++f) {
+    const bool tri = E.fnv[f] == 3;
+    for (int o = 0; o < (tri ? 6 : 8); ++o)
+      for (int q = 0; q < Nfq; ++q) {
+        double* row = V.data() + ((size_t)(f * 8 + o) * Nfq + q) * Np;
+        if (!tri) {
+          const int l = ft.quad_perm[o * Nfq + q], l1 = l % n1, l2 = l / n1;
+          if (t == kHex) {
+            const Vec& L = (f & 1) ? c->hex.Lp : c->hex.Lm;
+            for (int m = 0; m < n1; ++m) {
+              const int node = f < 2 ? m + n1 * (l1 + n1 * l2) : (f < 4 ? l1 + n1 * (m + n1 * l2) : l1 + n1 * (l2 + n1 * m));
+              row[node] = L[m];
+            }
+          } else if (t == kWedge) {
+            const WedgeRef& W = c->wedge;
+            const int ef = f - 2;
+            for (int js = 0; js < n1; ++js)
+              for (int jt = 0; jt < W.Ntri; ++jt)
+                row[js * W.Ntri + jt] = W.P1[l2 * n1 + js] * W.Fedge[((size_t)ef * n1 + l1) * W.Ntri + jt];
+          } else {  // pyramid base
+            for (int j = 0; j < Np; ++j) row[j] = c->pyr.Fquad[(size_t)l * Np + j];
+          }
+        } else {
+          for (int m = 0; m < Nfn; ++m) {
+            const double w = ft.Ican[q * Nfn + m];
+            const int lm = ft.tri_perm[o * Nfn + m];
+            if (t == kWedge) {
+              const WedgeRef& W = c->wedge;
+              const Vec& P1s = f == 0 ? W.P1m : W.P1p;
+              for (int js = 0; js < n1; ++js)
+                for (int jt = 0; jt < W.Ntri; ++jt)
+                  row[js * W.Ntri + jt] += w * W.Ftri[(size_t)lm * W.Ntri + jt] * P1s[js];
+            } else if (t == kPyr) {
+              for (int j = 0; j < Np; ++j) row[j] += w * c->pyr.Ftri[((size_t)(f - 1) * Nfn + lm) * Np + j];
+            } else {  // tetrahedron
+              row[c->tet.fnode[f * Nfn + lm]] += w;
+            }
+          }
+        }
+      }
+  }
+}
+
+// C_T(N, K) of every element on the device (once per context).
+int compute_trace_constants(hdg_ctx* c) {
+  bool done = true;
+  for (int t = 0; t < 4; ++t)
+    if (c->td[t].present && c->td[t].ctk.size() != (size_t)c->td[t].K) done = false;
+  if (done) return HDG_OK;
+  int rc = HDG_OK;
+  for (int t = 0; t < 4 && rc == HDG_OK; ++t) {
+    TypeData& d = c->td[t];
+    if (!d.present) continue;
+    std::vector<double> V;
+    build_face_bases(c, t, V);
+    std::vector<double> Linv;
+    if (t == kTet) {
+      // Mhat = L L^T; the kernel applies L^-1 and L^-T
+      const int n = d.Np;
+      const Vec& M = c->tet.Mhat;
+      std::vector<double> L((size_t)n * n, 0.0);
+      for (int j = 0; j < n; ++j) {
+        double dg = M[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) dg -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(dg > 0.0)) return fail(c, HDG_EINVAL, "internal: tetrahedron mass matrix is not positive definite");
+        L[(size_t)j * n + j] = std::sqrt(dg);
+        for (int i = j + 1; i < n; ++i) {
+          double v = M[(size_t)i * n + j];
+          for (int k = 0; k < j; ++k) v -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+          L[(size_t)i * n + j] = v / L[(size_t)j * n + j];
+        }
+      }
+      Linv.assign((size_t)n * n, 0.0);
+      for (int j = 0; j < n; ++j) {  // forward substitution, column j of L^-1
+        for (int i = j; i < n; ++i) {
+          double v = i == j ? 1.0 : 0.0;
+          for (int k = j; k < i; ++k) v -= L[(size_t)i * n + k] * Linv[(size_t)k * n + j];
+          Linv[(size_t)i * n + j] = v / L[(size_t)i * n + i];
+        }
+      }
+    }
+    double *dV = nullptr, *dW = nullptr, *dL = nullptr, *dout = nullptr;
+    auto put = [&](double** p, const std::vector<double>& h) -> int {
+      if (h.empty()) return HDG_OK;
+      if (hipMalloc((void**)p, h.size() * sizeof(double)) != hipSuccess) return fail(c, HDG_ENOMEM, "trace constant tables");
+      if (hipMemcpyAsync(*p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return fail(c, HDG_EHIP, "trace constant tables");
+      return HDG_OK;
+    };
+    rc = put(&dV, V);
+    if (rc == HDG_OK) rc = put(&dW, c->ft.tri_w);
+    if (rc == HDG_OK) rc = put(&dL, Linv);
+    if (rc == HDG_OK && hipMalloc((void**)&dout, (size_t)d.K * sizeof(double)) != hipSuccess)
+      rc = fail(c, HDG_ENOMEM, "trace constant output");
+    if (rc == HDG_OK) {
+      TraceConstArgs a{};
+      a.type = t;
+      a.K = d.K;
+      a.Np = d.Np;
+      a.nf = d.nf;
+      a.Nfq = c->ft.Nfq;
+      a.iters = 96;
+      a.V = dV;
+      a.tri_w = dW;
+      a.Linv = dL;
+      a.geo = d.geo;
+      a.fgeo = d.fgeo;
+      a.isqJ = d.isqJ;
+      a.ori = c->ori;
+      a.slot0 = d.slot0;
+      a.out = dout;
+      launch_trace_constants(a, c->stream);
+      d.ctk.resize(d.K);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(d.ctk.data(), dout, (size_t)d.K * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) {
+        d.ctk.clear();
+        rc = fail(c, HDG_EHIP, std::string("trace constants: ") + hipGetErrorString(e));
+      }
+    }
+    for (double* p : {dV, dW, dL, dout})
+      if (p) (void)hipFree(p);
+  }
+  return rc;
+}
+
+}  // namespace
+
+int hdg_trace_constants(hdg_ctx* c, double* out) {
+  if (!c || !out) return HDG_EINVAL;
+  int rc = compute_trace_constants(c);
+  if (rc) return rc;
+  for (int t = 0; t < 4; ++t) {
+    const TypeData& d = c->td[t];
+    for (int64_t k = 0; k < d.K; ++k) out[d.elems[k]] = d.ctk[k];
+  }
+  return HDG_OK;
+}
+
+int hdg_set_dt_mode(hdg_ctx* c, int mode) {
+  if (!c) return HDG_EINVAL;
+  if (mode != HDG_DT_REFERENCE && mode != HDG_DT_ELEMENT) return fail(c, HDG_EINVAL, "unknown time step mode");
+  if (mode == HDG_DT_ELEMENT) {
+    const int rc = compute_trace_constants(c);
+    if (rc) return rc;
+  }
+  c->dt_mode = mode;
+  return HDG_OK;
+}
+
 int hdg_dt(hdg_ctx* c, double cfl, double* dt_out, double* dt_min_out) {
   if (!c) return HDG_EINVAL;
   if (!(cfl > 0.0)) return fail(c, HDG_EINVAL, "CFL constant must be positive");
@@ -1137,8 +1307,9 @@ int hdg_dt(hdg_ctx* c, double cfl, double* dt_out, double* dt_min_out) {
   for (int t = 0; t < 4; ++t) {
     const TypeData& d = c->td[t];
     const double ct = trace_constant(t, c->N);
+    const bool elem = c->dt_mode == HDG_DT_ELEMENT;
     for (int64_t k = 0; k < d.K; ++k) {
-      const double dt = cfl / (d.crk[k] * ct * d.cJ[k]);
+      const double dt = elem ? cfl / (d.crk[k] * d.ctk[k]) : cfl / (d.crk[k] * ct * d.cJ[k]);
       if (dt_out) dt_out[d.elems[k]] = dt;
       mn = std::min(mn, dt);
     }

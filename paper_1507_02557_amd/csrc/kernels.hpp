@@ -59,6 +59,23 @@ struct MortarArgs {
 };
 void launch_mortar(const MortarArgs& a, hipStream_t s);
 
+// Per-element trace constants C_T(N, K) of one element type (FP64).
+struct TraceConstArgs {
+  int type;
+  int64_t K;
+  int Np, nf, Nfq, iters;
+  const double* V;        // [nf][8][Nfq][Np] element basis at canonical face points per orientation
+  const double* tri_w;    // [Nfq] canonical triangle weights (tetrahedra)
+  const double* Linv;     // tetrahedra: inverse of the Cholesky factor of Mhat [Np][Np] (lower)
+  const float* geo;       // stored geometric factors of the type
+  const float4* fgeo;     // face factors (n, w J^s) or, for tetrahedra, (n, J^s) per face
+  const float* isqJ;      // wedges: 1 / sqrt(J) at face points
+  const int8_t* ori;      // orientation codes per slot
+  int64_t slot0;
+  double* out;            // [K]
+};
+void launch_trace_constants(const TraceConstArgs& a, hipStream_t s);
+
 void launch_geometry(const GeoArgs& g, hipStream_t s);
 void launch_points(int type, int64_t K, int nv, const double* V, const double* pts, int npts, double* out,
                    hipStream_t s);

@@ -17,6 +17,7 @@ HEX, WEDGE, PYR, TET = 0, 1, 2, 3
 BC_FREE_SURFACE, BC_RIGID_WALL = 0, 1
 PREC_FP32, PREC_FP16X2, PREC_FP16X2_K16, PREC_BF16X2, PREC_BF16X3 = 0, 1, 2, 3, 4
 PATH_AUTO, PATH_GENERIC = 0, 1
+DT_REFERENCE, DT_ELEMENT = 0, 1
 STEPPER_LSERK4, STEPPER_MRAB3 = 0, 1
 PROJECT_SCRATCH_BYTES = 16 * 1024 * 1024  # HDG_PROJECT_SCRATCH_BYTES
 OK, EINVAL, EMESH, ENOMEM, EHIP, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
@@ -52,6 +53,8 @@ _SIGS = [
     ("hdg_mrab_setup", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _P, _P]),
     ("hdg_mrab_advance", ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     ("hdg_mrab_level_info", ctypes.c_int, [_P, _P]),
+    ("hdg_trace_constants", ctypes.c_int, [_P, _P]),
+    ("hdg_set_dt_mode", ctypes.c_int, [_P, ctypes.c_int]),
     ("hdg_profile", ctypes.c_int, [_P, ctypes.c_int]),
     ("hdg_profile_read", ctypes.c_int, [_P, _P, _P]),
     ("hdg_set_path", ctypes.c_int, [_P, ctypes.c_int]),
@@ -252,6 +255,16 @@ class Solver:
         self._check(self._lib.hdg_mrab_setup(self._h, n_levels, cfl, ctypes.byref(mn), cnt.ctypes.data,
                                              lev.ctypes.data))
         return mn.value, cnt, lev
+
+    def trace_constants(self):
+        """Per-element computed trace constants C_T(N, K) (n_elem,), mesh order."""
+        out = np.zeros(self.n_elem, dtype=np.float64)
+        self._check(self._lib.hdg_trace_constants(self._h, out.ctypes.data))
+        return out
+
+    def set_dt_mode(self, mode: int):
+        """DT_REFERENCE (C_T(N) C_J^K) or DT_ELEMENT (per-element C_T(N, K))."""
+        self._check(self._lib.hdg_set_dt_mode(self._h, int(mode)))
 
     def mrab_level_info(self, n_levels: int):
         """(4, n_levels, 2) int64: per type and level, the element count and the

@@ -124,6 +124,8 @@ def test_calls_on_a_null_context_are_rejected():
     assert lib.hdg_project_noalloc(None, 0, None, None, None, None) == hdg.EINVAL
     assert lib.hdg_project(None, 0, None, None, None, None) == hdg.EINVAL
     assert lib.hdg_mrab_level_info(None, buf) == hdg.EINVAL
+    assert lib.hdg_trace_constants(None, buf) == hdg.EINVAL
+    assert lib.hdg_set_dt_mode(None, hdg.DT_ELEMENT) == hdg.EINVAL
 
 
 def test_header_scratch_size_matches_binding():
