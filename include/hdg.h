@@ -227,6 +227,17 @@ int hdg_rhs(hdg_ctx* ctx);
  * type and stage.  Asynchronous on the context's stream. */
 int hdg_step(hdg_ctx* ctx, double dt, int64_t n_steps);
 
+/* hdg_step through a HIP graph: two steps (ten stage launches per element
+ * type, with the interface kernel) are captured once on the context's stream
+ * and the graph is replayed n_steps / 2 times; an odd last step runs as
+ * hdg_step.  The graph is kept for later calls with the same dt (and path)
+ * and released by hdg_destroy.  Results are bitwise those of hdg_step: the
+ * same kernels with the same arguments.  For many small problems batched
+ * into one mesh (disjoint union: one launch per type and stage for all of
+ * them) it removes the per-launch host cost.  Errors: HDG_EINVAL (dt <= 0,
+ * n_steps < 0), HDG_ESTATE (profiling on), HDG_EHIP (capture or launch). */
+int hdg_step_graph(hdg_ctx* ctx, double dt, int64_t n_steps);
+
 /* Time-step constants (Section 3.4).  HDG_DT_REFERENCE: the local step of
  * eq. dtK with the reference element's computed C_T(N) (Appendix B, Table
  * computedTrace) times C_J^K.  HDG_DT_ELEMENT: the mapped element's own

@@ -113,6 +113,12 @@ struct hdg_ctx {
   std::vector<int8_t> level_h; // multi-rate level per element (mesh order)
   std::vector<int8_t> half_h;  // 1: the element writes mid-step traces (mesh order)
   int dt_mode = HDG_DT_REFERENCE;  // local steps from the reference or the per-element trace constants
+  // captured graph of two LSERK4 steps (ten stages, so the trace buffers
+  // come back to the captured parity) for hdg_step_graph
+  hipGraphExec_t graph = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
+  double graph_dt = 0.0;
+  int graph_cur = -1, graph_path = -1;
   double* pscratch = nullptr;  // fixed work buffer of hdg_project_noalloc on this context's GPU
   // 1:4 non-conforming faces: slots [nslot0, nslot0 + 4 n_nc) are the
   // virtual slots (the coarse trace at a sub-face, read by the fine
@@ -1117,6 +1123,8 @@ void hdg_destroy(hdg_ctx* c) {
     (void)hipEventDestroy(p[0]);
     (void)hipEventDestroy(p[1]);
   }
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (void* p : c->allocs) (void)hipFree(p);
   delete c;
 }
@@ -1415,6 +1423,62 @@ int hdg_step(hdg_ctx* c, double dt, int64_t n_steps) {
       if ((rc = run_stage(c, kModeStage, (float)kRkA[s], (float)kRkB[s], (float)dt))) return rc;
     c->time += dt;
   }
+  return HDG_OK;
+}
+
+int hdg_step_graph(hdg_ctx* c, double dt, int64_t n_steps) {
+  if (!c) return HDG_EINVAL;
+  if (!(dt > 0.0) || n_steps < 0) return fail(c, HDG_EINVAL, "dt must be positive and n_steps >= 0");
+  if (c->prof) return fail(c, HDG_ESTATE, "profiling is on: use hdg_step");
+  int rc = ensure_traces(c);
+  if (rc) return rc;
+  c->mr_ready = false;
+  const int64_t pairs = n_steps / 2;
+  if (pairs > 0) {
+    if (!c->graph || c->graph_dt != dt || c->graph_cur != c->cur || c->graph_path != c->path) {
+      if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+      }
+      const int cur0 = c->cur;
+      // the context's stream may be the default stream, which cannot be
+      // captured: capture on a private stream (the graph is launched on the
+      // context's stream, after the work already enqueued there)
+      if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      hipStream_t user = c->stream;
+      c->stream = c->cap_stream;
+      const hipError_t eb = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+      if (eb != hipSuccess) {
+        c->stream = user;
+        return fail(c, HDG_EHIP, std::string("graph capture: ") + hipGetErrorString(eb));
+      }
+      for (int n = 0; n < 2 && rc == HDG_OK; ++n)
+        for (int st = 0; st < 5 && rc == HDG_OK; ++st)
+          rc = run_stage(c, kModeStage, (float)kRkA[st], (float)kRkB[st], (float)dt);
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(c->stream, &g);
+      c->stream = user;
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        c->cur = cur0;
+        return rc;
+      }
+      if (ec != hipSuccess) return fail(c, HDG_EHIP, std::string("graph capture: ") + hipGetErrorString(ec));
+      const hipError_t ei = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        c->graph = nullptr;
+        return fail(c, HDG_EHIP, std::string("graph instantiation: ") + hipGetErrorString(ei));
+      }
+      c->graph_dt = dt;
+      c->graph_cur = cur0;
+      c->graph_path = c->path;
+      // ten stages leave the buffer parity where it was
+    }
+    for (int64_t k = 0; k < pairs; ++k) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+    c->time += 2.0 * dt * (double)pairs;
+  }
+  if (n_steps % 2) return hdg_step(c, dt, 1);
   return HDG_OK;
 }
 

@@ -54,6 +54,7 @@ _SIGS = [
     ("hdg_mrab_advance", ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     ("hdg_mrab_level_info", ctypes.c_int, [_P, _P]),
     ("hdg_trace_constants", ctypes.c_int, [_P, _P]),
+    ("hdg_step_graph", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int64]),
     ("hdg_set_dt_mode", ctypes.c_int, [_P, ctypes.c_int]),
     ("hdg_profile", ctypes.c_int, [_P, ctypes.c_int]),
     ("hdg_profile_read", ctypes.c_int, [_P, _P, _P]),
@@ -206,6 +207,10 @@ class Solver:
 
     def step(self, dt: float, n_steps: int = 1):
         self._check(self._lib.hdg_step(self._h, float(dt), int(n_steps)))
+
+    def step_graph(self, dt: float, n_steps: int):
+        """n_steps LSERK4 steps replayed from a captured HIP graph (bitwise those of step)."""
+        self._check(self._lib.hdg_step_graph(self._h, float(dt), int(n_steps)))
 
     def energy(self) -> float:
         E = ctypes.c_double()

@@ -120,6 +120,36 @@ class Mesh:
         return np.lexsort((np.arange(self.n_elem), -level, self.etype.astype(np.int64)))
 
 
+def batch_meshes(meshes) -> tuple:
+    """Disjoint union of several meshes (one batch of independent problems):
+    vertex ids of mesh b are offset by the vertices before it, its elements
+    follow those of the meshes before it.  Within each part the order of the
+    global vertex ids is kept, so every face keeps its canonical frame.
+    Returns (mesh, element offsets [B + 1], vertex offsets [B + 1])."""
+    xyz, et, ev, ka, rh, hang, bcf = [], [], [], [], [], [], []
+    voff, eoff = [0], [0]
+    any_bc = any(m.bc_face is not None for m in meshes)
+    for m in meshes:
+        v0 = voff[-1]
+        xyz.append(np.asarray(m.xyz, dtype=np.float64))
+        et.append(np.asarray(m.etype, dtype=np.int8))
+        e = np.asarray(m.everts, dtype=np.int64)
+        ev.append(np.where(e >= 0, e + v0, -1))
+        ka.append(np.asarray(m.kappa, dtype=np.float64))
+        rh.append(np.asarray(m.rho, dtype=np.float64))
+        h = np.asarray(m.hanging, dtype=np.int64).reshape(-1, 3)
+        hang.append(h + v0)
+        if any_bc:
+            bcf.append(np.full((m.n_elem, 6), -1, dtype=np.int8) if m.bc_face is None
+                       else np.asarray(m.bc_face, dtype=np.int8))
+        voff.append(v0 + m.xyz.shape[0])
+        eoff.append(eoff[-1] + m.n_elem)
+    out = Mesh(xyz=np.concatenate(xyz), etype=np.concatenate(et), everts=np.concatenate(ev),
+               kappa=np.concatenate(ka), rho=np.concatenate(rh), n=0, info={"batch": len(meshes)},
+               hanging=np.concatenate(hang), bc_face=np.concatenate(bcf) if any_bc else None)
+    return out, np.asarray(eoff, dtype=np.int64), np.asarray(voff, dtype=np.int64)
+
+
 def _slab_of_layer(n: int, layer: int, nslab: int) -> int:
     for k in range(nslab):
         lo = int(round(k * n / nslab))

@@ -46,3 +46,21 @@ def test_seed_reproducible():
     b = four_slab_mesh(4, seed=11)
     c = four_slab_mesh(4, seed=12)
     assert np.array_equal(a.xyz, b.xyz) and not np.array_equal(a.xyz, c.xyz)
+
+
+def test_batch_of_meshes_is_their_disjoint_union():
+    from paper_1507_02557_amd.inputs import batch_meshes
+    parts = [four_slab_mesh(4, seed=1, jitter=0.1), four_slab_mesh(4, seed=2, jitter=0.1, refine_last=2),
+             four_slab_mesh(8, seed=3, jitter=0.1)]
+    m, eoff, voff = batch_meshes(parts)
+    assert m.n_elem == sum(p.n_elem for p in parts) == eoff[-1]
+    assert m.xyz.shape[0] == sum(p.xyz.shape[0] for p in parts) == voff[-1]
+    for b, p in enumerate(parts):
+        sl = slice(eoff[b], eoff[b + 1])
+        assert np.array_equal(m.etype[sl], p.etype)
+        ev = m.everts[sl]
+        assert np.array_equal(np.where(ev >= 0, ev - voff[b], -1), p.everts)
+        used = ev[ev >= 0]
+        assert used.min() >= voff[b] and used.max() < voff[b + 1]  # no shared vertices
+        assert np.array_equal(m.xyz[voff[b]:voff[b + 1]], p.xyz)
+    assert m.hanging.shape[0] == sum(p.hanging.shape[0] for p in parts)
