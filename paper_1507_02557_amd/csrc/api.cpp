@@ -36,6 +36,10 @@ const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 136
 struct TypeData {
   int present = 0;
   int64_t K = 0;
+  // Field stride in elements: K rounded up to a multiple of 4, so that each
+  // of the four fields of U, R and H starts 16-byte aligned and element tiles
+  // move as float4 vectors whatever K is (the pad elements stay zero).
+  int64_t Ks = 0;
   int Np = 0, nf = 0, nv = 0, nsample = 0, nvp = 0;
   std::vector<int64_t> elems;  // global element ids in mesh order
   int64_t slot0 = 0;
@@ -62,7 +66,7 @@ struct TypeData {
   bool elist_identity = false; // the sorted order is the storage order (no indirection needed)
   int8_t* elevel = nullptr;    // level per element
   int8_t* ehalf = nullptr;     // 1: a face neighbour is on a finer level (reads the mid-step traces)
-  float* H = nullptr;          // right-hand-side history [3][4][K][Np]
+  float* H = nullptr;          // right-hand-side history [3][4][Ks][Np]
   int64_t n_from[10] = {};     // number of elements with level >= l
 };
 
@@ -468,7 +472,7 @@ int ensure_traces(hdg_ctx* c) {
     TypeData& d = c->td[t];
     if (!d.present) continue;
     StageArgs a{};
-    a.K = d.K;
+    a.K = d.Ks;
     a.n_items = d.K;
     a.U = d.U;
     a.R = d.R;
@@ -553,7 +557,7 @@ int run_stage(hdg_ctx* c, int mode, float ra, float rb, float dt) {
     TypeData& d = c->td[t];
     if (!d.present) continue;
     StageArgs a{};
-    a.K = d.K;
+    a.K = d.Ks;
     a.n_items = d.K;
     a.U = d.U;
     a.R = d.R;
@@ -1058,7 +1062,8 @@ int create_impl(hdg_ctx* c, const hdg_mesh* m, int N) {
       if ((rc = upload(c, &d.mops, ops))) return rc;
       if ((rc = upload(c, &d.miops, iops))) return rc;
     }
-    const size_t nstate = (size_t)4 * K * d.Np;
+    d.Ks = (K + 3) / 4 * 4;
+    const size_t nstate = (size_t)4 * d.Ks * d.Np;
     if ((rc = dalloc(c, &d.U, nstate))) return rc;
     if ((rc = dalloc(c, &d.R, nstate))) return rc;
     HIPCHK(c, hipMemsetAsync(d.U, 0, nstate * sizeof(float), c->stream));
@@ -1344,8 +1349,8 @@ int hdg_project(hdg_ctx* c, int t, const double* p, const double* ux, const doub
     if (hipMalloc((void**)&tmp, (size_t)4 * d.K * d.nsample * sizeof(double)) != hipSuccess)
       return fail(c, HDG_ENOMEM, "projection scratch allocation failed");
   }
-  launch_project(t, d.K, d.nv, d.V, d.spts, d.sw, d.nsample, d.Np, d.Phi, d.gpts, p, ux, uy, uz, tmp, d.K, d.U,
-                 c->stream);
+  launch_project(t, d.K, d.nv, d.V, d.spts, d.sw, d.nsample, d.Np, d.Phi, d.gpts, p, ux, uy, uz, tmp, d.K, d.Ks,
+                 d.U, c->stream);
   hipError_t e = hipGetLastError();
   if (tmp) {
     const hipError_t es = hipStreamSynchronize(c->stream);
@@ -1372,7 +1377,7 @@ int hdg_project_noalloc(hdg_ctx* c, int t, const double* p, const double* ux, co
     chunk = kProjectScratchBytes / per_elem;
   }
   launch_project(t, d.K, d.nv, d.V, d.spts, d.sw, d.nsample, d.Np, d.Phi, d.gpts, p, ux, uy, uz, c->pscratch,
-                 chunk, d.U, c->stream);
+                 chunk, d.Ks, d.U, c->stream);
   HIPCHK(c, hipGetLastError());
   c->traces_valid = false;
   c->mr_ready = false;
@@ -1383,10 +1388,10 @@ int hdg_set_state(hdg_ctx* c, int t, const float* p, const float* ux, const floa
   if (!c) return HDG_EINVAL;
   if (check_type(c, t) || !p || !ux || !uy || !uz) return fail(c, HDG_EINVAL, "bad type or NULL input");
   TypeData& d = c->td[t];
-  const size_t n = (size_t)d.K * d.Np;
+  const size_t n = (size_t)d.K * d.Np, fs = (size_t)d.Ks * d.Np;
   const float* src[4] = {p, ux, uy, uz};
   for (int f = 0; f < 4; ++f)
-    HIPCHK(c, hipMemcpyAsync(d.U + f * n, src[f], n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d.U + f * fs, src[f], n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
   c->traces_valid = false;
   c->mr_ready = false;
   return HDG_OK;
@@ -1397,11 +1402,11 @@ int hdg_get_field(hdg_ctx* c, int which, int t, float* p, float* ux, float* uy, 
   if (check_type(c, t) || !p || !ux || !uy || !uz || (which != 0 && which != 1))
     return fail(c, HDG_EINVAL, "bad type, selector or NULL output");
   TypeData& d = c->td[t];
-  const size_t n = (size_t)d.K * d.Np;
+  const size_t n = (size_t)d.K * d.Np, fs = (size_t)d.Ks * d.Np;
   const float* base = which == 0 ? d.U : d.R;
   float* dst[4] = {p, ux, uy, uz};
   for (int f = 0; f < 4; ++f)
-    HIPCHK(c, hipMemcpyAsync(dst[f], base + f * n, n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dst[f], base + f * fs, n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
   return HDG_OK;
 }
 
@@ -1504,7 +1509,7 @@ int lmin_of(int L, int k) {
 
 StageArgs mr_args(hdg_ctx* c, TypeData& d, int lmin, int k, int dense) {
   StageArgs a{};
-  a.K = d.K;
+  a.K = d.Ks;
   a.n_items = d.n_from[lmin];
   // when the elements are already stored finest level first, the active set
   // is a prefix of the storage order and tiles move as contiguous blocks
@@ -1657,12 +1662,12 @@ int hdg_mrab_setup(hdg_ctx* c, int n_levels, double cfl, double* dt_min_out, int
     if (!d.elevel && (rc = dalloc(c, &d.elevel, d.K))) return rc;
     if (!d.ehalf && (rc = dalloc(c, &d.ehalf, d.K))) return rc;
     HIPCHK(c, hipMemcpyAsync(d.ehalf, hf.data(), d.K, hipMemcpyHostToDevice, c->stream));
-    if (!d.H && (rc = dalloc(c, &d.H, (size_t)3 * 4 * d.K * d.Np))) return rc;
+    if (!d.H && (rc = dalloc(c, &d.H, (size_t)3 * 4 * d.Ks * d.Np))) return rc;
     HIPCHK(c, hipMemcpyAsync(d.elist, order.data(), d.K * sizeof(int), hipMemcpyHostToDevice, c->stream));
     d.elist_identity = true;
     for (int64_t k = 0; k < d.K && d.elist_identity; ++k) d.elist_identity = order[k] == (int)k;
     HIPCHK(c, hipMemcpyAsync(d.elevel, el.data(), d.K, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemsetAsync(d.H, 0, (size_t)3 * 4 * d.K * d.Np * sizeof(float), c->stream));
+    HIPCHK(c, hipMemsetAsync(d.H, 0, (size_t)3 * 4 * d.Ks * d.Np * sizeof(float), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   if (dt_min_out) *dt_min_out = dtmin;
@@ -1732,7 +1737,7 @@ int check_finite_impl(hdg_ctx* c, bool* finite) {
   launch_fill_int(c->flag, 1, 0, c->stream);
   for (int t = 0; t < 4; ++t) {
     const TypeData& d = c->td[t];
-    if (d.present) launch_finite((int64_t)4 * d.K * d.Np, d.U, c->flag, c->stream);
+    if (d.present) launch_finite((int64_t)4 * d.Ks * d.Np, d.U, c->flag, c->stream);
   }
   HIPCHK(c, hipGetLastError());
   int h = 0;
@@ -1903,13 +1908,12 @@ int hdg_checkpoint_save(hdg_ctx* c, void* buf, int64_t bytes) {
   for (int t = 0; t < 4; ++t) {
     const TypeData& d = c->td[t];
     if (!d.present) continue;
-    const size_t n = (size_t)4 * d.K * d.Np * sizeof(float);
-    HIPCHK(c, hipMemcpyAsync(p, d.U, n, hipMemcpyDeviceToHost, c->stream));
-    p += n;
-    if (hist) {
-      HIPCHK(c, hipMemcpyAsync(p, d.H, 3 * n, hipMemcpyDeviceToHost, c->stream));
-      p += 3 * n;
-    }
+    // fields unpadded in the checkpoint: K Np values each
+    const size_t n = (size_t)d.K * d.Np * sizeof(float), fs = (size_t)d.Ks * d.Np;
+    for (int f = 0; f < 4; ++f, p += n) HIPCHK(c, hipMemcpyAsync(p, d.U + f * fs, n, hipMemcpyDeviceToHost, c->stream));
+    if (hist)
+      for (int f = 0; f < 12; ++f, p += n)
+        HIPCHK(c, hipMemcpyAsync(p, d.H + f * fs, n, hipMemcpyDeviceToHost, c->stream));
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return HDG_OK;
@@ -1939,13 +1943,11 @@ int hdg_checkpoint_load(hdg_ctx* c, const void* buf, int64_t bytes) {
   for (int t = 0; t < 4; ++t) {
     TypeData& d = c->td[t];
     if (!d.present) continue;
-    const size_t n = (size_t)4 * d.K * d.Np * sizeof(float);
-    HIPCHK(c, hipMemcpyAsync(d.U, p, n, hipMemcpyHostToDevice, c->stream));
-    p += n;
-    if (hist) {
-      HIPCHK(c, hipMemcpyAsync(d.H, p, 3 * n, hipMemcpyHostToDevice, c->stream));
-      p += 3 * n;
-    }
+    const size_t n = (size_t)d.K * d.Np * sizeof(float), fs = (size_t)d.Ks * d.Np;
+    for (int f = 0; f < 4; ++f, p += n) HIPCHK(c, hipMemcpyAsync(d.U + f * fs, p, n, hipMemcpyHostToDevice, c->stream));
+    if (hist)
+      for (int f = 0; f < 12; ++f, p += n)
+        HIPCHK(c, hipMemcpyAsync(d.H + f * fs, p, n, hipMemcpyHostToDevice, c->stream));
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->time = h.time;
@@ -1969,6 +1971,7 @@ int hdg_energy(hdg_ctx* c, double* E) {
     EnergyArgs a{};
     a.type = t;
     a.K = d.K;
+    a.Ks = d.Ks;
     a.Np = d.Np;
     a.U = d.U;
     a.geo = d.geo;

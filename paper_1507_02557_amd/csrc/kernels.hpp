@@ -29,6 +29,7 @@ struct GeoArgs {
 struct EnergyArgs {
   int type;
   int64_t K;
+  int64_t Ks;             // field stride of U in elements
   int Np;
   const float* U;
   const float* geo;
@@ -79,12 +80,12 @@ void launch_trace_constants(const TraceConstArgs& a, hipStream_t s);
 void launch_geometry(const GeoArgs& g, hipStream_t s);
 void launch_points(int type, int64_t K, int nv, const double* V, const double* pts, int npts, double* out,
                    hipStream_t s);
-// Projection of sampled initial data (wedge, pyramid: in chunks of at most
-// `chunk` elements through the work buffer tmp of 4 chunk npts doubles;
-// chunk < 1: all K at once).
+// Projection of sampled initial data into U (fields Ks Np floats apart;
+// wedge, pyramid: in chunks of at most `chunk` elements through the work
+// buffer tmp of 4 chunk npts doubles; chunk < 1: all K at once).
 void launch_project(int type, int64_t K, int nv, const double* V, const double* pts, const double* w, int npts,
                     int Np, const double* Phi, const double* geo_pts, const double* f0, const double* f1,
-                    const double* f2, const double* f3, double* tmp, int64_t chunk, float* U, hipStream_t s);
+                    const double* f2, const double* f3, double* tmp, int64_t chunk, int64_t Ks, float* U, hipStream_t s);
 // Fixed device work buffer of the allocation-free projection (bytes per GPU).
 constexpr int64_t kProjectScratchBytes = 16 * 1024 * 1024;
 constexpr int kMaxDevices = 64;

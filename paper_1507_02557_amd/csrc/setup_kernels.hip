@@ -138,10 +138,10 @@ __global__ void project_weight_kernel(int type, int64_t e0, int64_t Kc, int nv, 
   tmp[3 * n + it] = s * f3[gi];
 }
 
-// Projection step 2, elements e0 .. e0+Kc-1 of K:
+// Projection step 2, elements e0 .. e0+Kc-1 (fields Ks Np floats apart):
 // U[c][e][i] = sum_q Phi[q][i] tmp[c][e-e0][q] / m_i, with m_i = J(a_i, b_j)
 // for the pyramid and 1 for the wedge.
-__global__ void project_apply_kernel(int type, int64_t e0, int64_t Kc, int64_t K, int nv, const double* Vall,
+__global__ void project_apply_kernel(int type, int64_t e0, int64_t Kc, int64_t Ks, int nv, const double* Vall,
                                      const double* Phi, int npts, int Np, const double* geo_pts,
                                      const double* tmp, float* U) {
   const int64_t lt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -160,18 +160,18 @@ __global__ void project_apply_kernel(int type, int64_t e0, int64_t Kc, int64_t K
   for (int c = 0; c < 4; ++c) {
     double s = 0.0;
     for (int q = 0; q < npts; ++q) s += Phi[(int64_t)q * Np + i] * tmp[c * n + el * npts + q];
-    U[(int64_t)c * K * Np + it] = (float)(s / m);
+    U[(int64_t)c * Ks * Np + it] = (float)(s / m);
   }
 }
 
-__global__ void copy_samples_kernel(int64_t n, const double* f0, const double* f1, const double* f2,
+__global__ void copy_samples_kernel(int64_t n, int64_t fs, const double* f0, const double* f1, const double* f2,
                                     const double* f3, float* U) {
   const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (it >= n) return;
   U[it] = (float)f0[it];
-  U[n + it] = (float)f1[it];
-  U[2 * n + it] = (float)f2[it];
-  U[3 * n + it] = (float)f3[it];
+  U[fs + it] = (float)f1[it];
+  U[2 * fs + it] = (float)f2[it];
+  U[3 * fs + it] = (float)f3[it];
 }
 
 // Energy 1/2 sum (p^T M p / kappa + rho u^T M u), one thread per element,
@@ -183,7 +183,7 @@ __global__ void energy_kernel(EnergyArgs a) {
   if (e < a.K) {
     const int Np = a.Np;
     const double kap = a.mat[e].x, rho = 1.0 / a.mat[e].y;
-    const int64_t n = a.K * Np;
+    const int64_t n = a.Ks * Np;
     const float* U = a.U;
     if (a.type == 3) {
       const double J = 1.0 / a.geo[e * 12 + 9];
@@ -245,10 +245,11 @@ void launch_points(int type, int64_t K, int nv, const double* V, const double* p
 
 void launch_project(int type, int64_t K, int nv, const double* V, const double* pts, const double* w, int npts,
                     int Np, const double* Phi, const double* geo_pts, const double* f0, const double* f1,
-                    const double* f2, const double* f3, double* tmp, int64_t chunk, float* U, hipStream_t s) {
+                    const double* f2, const double* f3, double* tmp, int64_t chunk, int64_t Ks, float* U, hipStream_t s) {
   if (K == 0) return;
   if (type == 0 || type == 3) {
-    hipLaunchKernelGGL(copy_samples_kernel, dim3(nblk(K * Np, 256)), dim3(256), 0, s, K * Np, f0, f1, f2, f3, U);
+    hipLaunchKernelGGL(copy_samples_kernel, dim3(nblk(K * Np, 256)), dim3(256), 0, s, K * Np, Ks * Np, f0, f1, f2,
+                       f3, U);
     return;
   }
   if (chunk < 1) chunk = K;
@@ -257,7 +258,7 @@ void launch_project(int type, int64_t K, int nv, const double* V, const double* 
     const int64_t Kc = K - e0 < chunk ? K - e0 : chunk;
     hipLaunchKernelGGL(project_weight_kernel, dim3(nblk(Kc * npts, 256)), dim3(256), 0, s, type, e0, Kc, nv, V,
                        pts, w, npts, f0, f1, f2, f3, tmp);
-    hipLaunchKernelGGL(project_apply_kernel, dim3(nblk(Kc * Np, 256)), dim3(256), 0, s, type, e0, Kc, K, nv, V,
+    hipLaunchKernelGGL(project_apply_kernel, dim3(nblk(Kc * Np, 256)), dim3(256), 0, s, type, e0, Kc, Ks, nv, V,
                        Phi, npts, Np, geo_pts, tmp, U);
   }
 }

@@ -35,7 +35,7 @@ struct MrabParams {
 };
 
 struct StageArgs {
-  int64_t K;             // elements of this type (field stride)
+  int64_t K;             // field stride in elements (the type's count rounded up to 4)
   int64_t n_items;       // elements processed by this launch
   const int* elist;      // element of each item (NULL: item i is element i)
   const int8_t* elevel;  // level per element (multi-rate)
