@@ -381,32 +381,60 @@ int build_pyr_mfma_tables(hdg_ctx* c, std::vector<float>& ops, std::vector<int>&
   const FaceTables& ft = c->ft;
   const int Np = P.Np, Nfn = ft.Nfn, Nfq = ft.Nfq;
   const int SD = Np | 1, Mt = (Np + 15) / 16, Kf = (Nfn + 3) / 4;
+  const int Ks = (Np + 3) / 4, Mq = (Nfq + 15) / 16, Kq = (Nfq + 3) / 4, Mtf = (Nfn + 15) / 16;
   int nf = 0, ni = 0;
   if (pyr_mfma_table_sizes(c->N, &nf, &ni)) return fail(c, HDG_EINVAL, "internal: no pyramid matrix-core kernel");
   ops.clear();
   iops.clear();
-  auto rows = [&](const Vec& A, int R) {
-    for (int i = 0; i < R; ++i)
-      for (int j = 0; j < SD; ++j) ops.push_back(j < Np ? (float)A[(size_t)i * Np + j] : 0.0f);
-  };
-  rows(P.Dr, Np);
-  rows(P.Ds, Np);
-  rows(P.Dt, Np);
-  rows(P.Fquad, Nfq);
-  rows(P.Ftri, 4 * Nfn);
+  if (pyr_mfma_global(c->N)) {
+    // fragment order: lane l of (row tile t, k-step s) holds A[16t + l%16][4s + l/16]
+    // (transposed: A[4s + l/16][16t + l%16]), zero outside the R x C matrix
+    // (k-step outer, row tile inner)
+    auto frag = [&](const double* A, int R, int C, int t, int st, bool tr) {
+      for (int l = 0; l < 64; ++l) {
+        const int i = tr ? 4 * st + l / 16 : 16 * t + l % 16, j = tr ? 16 * t + l % 16 : 4 * st + l / 16;
+        ops.push_back(i < R && j < C ? (float)A[(size_t)i * C + j] : 0.0f);
+      }
+    };
+    const Vec* D[3] = {&P.Dr, &P.Ds, &P.Dt};
+    for (int st = 0; st < Ks; ++st)
+      for (int tr = 0; tr < 2; ++tr)
+        for (int r = 0; r < 3; ++r)
+          for (int t = 0; t < Mt; ++t) frag(D[r]->data(), Np, Np, t, st, tr == 1);
+    for (int st = 0; st < Ks; ++st)
+      for (int t = 0; t < Mq; ++t) frag(P.Fquad.data(), Nfq, Np, t, st, false);
+    for (int st = 0; st < Kq; ++st)
+      for (int t = 0; t < Mt; ++t) frag(P.Fquad.data(), Nfq, Np, t, st, true);
+    for (int tf = 0; tf < 4; ++tf)
+      for (int st = 0; st < Ks; ++st)
+        for (int t = 0; t < Mtf; ++t) frag(P.Ftri.data() + (size_t)tf * Nfn * Np, Nfn, Np, t, st, false);
+  } else {
+    auto rows = [&](const Vec& A, int R) {
+      for (int i = 0; i < R; ++i)
+        for (int j = 0; j < SD; ++j) ops.push_back(j < Np ? (float)A[(size_t)i * Np + j] : 0.0f);
+    };
+    rows(P.Dr, Np);
+    rows(P.Ds, Np);
+    rows(P.Dt, Np);
+    rows(P.Fquad, Nfq);
+    rows(P.Ftri, 4 * Nfn);
+  }
   std::vector<double> Mf((size_t)Nfn * Nfn, 0.0);
   for (int q = 0; q < Nfq; ++q)
     for (int x = 0; x < Nfn; ++x)
       for (int y = 0; y < Nfn; ++y) Mf[x * Nfn + y] += ft.Ican[q * Nfn + x] * ft.tri_w[q] * ft.Ican[q * Nfn + y];
+  // Lt fragments [4][Mt][Kf] (LDS tables) or [4][Kf][Mt] (global fragment order)
+  const bool g_order = pyr_mfma_global(c->N) != 0;
   for (int tf = 0; tf < 4; ++tf)
-    for (int t = 0; t < Mt; ++t)
-      for (int s = 0; s < Kf; ++s)
+    for (int u = 0; u < (g_order ? Kf : Mt); ++u)
+      for (int v = 0; v < (g_order ? Mt : Kf); ++v)
         for (int l = 0; l < 64; ++l) {
+          const int t = g_order ? v : u, s = g_order ? u : v;
           const int i = 16 * t + l % 16, col = 4 * s + l / 16;
-          double v = 0.0;
+          double acc = 0.0;
           if (i < Np && col < Nfn)
-            for (int m = 0; m < Nfn; ++m) v += P.Ftri[((size_t)tf * Nfn + m) * Np + i] * Mf[m * Nfn + col];
-          ops.push_back((float)v);
+            for (int m = 0; m < Nfn; ++m) acc += P.Ftri[((size_t)tf * Nfn + m) * Np + i] * Mf[m * Nfn + col];
+          ops.push_back((float)acc);
         }
   ops.push_back((float)ft.tri_w[0]);
   while (ops.size() % 2) ops.push_back(0.0f);
@@ -440,7 +468,7 @@ int launch_type(hdg_ctx* c, int t, StageArgs a, bool mrab) {
   a.lat = use_lattice(c) ? 1 : 0;
   a.V = c->td[t].V;
   // The matrix-core pyramid kernel serves the stage and right-hand-side
-  // modes at N = 3, 4 (the multi-rate right-hand side included); the
+  // modes at N = 3..5 (the multi-rate right-hand side included); the
   // multi-rate update and N <= 2 use the wavefront-batched vector kernels.
   const bool pyr_mfma = t == kPyr && a.lat && c->td[t].mops && !mrab && c->N >= 3;
   if (pyr_mfma) {

@@ -119,6 +119,9 @@ int launch_pyr_mfma(int N, const StageArgs& a, hipStream_t s, int max_blocks);
 // fragments, w0, geometry points; base and lattice permutations and their
 // inverses); -1 for orders without the kernel.
 int pyr_mfma_table_sizes(int N, int* n_floats, int* n_ints);
+// 1 if the order's pyramid tables are read from global memory in fragment
+// order (they exceed the LDS), 0 if they are copied to the LDS row-major.
+int pyr_mfma_global(int N);
 // Fragment geometry of precision P: K per instruction, entries per lane, pieces.
 void tet_mfma_frag_shape(int P, int* kk, int* ki, int* npc);
 

@@ -26,6 +26,14 @@
 // stage start are those it wrote at the end of the previous stage, so they
 // are read from the trace buffer rather than recomputed; the traces of the
 // updated state are the products Fq u and Ft_f u.
+//
+// Operator tables: in the LDS (G = false), or, where they do not fit there
+// (N = 5: D alone is 97 KiB), in global memory in fragment order (G = true):
+// each (matrix, row tile, k-step) is 64 consecutive floats, one per lane, so
+// a wavefront reads a fragment as one coalesced 256-byte load, and the
+// fragments of one k-step lie together (one base address per step, the
+// rest immediate offsets); a tile of 16 elements reads each fragment once,
+// from the L2 after the first tiles.
 #pragma once
 
 #include "mfma_common.hpp"
@@ -66,7 +74,7 @@ __device__ __forceinline__ double adjugate(const double F[3][3], double A[3][3])
   return F[0][0] * A[0][0] + F[0][1] * A[1][0] + F[0][2] * A[2][0];
 }
 
-template <int N, int NW>
+template <int N, int NW, bool G = false>
 struct PyrMfma {
   static constexpr int Np = (N + 1) * (N + 2) * (2 * N + 3) / 6;
   static constexpr int Nfn = (N + 1) * (N + 2) / 2;
@@ -77,16 +85,23 @@ struct PyrMfma {
   static constexpr int Mq = (Nfq + 15) / 16;  // row tiles over base-face points
   static constexpr int Kq = (Nfq + 3) / 4;    // k-steps over base-face points
   static constexpr int Kf = (Nfn + 3) / 4;    // k-steps over a triangle's lattice
-  static_assert(Nfn <= 16, "one row tile per triangle lattice");
+  static constexpr int Mf = (Nfn + 15) / 16;  // row tiles over a triangle's lattice
   static constexpr int SD = Np | 1;           // odd strides: conflict-free fragment reads
   static constexpr int SX = Np | 1;
   static constexpr int SF = Nfq | 1;
   static constexpr int NT = 64 * NW;
   static constexpr int kLFloats = 4 * Mt * Kf * 64;
-  // D [3][Np][SD], Fq [Nfq][SD], Ft [4][Nfn][SD], Lt fragments, w0, then the
-  // geometry points (a, b) as doubles at an even float offset
-  static constexpr int kOpsOpf = (3 * Np + Nfq + 4 * Nfn) * SD;
-  static constexpr int kGabOff = (kOpsOpf + kLFloats + 2) & ~1;
+  // G = false: D [3][Np][SD], Fq [Nfq][SD], Ft [4][Nfn][SD] (row-major, copied
+  // to the LDS as they are);
+  // G = true: fragments [64] of D and D^T [Ks][2][3][Mt], Fq [Ks][Mq],
+  // Fq^T [Kq][Mt], Ft [4][Ks][Mf] (k-step before row tile);
+  // then in both: the Lt fragments ([4][Mt][Kf], with G [4][Kf][Mt]), w0, and
+  // the geometry points (a, b) as doubles at an even float offset
+  static constexpr int kOpsOpf = G ? 0 : (3 * Np + Nfq + 4 * Nfn) * SD;
+  static constexpr int kDD = 0, kFqA = kDD + 6 * Mt * Ks * 64;
+  static constexpr int kFqT = kFqA + Mq * Ks * 64, kFtA = kFqT + Kq * Mt * 64, kFragEnd = kFtA + 4 * Mf * Ks * 64;
+  static constexpr int kLtOff = G ? kFragEnd : kOpsOpf;
+  static constexpr int kGabOff = (kLtOff + kLFloats + 2) & ~1;
   static constexpr int kOpsFloats = kGabOff + 4 * Np;
   static constexpr int kOpsInts = 2 * 8 * Nfq + 2 * 6 * Nfn;
   static constexpr int Q4 = 4 * Np;
@@ -100,11 +115,14 @@ struct PyrMfma {
   };
   static_assert(4 * 16 * SF >= 16 * SX, "output staging does not fit the flux buffer");
 
+  // LDS operator extents (a single float each when the tables stay in
+  // global memory)
+  static constexpr int LN = G ? 1 : Np, LS = G ? 1 : SD, LQ = G ? 1 : Nfq, LF = G ? 1 : Nfn;
   struct Smem {
-    float D[3][Np][SD];
-    float Fq[Nfq][SD];
-    float Ft[4][Nfn][SD];
-    float Lt[4][Mt][Kf][64];
+    float D[3][LN][LS];
+    float Fq[LQ][LS];
+    float Ft[4][LF][LS];
+    float Lt[G ? 1 : 4][G ? 1 : Mt][G ? 1 : Kf][G ? 1 : 64];
     double gab[Np][2];
     int qperm[8][Nfq], iqperm[8][Nfq];  // canonical <-> local base point
     int tperm[6][Nfn], itperm[6][Nfn];  // canonical <-> local lattice node
@@ -114,30 +132,99 @@ struct PyrMfma {
 
   // operator entry with zero outside [0, R) x [0, C)
   template <int R, int C, int S>
-  __device__ static float at(const float (*A)[S], int i, int j) {
+  __device__ __forceinline__ static float at(const float (*A)[S], int i, int j) {
     const bool in = i < R && j < C;
     return in ? A[in ? i : 0][in ? j : 0] : 0.f;
   }
+  // With the tables in global memory, the fragments of a step are all issued
+  // before its products: left to itself the scheduler (at the register
+  // limit) puts each load next to its product, with one or two loads in
+  // flight, and every product then waits a full L2 round trip.
+  __device__ __forceinline__ static void loads_issued() {
+    if constexpr (G) __builtin_amdgcn_sched_barrier(0);
+  }
+  // A loop over S k-steps whose body takes the M operator entries of its
+  // step.  With the tables in global memory the entries of step s + 1 are
+  // loaded while step s computes: the wait for a step's entries comes before
+  // the next step's loads are issued (a wait placed after them would wait for
+  // both).  With the tables in the LDS each step reads its own, unrolled U
+  // times.
+  template <int M, int U, class Load, class Body>
+  __device__ __forceinline__ static void ksteps(int S, const Load& load, const Body& body) {
+    if constexpr (G) {
+      float cur[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) cur[m] = load(m, 0);
+#pragma unroll 1
+      for (int s = 0; s < S; ++s) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) __asm__ volatile("" : "+v"(cur[m]));
+        loads_issued();
+        const int sn = s + 1 < S ? s + 1 : s;
+        float nxt[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) nxt[m] = load(m, sn);
+        loads_issued();
+        body(s, cur);
+#pragma unroll
+        for (int m = 0; m < M; ++m) cur[m] = nxt[m];
+      }
+    } else {
+#pragma unroll U
+      for (int s = 0; s < S; ++s) {
+        float cur[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) cur[m] = load(m, s);
+        body(s, cur);
+      }
+    }
+  }
+  // lane's A-operand entries of the operator fragments
+  __device__ __forceinline__ static float frag(const StageArgs& a, int off, int lane) { return a.ops[off + lane]; }
+  __device__ __forceinline__ static float opD(const Smem& sm, const StageArgs& a, int r, int t, int s, int lane) {
+    if constexpr (G) return frag(a, kDD + ((2 * s * 3 + r) * Mt + t) * 64, lane);
+    else return at<Np, Np, SD>(sm.D[r], 16 * t + (lane & 15), 4 * s + (lane >> 4));
+  }
+  __device__ __forceinline__ static float opDT(const Smem& sm, const StageArgs& a, int r, int t, int s, int lane) {
+    if constexpr (G) return frag(a, kDD + (((2 * s + 1) * 3 + r) * Mt + t) * 64, lane);
+    else return at<Np, Np, SD>(sm.D[r], 4 * s + (lane >> 4), 16 * t + (lane & 15));
+  }
+  __device__ __forceinline__ static float opFq(const Smem& sm, const StageArgs& a, int t, int s, int lane) {
+    if constexpr (G) return frag(a, kFqA + (s * Mq + t) * 64, lane);
+    else return at<Nfq, Np, SD>(sm.Fq, 16 * t + (lane & 15), 4 * s + (lane >> 4));
+  }
+  __device__ __forceinline__ static float opFqT(const Smem& sm, const StageArgs& a, int s, int t, int lane) {
+    if constexpr (G) return frag(a, kFqT + (s * Mt + t) * 64, lane);
+    else return at<Nfq, Np, SD>(sm.Fq, 4 * s + (lane >> 4), 16 * t + (lane & 15));
+  }
+  __device__ __forceinline__ static float opFt(const Smem& sm, const StageArgs& a, int tf, int t, int s, int lane) {
+    if constexpr (G) return frag(a, kFtA + ((tf * Ks + s) * Mf + t) * 64, lane);
+    else return at<Nfn, Np, SD>(sm.Ft[tf], 16 * t + (lane & 15), 4 * s + (lane >> 4));
+  }
+  __device__ __forceinline__ static float opLt(const Smem& sm, const StageArgs& a, int tf, int t, int s, int lane) {
+    if constexpr (G) return frag(a, kLtOff + ((tf * Kf + s) * Mt + t) * 64, lane);
+    else return sm.Lt[tf][t][s][lane];
+  }
 
   // ---- tile I/O (global [K][Np] per field <-> LDS [16][SX])
-  __device__ static bool contiguous(const StageArgs& a, int64_t e0) {
+  __device__ __forceinline__ static bool contiguous(const StageArgs& a, int64_t e0) {
     return a.elist == nullptr && e0 + 16 <= a.n_items && ((a.K * Np) & 3) == 0;
   }
-  __device__ static void load_rows(float (*dst)[SX], const float* src, const StageArgs& a, int64_t e0, int lane) {
+  __device__ __forceinline__ static void load_rows(float (*dst)[SX], const float* src, const StageArgs& a, int64_t e0, int lane) {
     for (int it = lane; it < 16 * Np; it += 64) {
       const int n = it / Np, k = it - n * Np;
       const int64_t e = item(a, e0 + n);
       dst[n][k] = e >= 0 ? src[e * Np + k] : 0.0f;
     }
   }
-  __device__ static void store_rows(float* dst, const float (*src)[SX], const StageArgs& a, int64_t e0, int lane) {
+  __device__ __forceinline__ static void store_rows(float* dst, const float (*src)[SX], const StageArgs& a, int64_t e0, int lane) {
     for (int it = lane; it < 16 * Np; it += 64) {
       const int n = it / Np, k = it - n * Np;
       const int64_t e = item(a, e0 + n);
       if (e >= 0) dst[e * Np + k] = src[n][k];
     }
   }
-  __device__ static void put4(float (*dst)[SX], int q0, float4 v) {
+  __device__ __forceinline__ static void put4(float (*dst)[SX], int q0, float4 v) {
     const float x[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -145,7 +232,7 @@ struct PyrMfma {
       dst[n][q - n * Np] = x[i];
     }
   }
-  __device__ static float4 get4(const float (*src)[SX], int q0) {
+  __device__ __forceinline__ static float4 get4(const float (*src)[SX], int q0) {
     float x[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -154,18 +241,18 @@ struct PyrMfma {
     }
     return make_float4(x[0], x[1], x[2], x[3]);
   }
-  __device__ static void load_field(float4 (&v)[JQ], const float* base, int64_t e0, int lane) {
+  __device__ __forceinline__ static void load_field(float4 (&v)[JQ], const float* base, int64_t e0, int lane) {
     const float4* src = reinterpret_cast<const float4*>(base + e0 * Np);
 #pragma unroll
     for (int j = 0; j < JQ; ++j)
       if (lane + 64 * j < Q4) v[j] = src[lane + 64 * j];
   }
-  __device__ static void put_field(float (*dst)[SX], const float4 (&v)[JQ], int lane) {
+  __device__ __forceinline__ static void put_field(float (*dst)[SX], const float4 (&v)[JQ], int lane) {
 #pragma unroll
     for (int j = 0; j < JQ; ++j)
       if (lane + 64 * j < Q4) put4(dst, 4 * (lane + 64 * j), v[j]);
   }
-  __device__ static void store_tile(float* dst, const float (*src)[SX], const StageArgs& a, int64_t e0, int lane,
+  __device__ __forceinline__ static void store_tile(float* dst, const float (*src)[SX], const StageArgs& a, int64_t e0, int lane,
                                     bool contig) {
     if (contig) {
       float4* d4 = reinterpret_cast<float4*>(dst + e0 * Np);
@@ -176,7 +263,7 @@ struct PyrMfma {
       store_rows(dst, src, a, e0, lane);
     }
   }
-  __device__ static void load_state(Wave& W, const StageArgs& a, int64_t e0, int lane, bool contig) {
+  __device__ __forceinline__ static void load_state(Wave& W, const StageArgs& a, int64_t e0, int lane, bool contig) {
     const int64_t fs = a.K * Np;
     if (contig) {
       float4 v0[JQ], v1[JQ], v2[JQ], v3[JQ];
@@ -195,7 +282,7 @@ struct PyrMfma {
 
   // ---- traces of the tile's state: base face at canonical GL points,
   // triangles at canonical lattice nodes
-  __device__ static void write_traces(const Smem& sm, const Wave& W, const StageArgs& a, int64_t e0, int lane,
+  __device__ __forceinline__ static void write_traces(const Smem& sm, const Wave& W, const StageArgs& a, int64_t e0, int lane,
                                       float4* tr) {
     const int n = lane & 15, g = lane >> 4;
     const int64_t e = item(a, e0 + n);
@@ -207,21 +294,20 @@ struct PyrMfma {
       for (int t = 0; t < Mq; ++t)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-      for (int s = 0; s < Ks; ++s) {
-        const int k = 4 * s + g;
-        const bool in = k < Np;
-        const int kk = in ? k : 0;
-        float b[4];
+      ksteps<Mq, 2>(
+          Ks, [&](int t, int s) { return opFq(sm, a, t, s, lane); },
+          [&](int s, const float(&af)[Mq]) {
+            const int k = 4 * s + g;
+            const bool in = k < Np;
+            const int kk = in ? k : 0;
+            float b[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = in ? W.X[c][n][kk] : 0.f;
+            for (int c = 0; c < 4; ++c) b[c] = in ? W.X[c][n][kk] : 0.f;
 #pragma unroll
-        for (int t = 0; t < Mq; ++t) {
-          const float af = at<Nfq, Np, SD>(sm.Fq, 16 * t + (lane & 15), 4 * s + (lane >> 4));
+            for (int t = 0; t < Mq; ++t)
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[c][t] = mma_f32(af, b[c], acc[c][t]);
-        }
-      }
+              for (int c = 0; c < 4; ++c) acc[c][t] = mma_f32(af[t], b[c], acc[c][t]);
+          });
       const int o = e >= 0 ? a.ori[slot] : 0;
 #pragma unroll
       for (int t = 0; t < Mq; ++t)
@@ -237,62 +323,43 @@ struct PyrMfma {
     // triangular faces: lattice values Ft_f u (rows = local lattice nodes)
 #pragma unroll 1
     for (int tf = 0; tf < 4; ++tf) {
-      f32x4 acc[4];
+      f32x4 acc[4][Mf];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-      for (int s = 0; s < Ks; ++s) {
-        const int k = 4 * s + g;
-        const bool in = k < Np;
-        const int kk = in ? k : 0;
-        const float af = at<Nfn, Np, SD>(sm.Ft[tf], lane & 15, 4 * s + (lane >> 4));
+      for (int t = 0; t < Mf; ++t)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = mma_f32(af, in ? W.X[c][n][kk] : 0.f, acc[c]);
-      }
+        for (int c = 0; c < 4; ++c) acc[c][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+      ksteps<Mf, 2>(
+          Ks, [&](int t, int s) { return opFt(sm, a, tf, t, s, lane); },
+          [&](int s, const float(&af)[Mf]) {
+            const int k = 4 * s + g;
+            const bool in = k < Np;
+            const int kk = in ? k : 0;
+            float b[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = in ? W.X[c][n][kk] : 0.f;
+#pragma unroll
+            for (int t = 0; t < Mf; ++t)
+#pragma unroll
+              for (int c = 0; c < 4; ++c) acc[c][t] = mma_f32(af[t], b[c], acc[c][t]);
+          });
       const int o = e >= 0 ? a.ori[slot + 1 + tf] : 0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int l = 4 * g + i;
-        if (e >= 0 && l < Nfn)
-          tr[(slot + 1 + tf) * TS + sm.itperm[o][l]] = make_float4(acc[0][i], acc[1][i], acc[2][i], acc[3][i]);
-        else if (e >= 0 && l < LW)  // padding to whole lines
-          tr[(slot + 1 + tf) * TS + l] = make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-    }
-  }
-
-  // multi-rate AB3 update: u_new = u + dtau_l sum_j beta_j(1) r_{s-j} with its
-  // traces, then the mid-step state u_new + dtau_l sum_j (beta_j(1/2) -
-  // beta_j(1)) r_{s-j} with its traces (dense output)
-  __device__ static void mrab_update(const Smem& sm, Wave& W, const StageArgs& a, int64_t e0, int lane) {
-    const int64_t K = a.K;
-    const int64_t hstr = 4 * K * Np;
-    for (int half = 0; half < 2; ++half) {
-      for (int c = 0; c < 4; ++c)
-        for (int it = lane; it < 16 * Np; it += 64) {
-          const int nn = it / Np, k = it - nn * Np;
-          const int64_t ee = item(a, e0 + nn);
-          if (ee < 0) continue;
-          const int lv = a.elevel[ee];
-          const int64_t gi = (int64_t)c * K * Np + ee * Np + k;
-          float acc = 0.f;
-          for (int j = 0; j < 3; ++j) {
-            const float w = half ? a.mr.bh[lv][j] - a.mr.b1[lv][j] : a.mr.b1[lv][j];
-            acc += w * a.H[a.mr.hs[lv][j] * hstr + gi];
-          }
-          const float un = W.X[c][nn][k] + a.mr.dtl[lv] * acc;
-          W.X[c][nn][k] = un;
-          if (!half) a.U[gi] = un;
+      for (int t = 0; t < Mf; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int l = 16 * t + 4 * g + i;
+          if (e >= 0 && l < Nfn)
+            tr[(slot + 1 + tf) * TS + sm.itperm[o][l]] =
+                make_float4(acc[0][t][i], acc[1][t][i], acc[2][t][i], acc[3][t][i]);
+          else if (e >= 0 && l < LW)  // padding to whole lines
+            tr[(slot + 1 + tf) * TS + l] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
-      wave_sync();
-      write_traces(sm, W, a, e0, lane, half ? a.tr_half : a.tr_out);
-      wave_sync();
     }
   }
 
   // vertices of element e (a reference pyramid for e < 0, keeping the
   // geometry of unused columns finite)
-  __device__ static void load_verts5(const StageArgs& a, int64_t e, double (&V)[5][3]) {
+  __device__ __forceinline__ static void load_verts5(const StageArgs& a, int64_t e, double (&V)[5][3]) {
     const double ref[5][3] = {{-1, -1, 0}, {1, -1, 0}, {1, 1, 0}, {-1, 1, 0}, {0, 0, 1}};
 #pragma unroll
     for (int v = 0; v < 5; ++v)
@@ -301,15 +368,22 @@ struct PyrMfma {
   }
 
   template <int C>
-  __device__ static void emit(Wave& W, const StageArgs& a, int64_t e0, int lane, bool contig, const float4 (&rv)[JQ],
+  __device__ __forceinline__ static void emit(Wave& W, const StageArgs& a, int64_t e0, int lane, bool contig, const float4 (&rv)[JQ],
                               const f32x4 (&rhs)[Mt]) {
     const int64_t K = a.K;
     const int n = lane & 15, g = lane >> 4;
     const bool stage = a.mode == kModeStage;
     float(*RB)[SX] = reinterpret_cast<float(*)[SX]>(&W.F[0][0][0]);
     if (stage) {
-      if (contig) put_field(RB, rv, lane);
-      else load_rows(RB, a.R + (int64_t)C * K * Np, a, e0, lane);
+      if (contig && !G) {
+        put_field(RB, rv, lane);
+      } else if (contig) {
+        float4 v[JQ];
+        load_field(v, a.R + (int64_t)C * K * Np, e0, lane);
+        put_field(RB, v, lane);
+      } else {
+        load_rows(RB, a.R + (int64_t)C * K * Np, a, e0, lane);
+      }
       wave_sync();
     }
 #pragma unroll
@@ -340,23 +414,25 @@ struct PyrMfma {
     wave_sync();
   }
 
-  __device__ static void tile(const Smem& sm, Wave& W, const StageArgs& a, int64_t e0, int lane) {
-    const int64_t K = a.K;
-    const int n = lane & 15, g = lane >> 4;
-    const int64_t e = item(a, e0 + n);
+  // One tile in the stage, right-hand-side and trace modes (the multi-rate
+  // update of pyramids runs on the vector kernels).
+  __device__ __forceinline__ static void tile(const Smem& sm, Wave& W, const StageArgs& a, int64_t e0, int lane) {
     const bool contig = contiguous(a, e0);
     // lanes of the previous tile may still read other columns of the tile
     wave_sync();
     load_state(W, a, e0, lane, contig);
     wave_sync();
-    if (a.mode == kModeTrace) {
-      write_traces(sm, W, a, e0, lane, a.tr_out);
-      return;
-    }
-    if (a.mode == kModeMrab) {
-      mrab_update(sm, W, a, e0, lane);
-      return;
-    }
+    if (a.mode != kModeTrace) rhs(sm, W, a, e0, lane, contig);
+    // traces of the (updated) state, from one call site: the code of a tile
+    // has to stay small enough for the instruction cache
+    if (a.mode == kModeTrace || a.mode == kModeStage) write_traces(sm, W, a, e0, lane, a.tr_out);
+  }
+
+  __device__ __forceinline__ static void rhs(const Smem& sm, Wave& W, const StageArgs& a, int64_t e0, int lane,
+                                             bool contig) {
+    const int64_t K = a.K;
+    const int n = lane & 15, g = lane >> 4;
+    const int64_t e = item(a, e0 + n);
     double V[5][3];
     load_verts5(a, e, V);
     float kap = 0.f, irho = 0.f;
@@ -372,11 +448,40 @@ struct PyrMfma {
 #pragma unroll
       for (int r = 0; r < 3; ++r) accG[r][t] = accV[t];
     }
-#pragma unroll 1
+    // operator entries one step ahead (with the tables in global memory their
+    // latency then overlaps a whole step of products)
+    float fd[3][Mt], fdt[3][Mt];
+#pragma unroll
+    for (int t = 0; t < Mt; ++t)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        fd[r][t] = opD(sm, a, r, t, 0, lane);
+        fdt[r][t] = opDT(sm, a, r, t, 0, lane);
+      }
+#pragma unroll 2
     for (int s = 0; s < Ks; ++s) {
       const int k = 4 * s + g;
       const bool in = k < Np;
       const int kk = in ? k : 0;
+      float nd[3][Mt], ndt[3][Mt];
+      const int sn = s + 1 < Ks ? s + 1 : s;  // (the last step reads its own entries again)
+      if constexpr (G) {
+        // this step's entries are waited for here, before the next step's
+        // loads are issued (a wait placed after them would wait for both)
+#pragma unroll
+        for (int t = 0; t < Mt; ++t)
+#pragma unroll
+          for (int r = 0; r < 3; ++r) __asm__ volatile("" : "+v"(fd[r][t]), "+v"(fdt[r][t]));
+        loads_issued();
+      }
+#pragma unroll
+      for (int t = 0; t < Mt; ++t)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          nd[r][t] = opD(sm, a, r, t, sn, lane);
+          ndt[r][t] = opDT(sm, a, r, t, sn, lane);
+        }
+      loads_issued();
       double F[3][3], A[3][3];
       pyr_jacobian(V, sm.gab[kk][0], sm.gab[kk][1], F);
       adjugate(F, A);
@@ -386,15 +491,14 @@ struct PyrMfma {
 #pragma unroll
       for (int r = 0; r < 3; ++r)
         ur[r] = in ? (float)A[r][0] * u1 + (float)A[r][1] * u2 + (float)A[r][2] * u3 : 0.f;
-      const int ra = lane & 15, ca = lane >> 4;
 #pragma unroll
       for (int t = 0; t < Mt; ++t)
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-          const float d = at<Np, Np, SD>(sm.D[r], 16 * t + ra, 4 * s + ca);
-          const float dt = at<Np, Np, SD>(sm.D[r], 4 * s + ca, 16 * t + ra);
-          accG[r][t] = mma_f32(d, p, accG[r][t]);
-          accV[t] = mma_f32(dt, ur[r], accV[t]);
+          accG[r][t] = mma_f32(fd[r][t], p, accG[r][t]);
+          accV[t] = mma_f32(fdt[r][t], ur[r], accV[t]);
+          fd[r][t] = nd[r][t];
+          fdt[r][t] = ndt[r][t];
         }
     }
     // surface-term accumulators start from the volume terms, scaled so that
@@ -415,11 +519,16 @@ struct PyrMfma {
         for (int d = 0; d < 3; ++d)
           accS[1 + d][t][i] = -((float)A[0][d] * accG[0][t][i] + (float)A[1][d] * accG[1][t][i] +
                                 (float)A[2][d] * accG[2][t][i]);
+        // one row's FP64 geometry at a time (interleaved, the rows' temporaries
+        // would exceed the registers)
+        __builtin_amdgcn_sched_barrier(0);
       }
     // the residual of the stage, fetched while the faces are processed
     const bool stage = a.mode == kModeStage;
+    // (not with the tables in global memory: there the registers hold the
+    // larger tiles, and each field's residual is read when it is emitted)
     float4 rv0[JQ], rv1[JQ], rv2[JQ], rv3[JQ];
-    if (stage && contig) {
+    if (!G && stage && contig) {
       const int64_t fs = K * Np;
       load_field(rv0, a.R, e0, lane);
       load_field(rv1, a.R + fs, e0, lane);
@@ -468,21 +577,20 @@ struct PyrMfma {
         }
       }
       wave_sync();
-#pragma unroll 1
-      for (int s = 0; s < Kq; ++s) {
-        const int k = 4 * s + g;
-        const bool in = k < Nfq;
-        const int kk = in ? k : 0;
-        float b[4];
+      ksteps<Mt, 1>(
+          Kq, [&](int t, int s) { return opFqT(sm, a, s, t, lane); },
+          [&](int s, const float(&af)[Mt]) {
+            const int k = 4 * s + g;
+            const bool in = k < Nfq;
+            const int kk = in ? k : 0;
+            float b[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = in ? W.F[c][n][kk] : 0.f;
+            for (int c = 0; c < 4; ++c) b[c] = in ? W.F[c][n][kk] : 0.f;
 #pragma unroll
-        for (int t = 0; t < Mt; ++t) {
-          const float af = at<Nfq, Np, SD>(sm.Fq, 4 * s + (lane >> 4), 16 * t + (lane & 15));
+            for (int t = 0; t < Mt; ++t)
 #pragma unroll
-          for (int c = 0; c < 4; ++c) accS[c][t] = mma_f32(af, b[c], accS[c][t]);
-        }
-      }
+              for (int c = 0; c < 4; ++c) accS[c][t] = mma_f32(af[t], b[c], accS[c][t]);
+          });
       wave_sync();
     }
     // triangular faces: J^s-weighted flux at local lattice nodes, then Ft^T M_f
@@ -517,26 +625,30 @@ struct PyrMfma {
         for (int c = 0; c < 4; ++c) W.F[c][n][l] = out[c];
       }
       wave_sync();
+      ksteps<Mt, Kf>(
+          Kf, [&](int t, int s) { return opLt(sm, a, tf, t, s, lane); },
+          [&](int s, const float(&lf)[Mt]) {
+            const int k = 4 * s + g;
+            const bool in = k < Nfn;
+            const int kk = in ? k : 0;
+            float b[4];
 #pragma unroll
-      for (int s = 0; s < Kf; ++s) {
-        const int k = 4 * s + g;
-        const bool in = k < Nfn;
-        const int kk = in ? k : 0;
-        float b[4];
+            for (int c = 0; c < 4; ++c) b[c] = in ? W.F[c][n][kk] : 0.f;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = in ? W.F[c][n][kk] : 0.f;
+            for (int t = 0; t < Mt; ++t)
 #pragma unroll
-        for (int t = 0; t < Mt; ++t) {
-          const float lf = sm.Lt[tf][t][s][lane];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) accS[c][t] = mma_f32(lf, b[c], accS[c][t]);
-        }
-      }
+              for (int c = 0; c < 4; ++c) accS[c][t] = mma_f32(lf[t], b[c], accS[c][t]);
+          });
       wave_sync();
     }
     // right-hand side at rows 16 t + 4 g + i (overwrites accS); 1/J from the
-    // vertices again (cheaper than keeping it live across the faces)
+    // vertices again (cheaper than keeping it live across the faces: the
+    // opaque copies keep the compiler from reusing the first evaluation)
     load_verts5(a, e, V);
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) __asm__ volatile("" : "+v"(V[v][d]));
 #pragma unroll
     for (int t = 0; t < Mt; ++t)
 #pragma unroll
@@ -550,21 +662,23 @@ struct PyrMfma {
         accS[0][t][i] *= sp;
 #pragma unroll
         for (int d = 0; d < 3; ++d) accS[1 + d][t][i] *= su;
+        __builtin_amdgcn_sched_barrier(0);
       }
     emit<0>(W, a, e0, lane, contig, rv0, accS[0]);
     emit<1>(W, a, e0, lane, contig, rv1, accS[1]);
     emit<2>(W, a, e0, lane, contig, rv2, accS[2]);
     emit<3>(W, a, e0, lane, contig, rv3, accS[3]);
-    if (stage) write_traces(sm, W, a, e0, lane, a.tr_out);
   }
 
-  __device__ static void run(Smem& sm, const StageArgs& a) {
+  __device__ __forceinline__ static void run(Smem& sm, const StageArgs& a) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    float* dst = &sm.D[0][0][0];
-    for (int i = tid; i < kOpsOpf; i += NT) dst[i] = a.ops[i];  // D, Fq, Ft are contiguous in Smem
-    float* lt = &sm.Lt[0][0][0][0];
-    for (int i = tid; i < kLFloats; i += NT) lt[i] = a.ops[kOpsOpf + i];
-    if (tid == 0) sm.w0 = a.ops[kOpsOpf + kLFloats];
+    if constexpr (!G) {
+      float* dst = &sm.D[0][0][0];
+      for (int i = tid; i < kOpsOpf; i += NT) dst[i] = a.ops[i];  // D, Fq, Ft are contiguous in Smem
+      float* lt = &sm.Lt[0][0][0][0];
+      for (int i = tid; i < kLFloats; i += NT) lt[i] = a.ops[kOpsOpf + i];
+    }
+    if (tid == 0) sm.w0 = a.ops[kLtOff + kLFloats];
     const double* gab = reinterpret_cast<const double*>(a.ops + kGabOff);
     for (int i = tid; i < 2 * Np; i += NT) (&sm.gab[0][0])[i] = gab[i];
     int* ip = &sm.qperm[0][0];
@@ -574,7 +688,14 @@ struct PyrMfma {
     __syncthreads();
     Wave& W = sm.w[wv];
     const int64_t ntile = (a.n_items + 15) / 16;
-    for (int64_t t = (int64_t)blockIdx.x * NW + wv; t < ntile; t += (int64_t)gridDim.x * NW) tile(sm, W, a, t * 16, lane);
+    for (int64_t t = (int64_t)blockIdx.x * NW + wv; t < ntile; t += (int64_t)gridDim.x * NW) {
+      // an opaque copy of the lane index keeps the lane-dependent indices
+      // inside the loop (hoisted out of it, they would stay live in
+      // registers across the whole tile)
+      int ln = lane;
+      if constexpr (G) __asm__ volatile("" : "+v"(ln));
+      tile(sm, W, a, t * 16, ln);
+    }
   }
 };
 

@@ -111,7 +111,7 @@ def test_single_type_meshes(slabs, n, path):
 
 
 @pytest.mark.parametrize("path", PATHS)
-@pytest.mark.parametrize("N", [2, 4])
+@pytest.mark.parametrize("N", [2, 4, 5])
 def test_ragged_batches_match_oracle(slab4_mesh, N, path):
     """A patch of the n=4 mesh whose per-type element counts are not multiples
     of the kernels' batch and tile sizes (odd counts, partial 16-element tiles):
