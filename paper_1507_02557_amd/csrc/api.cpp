@@ -401,13 +401,14 @@ int build_pyr_mfma_tables(hdg_ctx* c, std::vector<float>& ops, std::vector<int>&
       for (int tr = 0; tr < 2; ++tr)
         for (int r = 0; r < 3; ++r)
           for (int t = 0; t < Mt; ++t) frag(D[r]->data(), Np, Np, t, st, tr == 1);
-    for (int st = 0; st < Ks; ++st)
+    // trace operator: per k-step the base face's row tiles, then each triangle's
+    for (int st = 0; st < Ks; ++st) {
       for (int t = 0; t < Mq; ++t) frag(P.Fquad.data(), Nfq, Np, t, st, false);
+      for (int tf = 0; tf < 4; ++tf)
+        for (int t = 0; t < Mtf; ++t) frag(P.Ftri.data() + (size_t)tf * Nfn * Np, Nfn, Np, t, st, false);
+    }
     for (int st = 0; st < Kq; ++st)
       for (int t = 0; t < Mt; ++t) frag(P.Fquad.data(), Nfq, Np, t, st, true);
-    for (int tf = 0; tf < 4; ++tf)
-      for (int st = 0; st < Ks; ++st)
-        for (int t = 0; t < Mtf; ++t) frag(P.Ftri.data() + (size_t)tf * Nfn * Np, Nfn, Np, t, st, false);
   } else {
     auto rows = [&](const Vec& A, int R) {
       for (int i = 0; i < R; ++i)

@@ -93,13 +93,14 @@ struct PyrMfma {
   static constexpr int kLFloats = 4 * Mt * Kf * 64;
   // G = false: D [3][Np][SD], Fq [Nfq][SD], Ft [4][Nfn][SD] (row-major, copied
   // to the LDS as they are);
-  // G = true: fragments [64] of D and D^T [Ks][2][3][Mt], Fq [Ks][Mq],
-  // Fq^T [Kq][Mt], Ft [4][Ks][Mf] (k-step before row tile);
+  // G = true: fragments [64] of D and D^T [Ks][2][3][Mt], the trace
+  // operator [Ks][Mq + 4 Mf] (Fq's row tiles, then Ft_f's), Fq^T [Kq][Mt]
+  // (k-step before row tile);
   // then in both: the Lt fragments ([4][Mt][Kf], with G [4][Kf][Mt]), w0, and
   // the geometry points (a, b) as doubles at an even float offset
   static constexpr int kOpsOpf = G ? 0 : (3 * Np + Nfq + 4 * Nfn) * SD;
-  static constexpr int kDD = 0, kFqA = kDD + 6 * Mt * Ks * 64;
-  static constexpr int kFqT = kFqA + Mq * Ks * 64, kFtA = kFqT + Kq * Mt * 64, kFragEnd = kFtA + 4 * Mf * Ks * 64;
+  static constexpr int kDD = 0, kFW = kDD + 6 * Mt * Ks * 64;
+  static constexpr int kFqT = kFW + (Mq + 4 * Mf) * Ks * 64, kFragEnd = kFqT + Kq * Mt * 64;
   static constexpr int kLtOff = G ? kFragEnd : kOpsOpf;
   static constexpr int kGabOff = (kLtOff + kLFloats + 2) & ~1;
   static constexpr int kOpsFloats = kGabOff + 4 * Np;
@@ -190,16 +191,14 @@ struct PyrMfma {
     else return at<Np, Np, SD>(sm.D[r], 4 * s + (lane >> 4), 16 * t + (lane & 15));
   }
   __device__ __forceinline__ static float opFq(const Smem& sm, const StageArgs& a, int t, int s, int lane) {
-    if constexpr (G) return frag(a, kFqA + (s * Mq + t) * 64, lane);
-    else return at<Nfq, Np, SD>(sm.Fq, 16 * t + (lane & 15), 4 * s + (lane >> 4));
+    return at<Nfq, Np, SD>(sm.Fq, 16 * t + (lane & 15), 4 * s + (lane >> 4));
   }
   __device__ __forceinline__ static float opFqT(const Smem& sm, const StageArgs& a, int s, int t, int lane) {
     if constexpr (G) return frag(a, kFqT + (s * Mt + t) * 64, lane);
     else return at<Nfq, Np, SD>(sm.Fq, 4 * s + (lane >> 4), 16 * t + (lane & 15));
   }
   __device__ __forceinline__ static float opFt(const Smem& sm, const StageArgs& a, int tf, int t, int s, int lane) {
-    if constexpr (G) return frag(a, kFtA + ((tf * Ks + s) * Mf + t) * 64, lane);
-    else return at<Nfn, Np, SD>(sm.Ft[tf], 16 * t + (lane & 15), 4 * s + (lane >> 4));
+    return at<Nfn, Np, SD>(sm.Ft[tf], 16 * t + (lane & 15), 4 * s + (lane >> 4));
   }
   __device__ __forceinline__ static float opLt(const Smem& sm, const StageArgs& a, int tf, int t, int s, int lane) {
     if constexpr (G) return frag(a, kLtOff + ((tf * Kf + s) * Mt + t) * 64, lane);
@@ -281,80 +280,87 @@ struct PyrMfma {
   }
 
   // ---- traces of the tile's state: base face at canonical GL points,
-  // triangles at canonical lattice nodes
-  __device__ __forceinline__ static void write_traces(const Smem& sm, const Wave& W, const StageArgs& a, int64_t e0, int lane,
-                                      float4* tr) {
+  // triangles at canonical lattice nodes.  One k-loop for all five faces:
+  // row tiles u < Mq are the base face's (Fq), the others Mf per triangle
+  // (Ft_f), so each state entry is read from the LDS once per step and a step
+  // has 4 (Mq + 4 Mf) independent products.
+  static constexpr int MW = Mq + 4 * Mf;
+  __device__ __forceinline__ static float opW(const Smem& sm, const StageArgs& a, int u, int s, int lane) {
+    if constexpr (G) return frag(a, kFW + (s * MW + u) * 64, lane);
+    else if (u < Mq) return opFq(sm, a, u, s, lane);
+    else return opFt(sm, a, (u - Mq) / Mf, (u - Mq) % Mf, s, lane);
+  }
+  __device__ __forceinline__ static void write_traces(const Smem& sm, const Wave& W, const StageArgs& a, int64_t e0,
+                                                      int lane, float4* tr) {
     const int n = lane & 15, g = lane >> 4;
     const int64_t e = item(a, e0 + n);
     const int64_t slot = a.slot0 + (e >= 0 ? e : 0) * 5;
-    // base face: T = Fq u (rows = local GL points)
-    {
-      f32x4 acc[4][Mq];
+    f32x4 acc[MW][4];
 #pragma unroll
-      for (int t = 0; t < Mq; ++t)
+    for (int u = 0; u < MW; ++u)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-      ksteps<Mq, 2>(
-          Ks, [&](int t, int s) { return opFq(sm, a, t, s, lane); },
-          [&](int s, const float(&af)[Mq]) {
-            const int k = 4 * s + g;
-            const bool in = k < Np;
-            const int kk = in ? k : 0;
-            float b[4];
+      for (int c = 0; c < 4; ++c) acc[u][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    ksteps<MW, 2>(
+        Ks, [&](int u, int s) { return opW(sm, a, u, s, lane); },
+        [&](int s, const float(&af)[MW]) {
+          const int k = 4 * s + g;
+          const bool in = k < Np;
+          const int kk = in ? k : 0;
+          float b[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] = in ? W.X[c][n][kk] : 0.f;
+          for (int c = 0; c < 4; ++c) b[c] = in ? W.X[c][n][kk] : 0.f;
 #pragma unroll
-            for (int t = 0; t < Mq; ++t)
+          for (int u = 0; u < MW; ++u)
 #pragma unroll
-              for (int c = 0; c < 4; ++c) acc[c][t] = mma_f32(af[t], b[c], acc[c][t]);
-          });
-      const int o = e >= 0 ? a.ori[slot] : 0;
+            for (int c = 0; c < 4; ++c) acc[u][c] = mma_f32(af[u], b[c], acc[u][c]);
+        });
+    if (e < 0) return;
+    int ori[5];
 #pragma unroll
-      for (int t = 0; t < Mq; ++t)
+    for (int f = 0; f < 5; ++f) ori[f] = a.ori[slot + f];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int l = 16 * t + 4 * g + i;
-          if (e >= 0 && l < Nfq)
-            tr[slot * TS + sm.iqperm[o][l]] = make_float4(acc[0][t][i], acc[1][t][i], acc[2][t][i], acc[3][t][i]);
-          else if (e >= 0 && l < TS)  // padding to whole lines
-            tr[slot * TS + l] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int u = 0; u < MW; ++u) {
+      const int f = u < Mq ? 0 : 1 + (u - Mq) / Mf;
+      const int t = u < Mq ? u : (u - Mq) % Mf;
+      float4* dst = tr + (slot + f) * TS;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int l = 16 * t + 4 * g + i;
+        const float4 v = make_float4(acc[u][0][i], acc[u][1][i], acc[u][2][i], acc[u][3][i]);
+        if (f == 0) {
+          if (l < Nfq) dst[sm.iqperm[ori[0]][l]] = v;
+          else if (l < TS) dst[l] = make_float4(0.f, 0.f, 0.f, 0.f);  // padding to whole lines
+        } else {
+          if (l < Nfn) dst[sm.itperm[ori[f]][l]] = v;
+          else if (l < LW) dst[l] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
+      }
     }
-    // triangular faces: lattice values Ft_f u (rows = local lattice nodes)
-#pragma unroll 1
-    for (int tf = 0; tf < 4; ++tf) {
-      f32x4 acc[4][Mf];
+  }
+
+  // a triangle's own and neighbour lattice traces and its face factors
+  struct TriIn {
+    float4 own[JF], pv[JF], gf;
+  };
+  __device__ __forceinline__ static void load_tri(const StageArgs& a, int64_t e, int64_t slot0, int tf, int nb,
+                                                  bool mid, int g, TriIn& x) {
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int64_t slot = slot0 + 1 + tf;
+    const float4* nsrc = mid ? a.tr_half : a.tr_in;
+    float4 gf = z4;
+    if (e >= 0) gf = a.fgeo[(slot - a.slot0) * Nfq];
 #pragma unroll
-      for (int t = 0; t < Mf; ++t)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-      ksteps<Mf, 2>(
-          Ks, [&](int t, int s) { return opFt(sm, a, tf, t, s, lane); },
-          [&](int s, const float(&af)[Mf]) {
-            const int k = 4 * s + g;
-            const bool in = k < Np;
-            const int kk = in ? k : 0;
-            float b[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] = in ? W.X[c][n][kk] : 0.f;
-#pragma unroll
-            for (int t = 0; t < Mf; ++t)
-#pragma unroll
-              for (int c = 0; c < 4; ++c) acc[c][t] = mma_f32(af[t], b[c], acc[c][t]);
-          });
-      const int o = e >= 0 ? a.ori[slot + 1 + tf] : 0;
-#pragma unroll
-      for (int t = 0; t < Mf; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int l = 16 * t + 4 * g + i;
-          if (e >= 0 && l < Nfn)
-            tr[(slot + 1 + tf) * TS + sm.itperm[o][l]] =
-                make_float4(acc[0][t][i], acc[1][t][i], acc[2][t][i], acc[3][t][i]);
-          else if (e >= 0 && l < LW)  // padding to whole lines
-            tr[(slot + 1 + tf) * TS + l] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
+    for (int j = 0; j < JF; ++j) {
+      const int m = g + 4 * j;
+      float4 own = z4, pv = z4;
+      if (e >= 0 && m < Nfn) {
+        own = a.tr_in[slot * TS + m];
+        if (nb >= 0) pv = nsrc[(int64_t)nb * TS + m];
+      }
+      x.own[j] = own;
+      x.pv[j] = pv;
     }
+    x.gf = gf;
   }
 
   // vertices of element e (a reference pyramid for e < 0, keeping the
@@ -439,6 +445,26 @@ struct PyrMfma {
     if (e >= 0) {
       kap = a.mat[e].x;
       irho = a.mat[e].y;
+    }
+    // face records (neighbour or boundary code, orientation, penalties, and
+    // whether the neighbour's traces are the mid-step ones), read now so that
+    // their latency passes during the volume products
+    const int64_t slot0 = a.slot0 + (e >= 0 ? e : 0) * 5;
+    int rnb[5], rori[5];
+    bool rmid[5];
+    float2 rtau[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      rnb[f] = -1;
+      rori[f] = 0;
+      rmid[f] = false;
+      rtau[f] = make_float2(0.f, 0.f);
+      if (e >= 0) {
+        rnb[f] = a.nbr[slot0 + f];
+        rori[f] = a.ori[slot0 + f];
+        rtau[f] = a.tau[slot0 + f];
+        if (rnb[f] >= 0) rmid[f] = neighbour_mid(a, slot0 + f, rnb[f]);
+      }
     }
     // volume: grad = D^r p, div = sum_r (D^r)^T U^r
     f32x4 accG[3][Mt], accV[Mt];
@@ -535,80 +561,62 @@ struct PyrMfma {
       load_field(rv2, a.R + 2 * fs, e0, lane);
       load_field(rv3, a.R + 3 * fs, e0, lane);
     }
-    // surface term S
-    const int64_t slot0 = a.slot0 + (e >= 0 ? e : 0) * 5;
-    // base face: weighted flux at local GL points, then Fq^T
-    {
-      int nb = -1, o = 0;
-      float2 tau = make_float2(0.f, 0.f);
-      const float4* nsrc = a.tr_in;
-      if (e >= 0) {
-        nb = a.nbr[slot0];
-        o = a.ori[slot0];
-        tau = a.tau[slot0];
-        if (nb >= 0) nsrc = neighbour_src(a, slot0, nb);
+    // surface term S.  The trace loads of the base face and of the first
+    // triangle are issued together; each triangle's are issued before the
+    // previous triangle is processed.
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 bown[JB], bpv[JB], bg[JB];
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+      const int q = g + 4 * j;
+      bown[j] = bpv[j] = bg[j] = z4;
+      if (e >= 0 && q < Nfq) {
+        bown[j] = a.tr_in[slot0 * TS + q];
+        bg[j] = a.fgeo[(slot0 - a.slot0) * Nfq + q];
+        if (rnb[0] >= 0) bpv[j] = (rmid[0] ? a.tr_half : a.tr_in)[(int64_t)rnb[0] * TS + q];
       }
-#pragma unroll
-      for (int j0 = 0; j0 < JB; j0 += 2) {
-        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-        float4 own[2] = {z4, z4}, pv[2] = {z4, z4}, gq[2] = {z4, z4};
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
-          const int q = g + 4 * (j0 + jj);
-          if (e >= 0 && j0 + jj < JB && q < Nfq) {
-            own[jj] = a.tr_in[slot0 * TS + q];
-            gq[jj] = a.fgeo[(slot0 - a.slot0) * Nfq + q];
-            if (nb >= 0) pv[jj] = nsrc[(int64_t)nb * TS + q];
-          }
-        }
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
-          const int q = g + 4 * (j0 + jj);
-          if (j0 + jj >= JB || q >= Nfq) continue;
-          float out[4] = {0.f, 0.f, 0.f, 0.f};
-          int l = q;
-          if (e >= 0) {
-            l = sm.qperm[o][q];
-            const float4 p = nb >= 0 ? pv[jj] : mirror_state(own[jj], -nb - 1, gq[jj].x, gq[jj].y, gq[jj].z);
-            upwind_flux(own[jj], p, gq[jj], tau, true, out);
-          }
-#pragma unroll
-          for (int c = 0; c < 4; ++c) W.F[c][n][l] = out[c];
-        }
-      }
-      wave_sync();
-      ksteps<Mt, 1>(
-          Kq, [&](int t, int s) { return opFqT(sm, a, s, t, lane); },
-          [&](int s, const float(&af)[Mt]) {
-            const int k = 4 * s + g;
-            const bool in = k < Nfq;
-            const int kk = in ? k : 0;
-            float b[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] = in ? W.F[c][n][kk] : 0.f;
-#pragma unroll
-            for (int t = 0; t < Mt; ++t)
-#pragma unroll
-              for (int c = 0; c < 4; ++c) accS[c][t] = mma_f32(af[t], b[c], accS[c][t]);
-          });
-      wave_sync();
     }
-    // triangular faces: J^s-weighted flux at local lattice nodes, then Ft^T M_f
-#pragma unroll 1
-    for (int tf = 0; tf < 4; ++tf) {
-      const int64_t slot = slot0 + 1 + tf;
-      int nb = -1, o = 0;
-      float2 tau = make_float2(0.f, 0.f);
-      float4 gf = make_float4(0.f, 0.f, 0.f, 0.f);
-      const float4* nsrc = a.tr_in;
+    TriIn tri[2];  // (indexed by the unrolled face counter: registers, not memory)
+    load_tri(a, e, slot0, 0, rnb[1], rmid[1], g, tri[0]);
+    // base face: weighted flux at local GL points, then Fq^T
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+      const int q = g + 4 * j;
+      if (q >= Nfq) continue;
+      float out[4] = {0.f, 0.f, 0.f, 0.f};
+      int l = q;
       if (e >= 0) {
-        nb = a.nbr[slot];
-        o = a.ori[slot];
-        tau = a.tau[slot];
-        gf = a.fgeo[(slot - a.slot0) * Nfq];
-        gf.w /= sm.w0;  // J^s (the stored value carries the weight of point 0)
-        if (nb >= 0) nsrc = neighbour_src(a, slot, nb);
+        l = sm.qperm[rori[0]][q];
+        const float4 p = rnb[0] >= 0 ? bpv[j] : mirror_state(bown[j], -rnb[0] - 1, bg[j].x, bg[j].y, bg[j].z);
+        upwind_flux(bown[j], p, bg[j], rtau[0], true, out);
       }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) W.F[c][n][l] = out[c];
+    }
+    wave_sync();
+    ksteps<Mt, 1>(
+        Kq, [&](int t, int s) { return opFqT(sm, a, s, t, lane); },
+        [&](int s, const float(&af)[Mt]) {
+          const int k = 4 * s + g;
+          const bool in = k < Nfq;
+          const int kk = in ? k : 0;
+          float b[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) b[c] = in ? W.F[c][n][kk] : 0.f;
+#pragma unroll
+          for (int t = 0; t < Mt; ++t)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) accS[c][t] = mma_f32(af[t], b[c], accS[c][t]);
+        });
+    wave_sync();
+    // triangular faces: J^s-weighted flux at local lattice nodes, then Ft^T M_f
+#pragma unroll
+    for (int tf = 0; tf < 4; ++tf) {
+      if (tf < 3) load_tri(a, e, slot0, tf + 1, rnb[tf + 2], rmid[tf + 2], g, tri[(tf + 1) & 1]);
+      const TriIn& cur = tri[tf & 1];
+      const int nb = rnb[1 + tf];
+      float4 gf = cur.gf;
+      gf.w /= sm.w0;  // J^s (the stored value carries the weight of point 0)
 #pragma unroll
       for (int j = 0; j < JF; ++j) {
         const int m = g + 4 * j;
@@ -616,10 +624,9 @@ struct PyrMfma {
         float out[4] = {0.f, 0.f, 0.f, 0.f};
         int l = m;
         if (e >= 0) {
-          const float4 own = a.tr_in[slot * TS + m];
-          const float4 p = nb >= 0 ? nsrc[(int64_t)nb * TS + m] : mirror_state(own, -nb - 1, gf.x, gf.y, gf.z);
-          l = sm.tperm[o][m];
-          upwind_flux(own, p, gf, tau, true, out);
+          const float4 p = nb >= 0 ? cur.pv[j] : mirror_state(cur.own[j], -nb - 1, gf.x, gf.y, gf.z);
+          l = sm.tperm[rori[1 + tf]][m];
+          upwind_flux(cur.own[j], p, gf, rtau[1 + tf], true, out);
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) W.F[c][n][l] = out[c];
