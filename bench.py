@@ -173,7 +173,7 @@ MRAB_KERNELS = {
     (0, 0, 4): "stage_kernel<hdg::HexStage<4, 4> >", (1, 0, 4): "mrab_update_kernel<hdg::HexStage<4, 4> >",
     (0, 1, 4): "stage_kernel<hdg::WedgeStage<4, 2> >", (1, 1, 4): "mrab_update_kernel<hdg::WedgeStage<4, 2> >",
     (0, 2, 4): "pyr_mfma_kernel<hdg::PyrMfma<4, 4> >",
-    (1, 2, 4): "wave_mrab_update_kernel<hdg::PyrStage<4, 1, 64>, 12>",
+    (1, 2, 4): "pyr_mrab_update_kernel<hdg::PyrMfma<4, 4> >",
     (0, 3, 4): "tet_mfma_kernel<hdg::TetMfma<4, 8, 0, false> >",
     (1, 3, 4): "tet_mrab_update_kernel<hdg::TetMfma<4, 8, 0, true> >",
 }

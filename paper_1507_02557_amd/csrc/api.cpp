@@ -468,13 +468,13 @@ bool use_lattice(const hdg_ctx* c) { return c->path == HDG_PATH_AUTO && c->latti
 int launch_type(hdg_ctx* c, int t, StageArgs a, bool mrab) {
   a.lat = use_lattice(c) ? 1 : 0;
   a.V = c->td[t].V;
-  // The matrix-core pyramid kernel serves the stage and right-hand-side
-  // modes at N = 3..5 (the multi-rate right-hand side included); the
-  // multi-rate update and N <= 2 use the wavefront-batched vector kernels.
-  const bool pyr_mfma = t == kPyr && a.lat && c->td[t].mops && !mrab && c->N >= 3;
+  // The matrix-core pyramid kernel serves every mode at N = 3..5; N <= 2
+  // uses the wavefront-batched vector kernels.
+  const bool pyr_mfma = t == kPyr && a.lat && c->td[t].mops && c->N >= 3;
   if (pyr_mfma) {
     a.ops = c->td[t].mops;
     a.iops = c->td[t].miops;
+    if (mrab) a.mode = kModeMrab;
     if (launch_pyr_mfma(c->N, a, c->stream, c->max_blocks)) return fail(c, HDG_EINVAL, "no kernel for this order");
     return HDG_OK;
   }

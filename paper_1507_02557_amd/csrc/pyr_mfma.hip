@@ -11,7 +11,14 @@ namespace hdg {
 template <class S>
 __global__ __launch_bounds__(S::NT) void pyr_mfma_kernel(StageArgs a) {
   __shared__ typename S::Smem sm;
-  S::run(sm, a);
+  S::template run<false>(sm, a);
+}
+
+// multi-rate AB3 update of the pyramids (kModeMrab)
+template <class S>
+__global__ __launch_bounds__(S::NT) void pyr_mrab_update_kernel(StageArgs a) {
+  __shared__ typename S::Smem sm;
+  S::template run<true>(sm, a);
 }
 
 // operator tables in global memory when they do not fit the LDS beside one
@@ -40,7 +47,8 @@ static int go(const StageArgs& a, hipStream_t s, int max_blocks) {
   const int64_t ntile = (a.n_items + 15) / 16;
   const int64_t nblk = (ntile + S::NT / 64 - 1) / (S::NT / 64);
   const unsigned grid = (unsigned)(nblk < max_blocks ? nblk : max_blocks);
-  hipLaunchKernelGGL(pyr_mfma_kernel<S>, dim3(grid), dim3(S::NT), 0, s, a);
+  if (a.mode == kModeMrab) hipLaunchKernelGGL(pyr_mrab_update_kernel<S>, dim3(grid), dim3(S::NT), 0, s, a);
+  else hipLaunchKernelGGL(pyr_mfma_kernel<S>, dim3(grid), dim3(S::NT), 0, s, a);
   return 0;
 }
 

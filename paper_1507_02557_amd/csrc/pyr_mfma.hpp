@@ -420,12 +420,103 @@ struct PyrMfma {
     wave_sync();
   }
 
-  // One tile in the stage, right-hand-side and trace modes (the multi-rate
-  // update of pyramids runs on the vector kernels).
+  // Multi-rate AB3 update of a tile: u_new = u + dtau_l sum_j beta_j(1) r_j
+  // (state and traces) and, when an element of the tile has a finer
+  // neighbour, the mid-step state u + dtau_l sum_j beta_j(1/2) r_j (traces
+  // only).  A contiguous tile of one level reads u and the history once, as
+  // vectors; otherwise each value is combined on its own, the mid-step state
+  // first (u is still the old state then).
+  __device__ __forceinline__ static void mrab(const Smem& sm, Wave& W, const StageArgs& a, int64_t e0, int lane,
+                                              bool contig) {
+    const int64_t K = a.K, fs = K * Np, hstr = 4 * fs;
+    bool hf = false;
+    {
+      const int64_t e = item(a, e0 + (lane & 15));
+      hf = e >= 0 && a.ehalf[e] != 0;
+    }
+    const bool half = __ballot(hf) != 0;
+    if (contig && a.elevel[e0] == a.elevel[e0 + 15]) {
+      const int lv = a.elevel[e0];
+      const float dtl = a.mr.dtl[lv];
+      float b1[3], bh[3];
+      const float* hj[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        b1[j] = a.mr.b1[lv][j];
+        bh[j] = a.mr.bh[lv][j];
+        hj[j] = a.H + a.mr.hs[lv][j] * hstr;
+      }
+      float4 mid[4][JQ];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        float4 u[JQ], h0[JQ], h1[JQ], h2[JQ];
+        load_field(u, a.U + c * fs, e0, lane);
+        load_field(h0, hj[0] + c * fs, e0, lane);
+        load_field(h1, hj[1] + c * fs, e0, lane);
+        load_field(h2, hj[2] + c * fs, e0, lane);
+        float4 un[JQ];
+#pragma unroll
+        for (int j = 0; j < JQ; ++j) {
+          if (lane + 64 * j >= Q4) continue;
+          const float4 x = u[j], p = h0[j], q = h1[j], r = h2[j];
+          un[j] = make_float4(x.x + dtl * (b1[0] * p.x + b1[1] * q.x + b1[2] * r.x),
+                              x.y + dtl * (b1[0] * p.y + b1[1] * q.y + b1[2] * r.y),
+                              x.z + dtl * (b1[0] * p.z + b1[1] * q.z + b1[2] * r.z),
+                              x.w + dtl * (b1[0] * p.w + b1[1] * q.w + b1[2] * r.w));
+          mid[c][j] = make_float4(x.x + dtl * (bh[0] * p.x + bh[1] * q.x + bh[2] * r.x),
+                                  x.y + dtl * (bh[0] * p.y + bh[1] * q.y + bh[2] * r.y),
+                                  x.z + dtl * (bh[0] * p.z + bh[1] * q.z + bh[2] * r.z),
+                                  x.w + dtl * (bh[0] * p.w + bh[1] * q.w + bh[2] * r.w));
+          reinterpret_cast<float4*>(a.U + c * fs + e0 * Np)[lane + 64 * j] = un[j];
+        }
+        put_field(W.X[c], un, lane);
+      }
+      wave_sync();
+      write_traces(sm, W, a, e0, lane, a.tr_out);
+      if (!half) return;
+      wave_sync();  // the traces have read the tile
+#pragma unroll
+      for (int c = 0; c < 4; ++c) put_field(W.X[c], mid[c], lane);
+      wave_sync();
+      write_traces(sm, W, a, e0, lane, a.tr_half);
+      return;
+    }
+    for (int pass = half ? 0 : 1; pass < 2; ++pass) {
+      const bool m = pass == 0;  // mid-step state first, then the new state
+#pragma unroll 1
+      for (int it = lane; it < 4 * 16 * Np; it += 64) {
+        const int c = it / (16 * Np), r = it - c * 16 * Np;
+        const int nn = r / Np, k = r - nn * Np;
+        const int64_t ee = item(a, e0 + nn);
+        float v = 0.f;
+        if (ee >= 0) {
+          const int lv = a.elevel[ee];
+          const float* w = m ? a.mr.bh[lv] : a.mr.b1[lv];
+          const int64_t gi = c * fs + ee * Np + k;
+          const float acc = w[0] * a.H[a.mr.hs[lv][0] * hstr + gi] + w[1] * a.H[a.mr.hs[lv][1] * hstr + gi] +
+                            w[2] * a.H[a.mr.hs[lv][2] * hstr + gi];
+          v = a.U[gi] + a.mr.dtl[lv] * acc;
+          if (!m) a.U[gi] = v;
+        }
+        W.X[c][nn][k] = v;
+      }
+      wave_sync();
+      write_traces(sm, W, a, e0, lane, m ? a.tr_half : a.tr_out);
+      wave_sync();
+    }
+  }
+
+  // One tile: the multi-rate update (MR), or the stage, right-hand-side and
+  // trace modes.
+  template <bool MR>
   __device__ __forceinline__ static void tile(const Smem& sm, Wave& W, const StageArgs& a, int64_t e0, int lane) {
     const bool contig = contiguous(a, e0);
     // lanes of the previous tile may still read other columns of the tile
     wave_sync();
+    if constexpr (MR) {
+      mrab(sm, W, a, e0, lane, contig);
+      return;
+    }
     load_state(W, a, e0, lane, contig);
     wave_sync();
     if (a.mode != kModeTrace) rhs(sm, W, a, e0, lane, contig);
@@ -677,6 +768,7 @@ struct PyrMfma {
     emit<3>(W, a, e0, lane, contig, rv3, accS[3]);
   }
 
+  template <bool MR>
   __device__ __forceinline__ static void run(Smem& sm, const StageArgs& a) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if constexpr (!G) {
@@ -701,7 +793,7 @@ struct PyrMfma {
       // registers across the whole tile)
       int ln = lane;
       if constexpr (G) __asm__ volatile("" : "+v"(ln));
-      tile(sm, W, a, t * 16, ln);
+      tile<MR>(sm, W, a, t * 16, ln);
     }
   }
 };
