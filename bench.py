@@ -171,7 +171,8 @@ def measured_traffic(kernel_name: str, also: str = "", section: str = "bytes_per
 # multi-rate kernels of the refined workload at N = 4, FP32, by (kind, type, N)
 MRAB_KERNELS = {
     (0, 0, 4): "stage_kernel<hdg::HexStage<4, 4> >", (1, 0, 4): "mrab_update_kernel<hdg::HexStage<4, 4> >",
-    (0, 1, 4): "stage_kernel<hdg::WedgeStage<4, 2> >", (1, 1, 4): "mrab_update_kernel<hdg::WedgeStage<4, 2> >",
+    (0, 1, 4): "stage_kernel<hdg::WedgeStage<4, 2, 256> >",
+    (1, 1, 4): "wave_mrab_update_kernel<hdg::WedgeStage<4, 1, 64>, 14>",
     (0, 2, 4): "pyr_mfma_kernel<hdg::PyrMfma<4, 4> >",
     (1, 2, 4): "pyr_mrab_update_kernel<hdg::PyrMfma<4, 4> >",
     (0, 3, 4): "tet_mfma_kernel<hdg::TetMfma<4, 8, 0, false> >",

@@ -19,4 +19,9 @@ constexpr int epb(int type, int N) {
 // wavefront's registers fit without spilling (N = 3 needs more than 168).
 constexpr int pyr_waves(int N) { return N == 4 ? 12 : (N == 3 ? 8 : 16); }
 
+// Wavefronts per block of the wavefront-batched wedge kernel (the multi-rate
+// update at N = 4): fourteen batches of one element beside the tables fill
+// the LDS.
+constexpr int wedge_waves(int N) { return N == 5 ? 8 : (N == 4 ? 14 : 16); }
+
 }  // namespace hdg

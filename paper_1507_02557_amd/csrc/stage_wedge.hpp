@@ -18,7 +18,7 @@
 
 namespace hdg {
 
-template <int N, int EPB>
+template <int N, int EPB, int NTH = 256>
 struct WedgeStage {
   static constexpr int n1 = N + 1;
   static constexpr int Ntri = (N + 1) * (N + 2) / 2;
@@ -28,7 +28,7 @@ struct WedgeStage {
   static constexpr int Nfq = n1 * n1;
   static constexpr int TS = trace_stride(N);
   static constexpr int Nfn = Ntri;
-  static constexpr int NT = 256;
+  static constexpr int NT = NTH;
   static constexpr int kEPB = EPB;
   static constexpr int nphase = 6;
   static constexpr int kTraceBegin = 3;  // first phase that writes traces
@@ -40,10 +40,13 @@ struct WedgeStage {
   static constexpr int kOpsFloats = oIc + Nfq * Nfn;
   static constexpr int kOpsInts = 8 * Nfq + 6 * Nfn;
 
-  struct Smem {
+  // operator tables (shared by all batches of a block) and one batch's data
+  struct Ops {
     float ops[kOpsFloats];
     int qperm[8][Nfq];
     int tperm[6][Nfn];
+  };
+  struct Batch {
     float u[4][EPB][Np];
     // buffers whose lifetimes do not overlap share storage (phase parts in
     // brackets write / read them: 0 loads and face fluxes, 1a s-contraction,
@@ -66,6 +69,23 @@ struct WedgeStage {
     float isj[EPB][5][Nfq];  // 1/sqrt(J) at the face points [0] / [0, 4, 5]
     int fori[EPB][5];        // face orientation codes [0] / [0, 4, 5]
   };
+  struct Smem {
+    Ops o;
+    Batch b;
+  };
+  // a wavefront's view: the block's tables and the wavefront's own batch
+  struct WaveRef {
+    const Ops& o;
+    Batch& b;
+  };
+  HD static Batch& batch(Smem& sm) { return sm.b; }
+  HD static Batch& batch(WaveRef& r) { return r.b; }
+  // barrier between the two parts of a phase: the block's, or the
+  // wavefront's when one wavefront runs the batch
+  HD static void batch_sync() {
+    if constexpr (NT == 64) wave_sync();
+    else __syncthreads();
+  }
 
   HD static bool active(int ph, int mode) {
     if (mode == kModeTrace) return ph == 0 || ph >= kTraceBegin;
@@ -73,17 +93,20 @@ struct WedgeStage {
     return true;
   }
 
-  HD static Smem& batch(Smem& sm) { return sm; }
-
-  HD static void load_ops(int tid, Smem& sm, const StageArgs& a) {
-    for (int i = tid; i < kOpsFloats; i += NT) sm.ops[i] = a.ops[i];
-    for (int i = tid; i < 8 * Nfq; i += NT) (&sm.qperm[0][0])[i] = a.iops[i];
-    for (int i = tid; i < 6 * Nfn; i += NT) (&sm.tperm[0][0])[i] = a.iops[8 * Nfq + i];
+  // tables into LDS by nthr threads
+  HD static void load_ops(int tid, int nthr, Ops& o, const StageArgs& a) {
+    for (int i = tid; i < kOpsFloats; i += nthr) o.ops[i] = a.ops[i];
+    for (int i = tid; i < 8 * Nfq; i += nthr) (&o.qperm[0][0])[i] = a.iops[i];
+    for (int i = tid; i < 6 * Nfn; i += nthr) (&o.tperm[0][0])[i] = a.iops[8 * Nfq + i];
   }
+  HD static void load_ops(int tid, Smem& sm, const StageArgs& a) { load_ops(tid, NT, sm.o, a); }
 
-  HD static void phase(int ph, int tid, Smem& sm, const StageArgs& a, int64_t e0) {
+  HD static void phase(int ph, int tid, Smem& sm, const StageArgs& a, int64_t e0) { phase(ph, tid, sm.o, sm.b, a, e0); }
+  HD static void phase(int ph, int tid, WaveRef& r, const StageArgs& a, int64_t e0) { phase(ph, tid, r.o, r.b, a, e0); }
+
+  HD static void phase(int ph, int tid, const Ops& op, Batch& sm, const StageArgs& a, int64_t e0) {
     const int64_t K = a.K;
-    const float* O = sm.ops;
+    const float* O = op.ops;
     // triangle basis and its r, t derivatives at the triangle points, read as one vector
     const float4* P3 = reinterpret_cast<const float4*>(O + oP3);
     const float* Tw = O + oTw;
@@ -154,7 +177,7 @@ struct WedgeStage {
         if (!flux) continue;
         float out[4];
         upwind_flux(fm[r], fp[r], fg[r], ftau[r], true, out);
-        const int l = (f < 2) ? q : sm.qperm[fo[r]][q];
+        const int l = (f < 2) ? q : op.qperm[fo[r]][q];
         float* gd = sm.g[el][f][l];
         for (int c = 0; c < 4; ++c) gd[c] = out[c] * fisj[r];
       }
@@ -183,7 +206,7 @@ struct WedgeStage {
       }
       // the rest of the phase reads what the first part wrote: one barrier
       // (every thread of the block runs every phase)
-      __syncthreads();
+      batch_sync();
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         const int it = tid + r * NT;
@@ -231,7 +254,7 @@ struct WedgeStage {
           const float w = Ic[q * Nfn + m];
           for (int c = 0; c < 4; ++c) acc[c] += w * sm.g[el][tf][q][c];
         }
-        const int l = sm.tperm[o][m];
+        const int l = op.tperm[o][m];
         for (int c = 0; c < 4; ++c) sm.c[el][tf][l][c] = acc[c];
       }
     } else if (ph == 2) {
@@ -291,7 +314,7 @@ struct WedgeStage {
       }
       // the rest of the phase reads what the first part wrote: one barrier
       // (every thread of the block runs every phase)
-      __syncthreads();
+      batch_sync();
 #pragma unroll
       for (int r = 0; r < RN; ++r) {
         const int it = tid + r * NT;
@@ -363,7 +386,7 @@ struct WedgeStage {
         if (e < 0) continue;
         const int f = 2 + ef;
         const int64_t slot = a.slot0 + e * 5 + f;
-        const int l = sm.qperm[sm.fori[el][f]][q];
+        const int l = op.qperm[sm.fori[el][f]][q];
         const int l1 = l % n1, l2 = l / n1;
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int js = 0; js < n1; ++js) {
@@ -385,7 +408,7 @@ struct WedgeStage {
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         for (int m = 0; m < Nfn; ++m) {
           const float w = Ic[q * Nfn + m];
-          const int l = sm.tperm[o][m];
+          const int l = op.tperm[o][m];
           for (int c = 0; c < 4; ++c) acc[c] += w * sm.c[el][tf][l][c];
         }
         const float isj = sm.isj[el][tf][q];

@@ -16,8 +16,8 @@ template <class S>
 struct Occupancy {
   static constexpr int value = 1;
 };
-template <int N, int E>
-struct Occupancy<WedgeStage<N, E>> {
+template <int N, int E, int T>
+struct Occupancy<WedgeStage<N, E, T>> {
   static constexpr int value = N == 4 ? 5 : (N < 4 ? 3 : 1);
 };
 
@@ -165,7 +165,13 @@ template <int N>
 static int launch_n(int type, const StageArgs& a, hipStream_t s, bool mrab) {
   switch (type) {
     case 0: return go<HexStage<N, epb(0, N)>>(a, s, mrab);
-    case 1: return go<WedgeStage<N, epb(1, N)>>(a, s, mrab);
+    case 1:
+      // the multi-rate update runs faster wavefront-batched, the stage and
+      // right-hand side in blocks of EPB elements (measured at N = 4)
+      if constexpr (N == 4) {
+        if (mrab) return go_wave<WedgeStage<N, 1, 64>, wedge_waves(N)>(a, s, mrab);
+      }
+      return go<WedgeStage<N, epb(1, N)>>(a, s, mrab);
     case 2:
       if constexpr (N <= 4) return go_wave<PyrStage<N, 1, 64>, pyr_waves(N)>(a, s, mrab);
       else return go<PyrStage<N, epb(2, N)>>(a, s, mrab);
