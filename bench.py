@@ -173,10 +173,17 @@ MRAB_KERNELS = {
     (0, 0, 4): "stage_kernel<hdg::HexStage<4, 4> >", (1, 0, 4): "mrab_update_kernel<hdg::HexStage<4, 4> >",
     (0, 1, 4): "stage_kernel<hdg::WedgeStage<4, 2, 256> >",
     (1, 1, 4): "wave_mrab_update_kernel<hdg::WedgeStage<4, 1, 64>, 14>",
-    (0, 2, 4): "pyr_mfma_kernel<hdg::PyrMfma<4, 4> >",
-    (1, 2, 4): "pyr_mrab_update_kernel<hdg::PyrMfma<4, 4> >",
+    (0, 2, 4): "pyr_mfma_kernel<hdg::PyrMfma<4, 4, false> >",
+    (1, 2, 4): "pyr_mrab_update_kernel<hdg::PyrMfma<4, 4, false> >",
     (0, 3, 4): "tet_mfma_kernel<hdg::TetMfma<4, 8, 0, false> >",
     (1, 3, 4): "tet_mrab_update_kernel<hdg::TetMfma<4, 8, 0, true> >",
+}
+
+
+# single-rate stage kernels of the four-slab workload at N = 4, by type
+STAGE_KERNELS = {
+    0: "stage_kernel<hdg::HexStage<4, 4> >", 1: "stage_kernel<hdg::WedgeStage<4, 2, 256> >",
+    2: "pyr_mfma_kernel<hdg::PyrMfma<4, 4, false> >", 3: "tet_mfma_kernel<hdg::TetMfma<4, 8, 0, true> >",
 }
 
 
@@ -642,8 +649,11 @@ def run_four_slab(args, hdg, torch, np):
         ms_t = float(kms[0][t]) / kcnt[0][t]
         b = alg_bytes(t, N, lattice) * s.info[t][0]
         ach = b / (ms_t * 1e-3) / 1e9
+        # HBM bytes per stage launch from the counters (taken on the n = 48 mesh at N = 4)
+        tr = measured_traffic(STAGE_KERNELS[t]) if (N == 4 and args.n == 48 and lattice) else None
         roof[name] = {"bound": "hbm", "ms_per_launch": round(ms_t, 4), "achieved": round(ach, 1),
-                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                      "traffic": None if tr is None else int(tr),
                       "alg_bytes_per_launch": int(b), "alg_bytes_per_element": alg_bytes(t, N, lattice)}
     dominant = max(roof, key=lambda k: roof[k]["ms_per_launch"])
     out = {

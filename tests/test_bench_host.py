@@ -93,6 +93,8 @@ def test_source_hash_is_stable_and_keys_the_traffic_file():
     if data["source_hash"] == h:
         for name in bench.MRAB_KERNELS.values():
             assert bench.measured_traffic(name, section="bytes_per_coarse_step") > 0, name
+        for name in bench.STAGE_KERNELS.values():
+            assert bench.measured_traffic(name, section="bytes_per_launch") > 0, name
 
 
 def test_more_than_one_gpu_is_refused():
