@@ -54,8 +54,9 @@ __global__ __launch_bounds__(kFacesPerBlock* kLanes) void mortar_kernel(MortarAr
   const int64_t i = (int64_t)blockIdx.x * kFacesPerBlock + lf;
   const bool face = i < a.n;
   const bool act = face && m < a.nfn;
-  // written slots are padded with zeros to whole lines
-  const bool pad = face && m >= a.nfn && m < (a.nfn + 7) / 8 * 8;
+  // written slots are padded with zeros to whole lines (within the slot)
+  const int lw = (a.nfn + 7) / 8 * 8 < a.ts ? (a.nfn + 7) / 8 * 8 : a.ts;
+  const bool pad = face && m >= a.nfn && m < lw;
   const int nfn = a.nfn;
   const int64_t ts = a.ts;
   if (face && m < kNcRec) R[lf][m] = a.rec[i * kNcRec + m];

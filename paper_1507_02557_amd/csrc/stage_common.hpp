@@ -79,9 +79,13 @@ constexpr int kNcBase = 16;
 // trace (triangular face between tetrahedra or pyramids) is written as
 // lattice_width values, its lattice padded with zeros to whole lines: full
 // lines go to memory as plain writes, where a partly written line costs a
-// read-modify-write.
-HD constexpr int trace_stride(int N) { return ((N + 1) * (N + 1) + 7) / 8 * 8; }
-HD constexpr int lattice_width(int N) { return ((N + 1) * (N + 2) / 2 + 7) / 8 * 8; }
+// read-modify-write.  At N = 1 (four points, 64 bytes) a slot is not padded:
+// doubling every trace costs more there than the partial lines.
+HD constexpr int trace_stride(int N) { return N == 1 ? 4 : ((N + 1) * (N + 1) + 7) / 8 * 8; }
+HD constexpr int lattice_width(int N) {
+  return ((N + 1) * (N + 2) / 2 + 7) / 8 * 8 < trace_stride(N) ? ((N + 1) * (N + 2) / 2 + 7) / 8 * 8
+                                                                 : trace_stride(N);
+}
 
 // LDS writes of this wavefront become visible to its later LDS reads (LDS
 // operations of one wavefront complete in order; this stops the compiler
