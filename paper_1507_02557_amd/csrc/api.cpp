@@ -2008,6 +2008,7 @@ int hdg_energy(hdg_ctx* c, double* E) {
     a.Mhat = d.Mhat;
     a.partial = c->partial;
     const int nb = launch_energy(a, c->stream);
+    if (nb < 0) return fail(c, HDG_EINVAL, "internal: no energy kernel for this order");
     HIPCHK(c, hipGetLastError());
     part.resize(nb);
     HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));

@@ -174,46 +174,58 @@ __global__ void copy_samples_kernel(int64_t n, int64_t fs, const double* f0, con
   U[3 * fs + it] = (float)f3[it];
 }
 
-// Energy 1/2 sum (p^T M p / kappa + rho u^T M u), one thread per element,
-// FP64 accumulation, one partial sum per block.
-__global__ void energy_kernel(EnergyArgs a) {
-  __shared__ double red[256];
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Energy 1/2 sum (p^T M p / kappa + rho u^T M u) in FP64: one wavefront per
+// element (lanes over the element's nodes, so the loads of a field are
+// contiguous), four wavefronts per block striding over the elements, one
+// partial sum per block.  Tetrahedra: the element's values go to the LDS and
+// lane i forms (M p)_i with the reference mass (symmetric, read by column so
+// that consecutive lanes read consecutive entries); other types have a
+// diagonal mass.
+constexpr int kEnergyWaves = 4, kEnergyNpMax = 216, kTetNpMax = 56;
+__global__ __launch_bounds__(64 * kEnergyWaves) void energy_kernel(EnergyArgs a) {
+  __shared__ double red[kEnergyWaves];
+  __shared__ float uv[kEnergyWaves][4][kTetNpMax];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int Np = a.Np;
+  const int64_t n = a.Ks * Np;
   double acc = 0.0;
-  if (e < a.K) {
-    const int Np = a.Np;
+  for (int64_t e = (int64_t)blockIdx.x * kEnergyWaves + w; e < a.K; e += (int64_t)gridDim.x * kEnergyWaves) {
     const double kap = a.mat[e].x, rho = 1.0 / a.mat[e].y;
-    const int64_t n = a.Ks * Np;
-    const float* U = a.U;
+    const float* U = a.U + e * Np;
     if (a.type == 3) {
+      for (int i = lane; i < Np; i += 64)
+        for (int c = 0; c < 4; ++c) uv[w][c][i] = U[c * n + i];
+      wave_sync();
       const double J = 1.0 / a.geo[e * 12 + 9];
-      for (int i = 0; i < Np; ++i)
+      for (int i = lane; i < Np; i += 64) {
+        double mu[4] = {0.0, 0.0, 0.0, 0.0};
         for (int j = 0; j < Np; ++j) {
-          const double m = a.Mhat[i * Np + j] * J;
-          const int64_t ii = e * Np + i, jj = e * Np + j;
-          acc += m * ((double)U[ii] * U[jj] / kap +
-                      rho * ((double)U[n + ii] * U[n + jj] + (double)U[2 * n + ii] * U[2 * n + jj] +
-                             (double)U[3 * n + ii] * U[3 * n + jj]));
+          const double m = a.Mhat[j * Np + i];
+          for (int c = 0; c < 4; ++c) mu[c] += m * uv[w][c][j];
         }
+        acc += J * (uv[w][0][i] * mu[0] / kap + rho * (uv[w][1][i] * mu[1] + uv[w][2][i] * mu[2] +
+                                                      uv[w][3][i] * mu[3]));
+      }
+      // the next element's values overwrite these only after every lane has read them
+      wave_sync();
     } else {
-      for (int i = 0; i < Np; ++i) {
+      for (int i = lane; i < Np; i += 64) {
         double m = 1.0;
         if (a.type == 0) m = 1.0 / a.geo[(e * 10 + 9) * Np + i];
         else if (a.type == 2) m = a.geo[(e * 10 + 9) * Np + i];
-        const int64_t ii = e * Np + i;
-        acc += m * ((double)U[ii] * U[ii] / kap +
-                    rho * ((double)U[n + ii] * U[n + ii] + (double)U[2 * n + ii] * U[2 * n + ii] +
-                           (double)U[3 * n + ii] * U[3 * n + ii]));
+        const double p = U[i], u1 = U[n + i], u2 = U[2 * n + i], u3 = U[3 * n + i];
+        acc += m * (p * p / kap + rho * (u1 * u1 + u2 * u2 + u3 * u3));
       }
     }
   }
-  red[threadIdx.x] = 0.5 * acc;
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if (lane == 0) red[w] = 0.5 * acc;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < kEnergyWaves; ++k) t += red[k];
+    a.partial[blockIdx.x] = t;
   }
-  if (threadIdx.x == 0) a.partial[blockIdx.x] = red[0];
 }
 
 __global__ void fill_int_kernel(int* p, int n, int v) {
@@ -292,8 +304,11 @@ void launch_fill_int(int* p, int n, int v, hipStream_t s) {
 
 int launch_energy(const EnergyArgs& a, hipStream_t s) {
   if (a.K == 0) return 0;
-  const unsigned nb = nblk(a.K, 256);
-  hipLaunchKernelGGL(energy_kernel, dim3(nb), dim3(256), 0, s, a);
+  if (a.Np > kEnergyNpMax || (a.type == 3 && a.Np > kTetNpMax)) return -1;
+  // at most K / 256 + 8 partial sums (the size of the caller's buffer)
+  const int64_t want = (a.K + kEnergyWaves - 1) / kEnergyWaves, cap = a.K / 256 + 8;
+  const unsigned nb = (unsigned)(want < cap ? want : cap);
+  hipLaunchKernelGGL(energy_kernel, dim3(nb), dim3(64 * kEnergyWaves), 0, s, a);
   return (int)nb;
 }
 

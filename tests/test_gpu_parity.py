@@ -60,13 +60,16 @@ def test_rhs_matches_oracle(slab4_mesh, N, path):
 
 
 @pytest.mark.parametrize("path", PATHS)
-def test_rhs_free_surface_and_materials(path):
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
+def test_rhs_free_surface_and_materials(N, path):
+    """Free-surface mirror states and random materials, at every order the
+    matrix-core pyramid kernel serves (N = 3..5) and one it does not."""
     m = four_slab_mesh(4, seed=5, jitter=0.1)
     rng = np.random.default_rng(9)
     m.kappa = rng.uniform(0.5, 2.0, m.n_elem)
     m.rho = rng.uniform(0.5, 2.0, m.n_elem)
-    d = Disc(m, 2, bc=BC_FREE_SURFACE)
-    s = hdg.Solver(m, 2, bc=hdg.BC_FREE_SURFACE, path=path)
+    d = Disc(m, N, bc=BC_FREE_SURFACE)
+    s = hdg.Solver(m, N, bc=hdg.BC_FREE_SURFACE, path=path)
     U = random_state(d, seed=3)
     set_lib_state(s, U)
     Rl = {t: v.double().cpu().numpy() for t, v in s.rhs().items()}
