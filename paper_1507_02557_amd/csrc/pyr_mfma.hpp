@@ -375,7 +375,7 @@ struct PyrMfma {
 
   template <int C>
   __device__ __forceinline__ static void emit(Wave& W, const StageArgs& a, int64_t e0, int lane, bool contig, const float4 (&rv)[JQ],
-                              const f32x4 (&rhs)[Mt]) {
+                              const f32x4 (&rhs)[Mt], float* hist) {
     const int64_t K = a.K;
     const int n = lane & 15, g = lane >> 4;
     const bool stage = a.mode == kModeStage;
@@ -407,7 +407,9 @@ struct PyrMfma {
         }
       }
     wave_sync();
-    if (a.mode == kModeRhsHist) {
+    if (a.mode == kModeRhsHist && hist) {
+      store_tile(hist + (int64_t)C * K * Np, RB, a, e0, lane, true);
+    } else if (a.mode == kModeRhsHist) {
       for (int it = lane; it < 16 * Np; it += 64) {
         const int nn = it / Np, k = it - nn * Np;
         const int64_t ee = item(a, e0 + nn);
@@ -762,10 +764,18 @@ struct PyrMfma {
         for (int d = 0; d < 3; ++d) accS[1 + d][t][i] *= su;
         __builtin_amdgcn_sched_barrier(0);
       }
-    emit<0>(W, a, e0, lane, contig, rv0, accS[0]);
-    emit<1>(W, a, e0, lane, contig, rv1, accS[1]);
-    emit<2>(W, a, e0, lane, contig, rv2, accS[2]);
-    emit<3>(W, a, e0, lane, contig, rv3, accS[3]);
+    // a multi-rate launch without an item list has its elements stored finest
+    // level first, so equal levels at both ends of a contiguous tile mean one
+    // level: its history slot takes the tile as float4 vectors
+    float* hist = nullptr;
+    if (a.mode == kModeRhsHist && contig) {
+      const int lv = a.elevel[e0];
+      if (a.elevel[e0 + 15] == lv) hist = a.H + (int64_t)a.mr.hs[lv][0] * 4 * K * Np;
+    }
+    emit<0>(W, a, e0, lane, contig, rv0, accS[0], hist);
+    emit<1>(W, a, e0, lane, contig, rv1, accS[1], hist);
+    emit<2>(W, a, e0, lane, contig, rv2, accS[2], hist);
+    emit<3>(W, a, e0, lane, contig, rv3, accS[3], hist);
   }
 
   template <bool MR>
