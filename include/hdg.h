@@ -369,8 +369,8 @@ int hdg_profile_read(hdg_ctx* ctx, double* ms_out, int64_t* count_out);
  * tetrahedron or pyramid, faces between tetrahedra and pyramids exchange
  * face-lattice traces (the traces there are degree-N polynomials, so the
  * lattice values determine them and the flux on a planar face), and
- * tetrahedra (and, for single-rate stepping at N = 3 and 4, pyramids) run
- * on the matrix cores.  Otherwise, or with HDG_PATH_GENERIC,
+ * tetrahedra (and, at N = 3..5, pyramids) run on the matrix cores, in
+ * single-rate and multi-rate stepping.  Otherwise, or with HDG_PATH_GENERIC,
  * every face exchanges traces at the canonical cubature points.
  * hdg_set_path: path is HDG_PATH_AUTO or HDG_PATH_GENERIC (else
  * HDG_EINVAL); HDG_ESTATE after hdg_mrab_setup; HDG_EINVAL for

@@ -59,7 +59,8 @@ __global__ __launch_bounds__(S::NT) void mrab_update_kernel(StageArgs a) {
   }
 }
 
-// Wavefront-batched form (vector pyramids at N <= 4): the block holds the
+// Wavefront-batched form (vector pyramids at N <= 4, the wedges' multi-rate
+// update at N = 4): the block holds the
 // operator tables once; each of its W wavefronts runs the same phases on a
 // batch of its own (one element), separated by wavefront syncs instead of
 // block barriers, so the wavefronts of a compute unit proceed independently
