@@ -227,6 +227,22 @@ int hdg_rhs(hdg_ctx* ctx);
  * type and stage.  Asynchronous on the context's stream. */
 int hdg_step(hdg_ctx* ctx, double dt, int64_t n_steps);
 
+/* Launch-shape autotuner (Section 4.3.2: the number of elements a work-group
+ * processes is tuned per element type and order).  For the hexahedron and
+ * wedge block kernels, times `reps` right-hand-side launches (after one
+ * untimed launch) of every batch size the kernel is built with, on the
+ * context's mesh and state, with HIP events on the context's stream, and keeps
+ * the fastest for all later launches of the context (the wedge multi-rate
+ * update at N = 4 stays wavefront-batched).  Results agree with untuned
+ * launches to FP32 rounding (a batch size can change the order of a
+ * kernel's sums).  Overwrites the right-hand-side buffer
+ * (hdg_get_field(1)); the state is only read.  epb_out (host, may be NULL):
+ * int32[4], the chosen elements per block per type, 0 where the type is
+ * absent or its kernel has no batch size to tune.  Synchronises the stream.
+ * Errors: HDG_EINVAL (reps outside [1, 1000]), HDG_ESTATE (profiling on),
+ * HDG_EHIP. */
+int hdg_autotune(hdg_ctx* ctx, int reps, int32_t* epb_out);
+
 /* hdg_step through a HIP graph: two steps (ten stage launches per element
  * type, with the interface kernel) are captured once on the context's stream
  * and the graph is replayed n_steps / 2 times; an odd last step runs as

@@ -94,6 +94,7 @@ struct hdg_ctx {
   int path = HDG_PATH_AUTO;
   int prec = HDG_PREC_FP32;    // operand precision of the matrix-core products
   int max_blocks = 256;        // cap of persistent matrix-core grids (one block per compute unit)
+  int epb[4] = {0, 0, 0, 0};   // elements per block of the block kernels (0: default; hdg_autotune)
   GeoTables* gtab = nullptr;
   double* partial = nullptr;
   int* flag = nullptr;
@@ -485,7 +486,7 @@ int launch_type(hdg_ctx* c, int t, StageArgs a, bool mrab) {
     if (launch_tet_mfma(c->N, c->prec, a, c->stream, c->max_blocks)) return fail(c, HDG_EINVAL, "no kernel for this order");
     return HDG_OK;
   }
-  const int r = mrab ? launch_mrab_update(t, c->N, a, c->stream) : launch_stage(t, c->N, a, c->stream);
+  const int r = mrab ? launch_mrab_update(t, c->N, a, c->stream, c->epb[t]) : launch_stage(t, c->N, a, c->stream, c->epb[t]);
   if (r) return fail(c, HDG_EINVAL, "no stage kernel for this order");
   return HDG_OK;
 }
@@ -579,33 +580,39 @@ int run_mortar(hdg_ctx* c, float4* tr, float4* tr_half, int ksub, int dense) {
   return HDG_OK;
 }
 
+// Arguments of one type's stage kernel (mode, LSERK4 coefficients, step).
+StageArgs stage_args(hdg_ctx* c, const TypeData& d, int mode, float ra, float rb, float dt) {
+  StageArgs a{};
+  a.K = d.Ks;
+  a.n_items = d.K;
+  a.U = d.U;
+  a.R = d.R;
+  a.geo = d.geo;
+  a.mat = d.mat;
+  a.nbr = c->nbr;
+  a.ori = c->ori;
+  a.tau = c->tau;
+  a.fgeo = d.fgeo;
+  a.isqJ = d.isqJ;
+  a.tr_in = c->trace[c->cur];
+  a.tr_out = c->trace[1 - c->cur];
+  a.slot0 = d.slot0;
+  a.ops = d.ops;
+  a.iops = d.iops;
+  a.a = ra;
+  a.b = rb;
+  a.dt = dt;
+  a.mode = mode;
+  return a;
+}
+
 int run_stage(hdg_ctx* c, int mode, float ra, float rb, float dt) {
   int rc0 = run_mortar(c, c->trace[c->cur], nullptr, 0, 0);
   if (rc0) return rc0;
   for (int t = 0; t < 4; ++t) {
     TypeData& d = c->td[t];
     if (!d.present) continue;
-    StageArgs a{};
-    a.K = d.Ks;
-    a.n_items = d.K;
-    a.U = d.U;
-    a.R = d.R;
-    a.geo = d.geo;
-    a.mat = d.mat;
-    a.nbr = c->nbr;
-    a.ori = c->ori;
-    a.tau = c->tau;
-    a.fgeo = d.fgeo;
-    a.isqJ = d.isqJ;
-    a.tr_in = c->trace[c->cur];
-    a.tr_out = c->trace[1 - c->cur];
-    a.slot0 = d.slot0;
-    a.ops = d.ops;
-    a.iops = d.iops;
-    a.a = ra;
-    a.b = rb;
-    a.dt = dt;
-    a.mode = mode;
+    const StageArgs a = stage_args(c, d, mode, ra, rb, dt);
     hipEvent_t stop;
     int rc = prof_begin(c, t, &stop);
     if (rc) return rc;
@@ -1444,6 +1451,57 @@ int hdg_rhs(hdg_ctx* c) {
   int rc = ensure_traces(c);
   if (rc) return rc;
   return run_stage(c, kModeRhs, 0.f, 0.f, 1.f);
+}
+
+int hdg_autotune(hdg_ctx* c, int reps, int32_t* epb_out) {
+  if (!c) return HDG_EINVAL;
+  if (reps < 1 || reps > 1000) return fail(c, HDG_EINVAL, "reps must be in [1, 1000]");
+  if (c->prof) return fail(c, HDG_ESTATE, "profiling is on: turn it off first");
+  int rc = ensure_traces(c);
+  if (rc) return rc;
+  struct Events {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  HIPCHK(c, hipEventCreate(&ev.e[0]));
+  HIPCHK(c, hipEventCreate(&ev.e[1]));
+  for (int t = 0; t < 4; ++t) {
+    if (epb_out) epb_out[t] = 0;
+    const TypeData& d = c->td[t];
+    int opts[4];
+    // (hexahedra and wedges; the other types' kernels keep their shapes)
+    const int n = d.present ? stage_epb_options(t, c->N, opts) : 0;
+    if (n == 0) continue;
+    const StageArgs a = stage_args(c, d, kModeRhs, 0.f, 0.f, 1.f);
+    int best = 0;
+    float best_ms = 0.f;
+    for (int i = 0; i < n; ++i) {
+      c->epb[t] = opts[i];
+      if ((rc = launch_type(c, t, a, false))) return rc;  // first launch untimed
+      HIPCHK(c, hipEventRecord(ev.e[0], c->stream));
+      for (int r = 0; r < reps; ++r)
+        if ((rc = launch_type(c, t, a, false))) return rc;
+      HIPCHK(c, hipEventRecord(ev.e[1], c->stream));
+      HIPCHK(c, hipEventSynchronize(ev.e[1]));
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+      if (best == 0 || ms < best_ms) {
+        best = opts[i];
+        best_ms = ms;
+      }
+    }
+    c->epb[t] = best;
+    if (epb_out) epb_out[t] = best;
+  }
+  // a captured graph holds the previous launch shapes
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  return HDG_OK;
 }
 
 int hdg_step(hdg_ctx* c, double dt, int64_t n_steps) {

@@ -97,10 +97,14 @@ int launch_energy(const EnergyArgs& a, hipStream_t s);
 void launch_finite(int64_t n, const float* x, int* flag, hipStream_t s);
 
 // Fused stage kernel for one element type; returns 0 or -1 if (type, N) has
-// no instantiation.
-int launch_stage(int type, int N, const StageArgs& a, hipStream_t s);
+// no instantiation.  eb: elements per block of the hexahedron or wedge block
+// kernel, one of stage_epb_options (0: the default of stage_config.hpp).
+int launch_stage(int type, int N, const StageArgs& a, hipStream_t s, int eb = 0);
 // Multi-rate AB3 update of the items of a (state, traces, mid-step traces).
-int launch_mrab_update(int type, int N, const StageArgs& a, hipStream_t s);
+int launch_mrab_update(int type, int N, const StageArgs& a, hipStream_t s, int eb = 0);
+// Batch sizes the block kernel of (type, N) is instantiated with (hexahedra,
+// wedges; 0 for other types); out holds at least 4.
+int stage_epb_options(int type, int N, int* out);
 // Packed operator table sizes of the stage kernel for (type, N).
 void stage_table_sizes(int type, int N, int* n_floats, int* n_ints);
 int stage_batch(int type, int N);

@@ -138,14 +138,10 @@ HD inline void load_residual(const StageArgs& a, int64_t base, int Np, float (&r
 // node in the block's state arrays, fields fstride apart).
 HD inline void node_update(const StageArgs& a, int64_t e, int Np, int64_t base, const float (&rhs)[4],
                            const float (&r)[4], const float* u, float* un, int fstride) {
-  // the destination once per node: the element's level byte, read after a
-  // float store, would otherwise be read again before every store
-  const bool out_rhs = a.mode == kModeRhs || a.mode == kModeRhsHist;
-  float* dst = out_rhs ? rhs_dst(a, e, Np) : nullptr;
   for (int c = 0; c < 4; ++c) {
     const int64_t gi = (int64_t)c * a.K * Np + base;
-    if (out_rhs) {
-      dst[gi] = rhs[c];
+    if (a.mode == kModeRhs || a.mode == kModeRhsHist) {
+      rhs_dst(a, e, Np)[gi] = rhs[c];
     } else {
       const float res = a.a * r[c] + a.dt * rhs[c];
       const float v = u[c * fstride] + a.b * res;

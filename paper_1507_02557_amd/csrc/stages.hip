@@ -162,16 +162,76 @@ static void sizes(int* nf, int* ni) {
   *ni = S::kOpsInts;
 }
 
+// Elements per block the autotuner may choose for the hexahedron and wedge
+// block kernels: the batch sizes whose LDS fits a compute unit and, for
+// hexahedra, whose per-thread arrays fit the registers (at most 1000 nodes a
+// batch: larger ones spill).
+constexpr int kHexEpb[] = {2, 4, 8, 16}, kWedgeEpb[] = {1, 2, 4, 8};
+template <class S>
+constexpr bool fits() {
+  return sizeof(typename S::Smem) <= 160 * 1024;
+}
+template <int N, int E>
+constexpr bool hex_fits() {
+  return fits<HexStage<N, E>>() && E * HexStage<N, E>::Np <= 1000;
+}
+template <class S>
+static int go_fit(const StageArgs& a, hipStream_t s, bool mrab) {
+  if constexpr (fits<S>()) return go<S>(a, s, mrab);
+  else return -1;
+}
+template <int N, int I>
+static int hex_epb(const StageArgs& a, hipStream_t s, bool mrab, int eb) {
+  if constexpr (I < 4) {
+    if constexpr (hex_fits<N, kHexEpb[I]>()) {
+      if (eb == kHexEpb[I]) return go<HexStage<N, kHexEpb[I]>>(a, s, mrab);
+    }
+    return hex_epb<N, I + 1>(a, s, mrab, eb);
+  } else {
+    return -1;
+  }
+}
+template <int N, int I>
+static int wedge_epb(const StageArgs& a, hipStream_t s, bool mrab, int eb) {
+  if constexpr (I < 4) {
+    if (eb == kWedgeEpb[I]) return go_fit<WedgeStage<N, kWedgeEpb[I]>>(a, s, mrab);
+    return wedge_epb<N, I + 1>(a, s, mrab, eb);
+  } else {
+    return -1;
+  }
+}
 template <int N>
-static int launch_n(int type, const StageArgs& a, hipStream_t s, bool mrab) {
+static int epb_options_n(int type, int* out) {
+  int n = 0;
+  if (type == 0) {
+    if (hex_fits<N, 2>()) out[n++] = 2;
+    if (hex_fits<N, 4>()) out[n++] = 4;
+    if (hex_fits<N, 8>()) out[n++] = 8;
+    if (hex_fits<N, 16>()) out[n++] = 16;
+  } else if (type == 1) {
+    if (fits<WedgeStage<N, 1>>()) out[n++] = 1;
+    if (fits<WedgeStage<N, 2>>()) out[n++] = 2;
+    if (fits<WedgeStage<N, 4>>()) out[n++] = 4;
+    if (fits<WedgeStage<N, 8>>()) out[n++] = 8;
+  }
+  return n;
+}
+
+// eb: elements per block of the hexahedron or wedge block kernel (0: the
+// default of stage_config.hpp).
+template <int N>
+static int launch_n(int type, const StageArgs& a, hipStream_t s, bool mrab, int eb) {
   switch (type) {
-    case 0: return go<HexStage<N, epb(0, N)>>(a, s, mrab);
+    case 0:
+      if (eb > 0) return hex_epb<N, 0>(a, s, mrab, eb);
+      return go<HexStage<N, epb(0, N)>>(a, s, mrab);
     case 1:
       // the multi-rate update runs faster wavefront-batched, the stage and
       // right-hand side in blocks of EPB elements (measured at N = 4)
       if constexpr (N == 4) {
         if (mrab) return go_wave<WedgeStage<N, 1, 64>, wedge_waves(N)>(a, s, mrab);
       }
+      if (eb > 0) return wedge_epb<N, 0>(a, s, mrab, eb);
       return go<WedgeStage<N, epb(1, N)>>(a, s, mrab);
     case 2:
       if constexpr (N <= 4) return go_wave<PyrStage<N, 1, 64>, pyr_waves(N)>(a, s, mrab);
@@ -191,20 +251,35 @@ static void sizes_n(int type, int* nf, int* ni) {
   }
 }
 
-static int launch_any(int type, int N, const StageArgs& a, hipStream_t s, bool mrab) {
+static int launch_any(int type, int N, const StageArgs& a, hipStream_t s, bool mrab, int eb) {
   switch (N) {
-    case 1: return launch_n<1>(type, a, s, mrab);
-    case 2: return launch_n<2>(type, a, s, mrab);
-    case 3: return launch_n<3>(type, a, s, mrab);
-    case 4: return launch_n<4>(type, a, s, mrab);
-    case 5: return launch_n<5>(type, a, s, mrab);
+    case 1: return launch_n<1>(type, a, s, mrab, eb);
+    case 2: return launch_n<2>(type, a, s, mrab, eb);
+    case 3: return launch_n<3>(type, a, s, mrab, eb);
+    case 4: return launch_n<4>(type, a, s, mrab, eb);
+    case 5: return launch_n<5>(type, a, s, mrab, eb);
   }
   return -1;
 }
 
-int launch_stage(int type, int N, const StageArgs& a, hipStream_t s) { return launch_any(type, N, a, s, false); }
+int launch_stage(int type, int N, const StageArgs& a, hipStream_t s, int eb) {
+  return launch_any(type, N, a, s, false, eb);
+}
 
-int launch_mrab_update(int type, int N, const StageArgs& a, hipStream_t s) { return launch_any(type, N, a, s, true); }
+int launch_mrab_update(int type, int N, const StageArgs& a, hipStream_t s, int eb) {
+  return launch_any(type, N, a, s, true, eb);
+}
+
+int stage_epb_options(int type, int N, int* out) {
+  switch (N) {
+    case 1: return epb_options_n<1>(type, out);
+    case 2: return epb_options_n<2>(type, out);
+    case 3: return epb_options_n<3>(type, out);
+    case 4: return epb_options_n<4>(type, out);
+    case 5: return epb_options_n<5>(type, out);
+  }
+  return 0;
+}
 
 void stage_table_sizes(int type, int N, int* nf, int* ni) {
   switch (N) {

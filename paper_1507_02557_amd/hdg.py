@@ -55,6 +55,7 @@ _SIGS = [
     ("hdg_mrab_level_info", ctypes.c_int, [_P, _P]),
     ("hdg_trace_constants", ctypes.c_int, [_P, _P]),
     ("hdg_step_graph", ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int64]),
+    ("hdg_autotune", ctypes.c_int, [_P, ctypes.c_int, _P]),
     ("hdg_set_dt_mode", ctypes.c_int, [_P, ctypes.c_int]),
     ("hdg_profile", ctypes.c_int, [_P, ctypes.c_int]),
     ("hdg_profile_read", ctypes.c_int, [_P, _P, _P]),
@@ -211,6 +212,14 @@ class Solver:
     def step_graph(self, dt: float, n_steps: int):
         """n_steps LSERK4 steps replayed from a captured HIP graph (bitwise those of step)."""
         self._check(self._lib.hdg_step_graph(self._h, float(dt), int(n_steps)))
+
+    def autotune(self, reps: int = 5):
+        """Time every batch size of the hexahedron and wedge block kernels on this
+        mesh and keep the fastest; returns the chosen elements per block per type
+        (0: not tuned).  Overwrites the right-hand-side buffer."""
+        out = (ctypes.c_int32 * 4)()
+        self._check(self._lib.hdg_autotune(self._h, int(reps), ctypes.cast(out, ctypes.c_void_p)))
+        return [int(v) for v in out]
 
     def energy(self) -> float:
         E = ctypes.c_double()

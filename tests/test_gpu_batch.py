@@ -76,3 +76,36 @@ def test_batched_problems_reproduce_their_standalone_runs(prec):
             assert torch.equal(got[o:o + ref.shape[0]], ref), t
             o += ref.shape[0]
         assert o == got.shape[0]
+
+
+def _close(a, b, tol=1e-6):
+    for t in a:
+        scale = float(a[t].abs().max())
+        if float((a[t] - b[t]).abs().max()) > tol * max(scale, 1e-30):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_autotune_keeps_results(N):
+    """The launch-shape autotuner picks a batch size for the hexahedron and
+    wedge block kernels; single-rate and multi-rate steps after tuning agree
+    with untuned ones to FP32 rounding (a batch size can change the order of
+    a kernel's sums)."""
+    m = four_slab_mesh(6, seed=2, jitter=0.1)
+    base, tuned = hdg.Solver(m, N), hdg.Solver(m, N)
+    for s in (base, tuned):
+        s.project_function(standing_mode_rigid)
+    choice = tuned.autotune(3)
+    print("elements per block chosen", choice)
+    assert choice[0] in (2, 4, 8, 16) and choice[1] in (1, 2, 4, 8)
+    assert choice[2] == 0 and choice[3] == 0
+    tuned.project_function(standing_mode_rigid)  # (the tuner overwrote the rhs buffer only)
+    _, dt = base.dt(0.5)
+    base.step(dt, 3)
+    tuned.step(dt, 3)
+    assert _close(_fields(base), _fields(tuned))
+    for s in (base, tuned):
+        s.mrab_setup(2)
+        s.mrab_advance(2)
+    assert _close(_fields(base), _fields(tuned))

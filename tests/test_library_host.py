@@ -126,6 +126,7 @@ def test_calls_on_a_null_context_are_rejected():
     assert lib.hdg_mrab_level_info(None, buf) == hdg.EINVAL
     assert lib.hdg_trace_constants(None, buf) == hdg.EINVAL
     assert lib.hdg_set_dt_mode(None, hdg.DT_ELEMENT) == hdg.EINVAL
+    assert lib.hdg_autotune(None, 5, None) == hdg.EINVAL
 
 
 def test_header_scratch_size_matches_binding():
